@@ -1,0 +1,158 @@
+/*
+ * dts.h -- C ABI of libdts, the gfx950 (MI355X) hot path of the Domain Transform Solver.
+ *
+ * Method: A. Bapat and J.-M. Frahm, "The Domain Transform Solver", ECCV 2018
+ * (arXiv:1805.04590).  Equation numbers count the paper's displayed equations in order:
+ * Eq. (2) objective without the application term, Eq. (3) its gradient (the descent
+ * direction), Eq. (8)-(9) the domain transform, Eq. (10) the edge-aware mean.
+ *
+ * Conventions shared by every entry point
+ *   - Every array pointer is a DEVICE pointer (memory of the current HIP device), fp32,
+ *     planar row-major: guide [batch][Cg][H][W]; target, output and gradients
+ *     [batch][Ct][H][W]; confidence [batch][Cc][H][W] with Cc = 1 (shared by all target
+ *     channels) or Cc = Ct.
+ *   - The caller owns every buffer, including the workspace, whose size it obtains from
+ *     the matching *_workspace_bytes call.  The library allocates nothing and keeps no
+ *     state between calls; a workspace must not be used by two calls that may run at the
+ *     same time.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Every call only enqueues
+ *     work on it and returns without synchronising, so calls may be captured into a HIP
+ *     graph.  Inputs are never written; outputs must not alias inputs.
+ *   - Return value: DTS_OK (0) or a negative error code; nothing is enqueued when an
+ *     argument check fails.  Values are not range-checked: NaN and Inf propagate.
+ *   - Device-side failures (a bounded wait inside a kernel that timed out) set a flag in
+ *     the workspace; dts_workspace_status() reads it back.
+ */
+#ifndef DTS_H
+#define DTS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DTS_OK 0
+#define DTS_EINVAL (-1)     /* null pointer, bad size, channel count, sigma, N or T      */
+#define DTS_EWORKSPACE (-2) /* workspace null or smaller than *_workspace_bytes          */
+#define DTS_EHIP (-3)       /* a HIP runtime call or kernel launch failed                */
+#define DTS_ENOTSUP (-4)    /* shape beyond the supported limits (see DTS_MAX_*)         */
+#define DTS_EDEVICE (-5)    /* a kernel reported a device-side failure (status call)     */
+
+#define DTS_MAX_CHANNELS 16 /* Cg, Ct <= 16: the paper motivates 16-band imagery (Sec. 1) */
+#define DTS_MAX_WIDTH 16384  /* row pass: at most 16 waves x 4 tiles of 256 pixels */
+#define DTS_MAX_HEIGHT 32768
+
+/* Solver parameters (Sec. 3.1 and Sec. 4).  sigma_s is the spatial standard deviation
+ * in pixels (sigma_x = sigma_y), sigma_r the range standard deviation in guide units;
+ * filter_iters N >= 1 domain-transform iterations per edge-aware mean (each a row pass
+ * then a column pass); solver_iters T >= 0 gradient-descent iterations; lambda weighs the
+ * edge-aware regulariser and step scales the Eq. (3) direction (both 0.99 in the paper). */
+typedef struct dts_params {
+    float sigma_s;
+    float sigma_r;
+    int filter_iters;
+    int solver_iters;
+    float lambda;
+    float step;
+} dts_params;
+
+/* Workspace sizes in bytes (always a multiple of 256). */
+size_t dts_filter_workspace_bytes(int batch, int H, int W, int Cs);
+size_t dts_solve_workspace_bytes(int batch, int H, int W, int Ct, const dts_params* p);
+size_t dts_solve_backward_workspace_bytes(int batch, int H, int W, int Cg, int Ct,
+                                          const dts_params* p);
+
+/* dts_filter -- the 2-D domain-transform edge-aware filter DT(src) (Sec. 3.2, Eq. (8)-(10)
+ * in its recursive-filter form).  Distances from the guide's channel differences
+ *   dx = sqrt(1 + (sigma_s/sigma_r)^2 sum_k (I_k[y][x] - I_k[y][x-1])^2)   (dy likewise),
+ * weights w = a_i^d with a_i = exp(-sqrt(2)/sigma_Hi), sigma_Hi = sigma_s sqrt(3)
+ * 2^(N-i) / sqrt(4^N - 1); then for i = 1..N a causal+anticausal recursive pass along
+ * every row, then along every column.  All Cs channels of src use the same weights.
+ * guide [batch][Cg][H][W], src/dst [batch][Cs][H][W]; dst may equal src (in place). */
+int dts_filter(const float* guide, int Cg, const float* src, float* dst, int Cs, int batch,
+               int H, int W, float sigma_s, float sigma_r, int filter_iters, void* workspace,
+               size_t workspace_bytes, void* stream);
+
+/* dts_solve -- gradient descent along Eq. (3) on the objective of Eq. (2):
+ *   z^0 = target,  z^{k+1} = z^k - step (lambda (z^k - DT(z^k)) + c (z^k - target)),
+ * k = 0..T-1, writing z^T to `out` [batch][Ct][H][W].  `checkpoints` is NULL or an array
+ * of T slots [T][batch][Ct][H][W]; slot k receives z^k (slot 0 a copy of the target),
+ * which is what dts_solve_backward reads.  T = 0 copies the target to `out`. */
+int dts_solve(const float* guide, int Cg, const float* target, const float* conf, int Cc,
+              int Ct, int batch, int H, int W, const dts_params* p, float* out,
+              float* checkpoints, void* workspace, size_t workspace_bytes, void* stream);
+
+/* dts_solve_backward -- reverse-mode gradient of a scalar loss through dts_solve (not in
+ * the paper; derived from Eq. (3) and the filter by the chain rule).  Given
+ * grad_out = dL/dz^T and the T checkpoints written by dts_solve with the same inputs, it
+ * writes dL/dtarget [batch][Ct][H][W], dL/dconf [batch][Cc][H][W] (summed over the target
+ * channels when Cc = 1) and dL/dguide [batch][Cg][H][W].  Each gradient pointer may be
+ * NULL to skip it (the guide gradient costs one extra accumulation per filter pass).
+ * Per iteration the filter's pass inputs are recomputed from the checkpoint. */
+int dts_solve_backward(const float* guide, int Cg, const float* target, const float* conf,
+                       int Cc, int Ct, int batch, int H, int W, const dts_params* p,
+                       const float* checkpoints, const float* grad_out, float* grad_target,
+                       float* grad_conf, float* grad_guide, void* workspace,
+                       size_t workspace_bytes, void* stream);
+
+/* ---- The individual steps of the filter (each also runs inside the calls above) ---- */
+
+/* dts_distances -- transformed distances of the domain transform (Sec. 3.2, Eq. (8)-(9)):
+ *   dx[b][y][x] = sqrt(1 + (sigma_s/sigma_r)^2 sum_k (I_k[y][x] - I_k[y][x-1])^2), x >= 1,
+ *   dy[b][y][x] = sqrt(1 + (sigma_s/sigma_r)^2 sum_k (I_k[y][x] - I_k[y-1][x])^2), y >= 1,
+ * and 1 at x = 0 (dx) and y = 0 (dy).  guide [batch][Cg][H][W]; dx, dy [batch][H][W]. */
+int dts_distances(const float* guide, int Cg, int batch, int H, int W, float sigma_s,
+                  float sigma_r, float* dx, float* dy, void* stream);
+
+/* Workspace of one dts_col_pass call. */
+size_t dts_pass_workspace_bytes(int batch, int H, int W, int C);
+
+/* dts_row_pass / dts_col_pass -- one causal+anticausal recursive pass of filter iteration
+ * `iter` (1..N) along every row (weights a_iter^dx) or every column (a_iter^dy):
+ *   J[0] = f[0], J[n] = (1 - w[n]) f[n] + w[n] J[n-1];
+ *   K[L-1] = J[L-1], K[n] = (1 - w[n+1]) J[n] + w[n+1] K[n+1];  dst = K.
+ * src/dst [batch][C][H][W] (dst may equal src); dx or dy [batch][H][W] from dts_distances. */
+int dts_row_pass(const float* src, float* dst, const float* dx, int C, int batch, int H, int W,
+                 float sigma_s, int iter, int filter_iters, void* stream);
+int dts_col_pass(const float* src, float* dst, const float* dy, int C, int batch, int H, int W,
+                 float sigma_s, int iter, int filter_iters, void* workspace,
+                 size_t workspace_bytes, void* stream);
+
+/* ---- Kernel timing (HIP events around each launch, on the launch's own stream) ---- */
+
+/* One row of the timing table: a kernel variant, how many launches were recorded, their
+ * summed duration and the algorithmic bytes those launches must move (inputs read once,
+ * outputs written once, fp32). */
+typedef struct dts_kernel_stat {
+    char name[48];
+    int launches;
+    double total_ms;
+    double bytes;
+} dts_kernel_stat;
+
+/* on != 0 clears the table and starts recording every launch of this process; on == 0
+ * stops.  Not for use while a stream is being captured into a graph. */
+int dts_profile_enable(int on);
+
+/* Waits for the recorded launches, fills up to `max_rows` rows and returns the number of
+ * kernel variants recorded (or a negative error code). */
+int dts_profile_read(dts_kernel_stat* rows, int max_rows);
+
+/* Reads back (synchronously, on `stream`) the device-side status flag of a workspace,
+ * which every call clears when it starts: DTS_OK, or DTS_EDEVICE if a kernel of the most
+ * recent call on this workspace reported a failure (a bounded wait that timed out, a work
+ * ticket out of range).  The flag is cleared after it is read. */
+int dts_workspace_status(void* workspace, void* stream);
+
+/* Human-readable text of an error code (static storage). */
+const char* dts_strerror(int code);
+
+/* Text of the last HIP error seen by this thread (static thread-local storage). */
+const char* dts_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DTS_H */

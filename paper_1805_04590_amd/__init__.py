@@ -1,0 +1,384 @@
+"""MI355X (gfx950) hot path of the Domain Transform Solver (Bapat & Frahm, ECCV 2018).
+
+Thin ctypes binding over ``libdts.so`` (C ABI declared in ``include/dts.h``).  This module
+only marshals arguments: it checks dtypes, devices, shapes and contiguity, sizes and
+allocates workspaces with PyTorch (device memory is PyTorch's, the stream is PyTorch's
+current stream) and forwards raw device pointers.  Every step of the method runs in the
+library's HIP kernels; there is no fallback path, and calls fail loudly when the library
+is missing or a tensor is not on the GPU.
+
+Entry points (same names as the C ABI):
+  filter(guide, src, sigma_s, sigma_r, filter_iters=3)           edge-aware mean DT(src)
+  solve(guide, target, conf, sigma_s, sigma_r, ...)               Eq. (3) gradient descent
+  solve_backward(guide, target, conf, checkpoints, grad_out, ...) adjoint of solve
+  DTSFunction.apply(guide, target, conf, params)                  autograd wrapper
+Tensors are float32, contiguous, shaped [B][C][H][W] (or [C][H][W] for B = 1).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+__all__ = [
+    "DTSError",
+    "Params",
+    "library",
+    "library_path",
+    "filter",
+    "solve",
+    "solve_backward",
+    "DTSFunction",
+    "workspace_status",
+    "distances",
+    "row_pass",
+    "col_pass",
+    "profile_enable",
+    "profile_read",
+    "EXPORTED_SYMBOLS",
+]
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_PKG, "libdts.so")
+
+DTS_OK = 0
+DTS_EINVAL = -1
+DTS_EWORKSPACE = -2
+DTS_EHIP = -3
+DTS_ENOTSUP = -4
+DTS_EDEVICE = -5
+
+EXPORTED_SYMBOLS = (
+    "dts_filter_workspace_bytes",
+    "dts_solve_workspace_bytes",
+    "dts_solve_backward_workspace_bytes",
+    "dts_filter",
+    "dts_solve",
+    "dts_solve_backward",
+    "dts_workspace_status",
+    "dts_strerror",
+    "dts_last_hip_error",
+    "dts_distances",
+    "dts_pass_workspace_bytes",
+    "dts_row_pass",
+    "dts_col_pass",
+    "dts_profile_enable",
+    "dts_profile_read",
+)
+
+
+class DTSError(RuntimeError):
+    def __init__(self, code, what):
+        self.code = code
+        super().__init__(f"{what}: {_strerror(code)} ({code})")
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("sigma_s", ctypes.c_float),
+        ("sigma_r", ctypes.c_float),
+        ("filter_iters", ctypes.c_int),
+        ("solver_iters", ctypes.c_int),
+        ("lam", ctypes.c_float),
+        ("step", ctypes.c_float),
+    ]
+
+
+class _KernelStat(ctypes.Structure):
+    _fields_ = [
+        ("name", ctypes.c_char * 48),
+        ("launches", ctypes.c_int),
+        ("total_ms", ctypes.c_double),
+        ("bytes", ctypes.c_double),
+    ]
+
+
+@dataclass(frozen=True)
+class Params:
+    """Solver parameters; defaults are the paper's lambda = step = 0.99 (Sec. 4) and three
+    filter iterations per edge-aware mean."""
+    sigma_s: float
+    sigma_r: float
+    filter_iters: int = 3
+    solver_iters: int = 10
+    lam: float = 0.99
+    step: float = 0.99
+
+    def c(self):
+        return _Params(float(self.sigma_s), float(self.sigma_r), int(self.filter_iters),
+                       int(self.solver_iters), float(self.lam), float(self.step))
+
+
+_lib = None
+
+
+def library_path():
+    return _LIB_PATH
+
+
+def library():
+    """Load libdts.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"libdts.so not built at {_LIB_PATH}; run "
+                           "`python -m paper_1805_04590_amd.build`")
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.POINTER(_Params)
+    vp, fp, i, sz, f = ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.c_float
+    lib.dts_filter_workspace_bytes.argtypes = [i, i, i, i]
+    lib.dts_filter_workspace_bytes.restype = sz
+    lib.dts_solve_workspace_bytes.argtypes = [i, i, i, i, P]
+    lib.dts_solve_workspace_bytes.restype = sz
+    lib.dts_solve_backward_workspace_bytes.argtypes = [i, i, i, i, i, P]
+    lib.dts_solve_backward_workspace_bytes.restype = sz
+    lib.dts_filter.argtypes = [fp, i, fp, fp, i, i, i, i, f, f, i, vp, sz, vp]
+    lib.dts_filter.restype = i
+    lib.dts_solve.argtypes = [fp, i, fp, fp, i, i, i, i, i, P, fp, fp, vp, sz, vp]
+    lib.dts_solve.restype = i
+    lib.dts_solve_backward.argtypes = [fp, i, fp, fp, i, i, i, i, i, P, fp, fp, fp, fp, fp,
+                                       vp, sz, vp]
+    lib.dts_solve_backward.restype = i
+    lib.dts_distances.argtypes = [fp, i, i, i, i, f, f, fp, fp, vp]
+    lib.dts_distances.restype = i
+    lib.dts_pass_workspace_bytes.argtypes = [i, i, i, i]
+    lib.dts_pass_workspace_bytes.restype = sz
+    lib.dts_row_pass.argtypes = [fp, fp, fp, i, i, i, i, f, i, i, vp]
+    lib.dts_row_pass.restype = i
+    lib.dts_col_pass.argtypes = [fp, fp, fp, i, i, i, i, f, i, i, vp, sz, vp]
+    lib.dts_col_pass.restype = i
+    lib.dts_profile_enable.argtypes = [i]
+    lib.dts_profile_enable.restype = i
+    lib.dts_profile_read.argtypes = [ctypes.POINTER(_KernelStat), i]
+    lib.dts_profile_read.restype = i
+    lib.dts_workspace_status.argtypes = [vp, vp]
+    lib.dts_workspace_status.restype = i
+    lib.dts_strerror.argtypes = [i]
+    lib.dts_strerror.restype = ctypes.c_char_p
+    lib.dts_last_hip_error.argtypes = []
+    lib.dts_last_hip_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _strerror(code):
+    try:
+        s = library().dts_strerror(int(code)).decode()
+        if code == DTS_EHIP:
+            s += " [" + library().dts_last_hip_error().decode() + "]"
+        return s
+    except Exception:  # pragma: no cover - only when the library cannot load at all
+        return "error"
+
+
+def _check(rc, what):
+    if rc != DTS_OK:
+        raise DTSError(rc, what)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _as4d(t, name):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a GPU tensor (got {t.device}); libdts runs on gfx950 only")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32 (got {t.dtype})")
+    if t.dim() == 3:
+        t = t.unsqueeze(0)
+    if t.dim() != 4:
+        raise ValueError(f"{name} must be [B][C][H][W] or [C][H][W]")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _check_plane(t, name, shape, device):
+    if (not isinstance(t, torch.Tensor) or tuple(t.shape) != tuple(shape) or t.device != device
+            or t.dtype != torch.float32 or not t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float32 {list(shape)} tensor on {device}")
+
+
+def _workspace(nbytes, device):
+    if nbytes == 0:
+        raise DTSError(DTS_EINVAL, "workspace size query")
+    return torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+
+
+def distances(guide, sigma_s, sigma_r):
+    """(dx, dy), each [B][H][W]: the transformed distances of Eq. (8)-(9)."""
+    g = _as4d(guide, "guide")
+    B, Cg, H, W = g.shape
+    dx = torch.empty((B, H, W), dtype=torch.float32, device=g.device)
+    dy = torch.empty_like(dx)
+    _check(library().dts_distances(_ptr(g), Cg, B, H, W, float(sigma_s), float(sigma_r), _ptr(dx),
+                                   _ptr(dy), _stream()), "dts_distances")
+    return dx, dy
+
+
+def row_pass(src, dx, sigma_s, iter, filter_iters=3, out=None):
+    """One causal+anticausal recursive pass along rows for filter iteration ``iter``."""
+    x = _as4d(src, "src")
+    B, C, H, W = x.shape
+    _check_plane(dx, "dx", (B, H, W), x.device)
+    out = torch.empty_like(x) if out is None else _as4d(out, "out")
+    _check(library().dts_row_pass(_ptr(x), _ptr(out), _ptr(dx), C, B, H, W, float(sigma_s),
+                                  int(iter), int(filter_iters), _stream()), "dts_row_pass")
+    return out
+
+
+def col_pass(src, dy, sigma_s, iter, filter_iters=3, out=None, workspace=None):
+    """One causal+anticausal recursive pass along columns for filter iteration ``iter``."""
+    x = _as4d(src, "src")
+    B, C, H, W = x.shape
+    _check_plane(dy, "dy", (B, H, W), x.device)
+    out = torch.empty_like(x) if out is None else _as4d(out, "out")
+    lib = library()
+    if workspace is None:
+        workspace = _workspace(lib.dts_pass_workspace_bytes(B, H, W, C), x.device)
+    _check(lib.dts_col_pass(_ptr(x), _ptr(out), _ptr(dy), C, B, H, W, float(sigma_s), int(iter),
+                            int(filter_iters), _ptr(workspace), workspace.numel(), _stream()),
+           "dts_col_pass")
+    return out
+
+
+def profile_enable(on=True):
+    """Start (clearing earlier records) or stop timing every libdts kernel launch."""
+    _check(library().dts_profile_enable(1 if on else 0), "dts_profile_enable")
+
+
+def profile_read():
+    """{kernel: {"launches", "total_ms", "avg_ms", "bytes_per_launch"}} of recorded launches."""
+    rows = (_KernelStat * 64)()
+    n = library().dts_profile_read(rows, 64)
+    if n < 0:
+        raise DTSError(n, "dts_profile_read")
+    out = {}
+    for r in rows[:min(n, 64)]:
+        out[r.name.decode()] = dict(launches=r.launches, total_ms=r.total_ms,
+                                    avg_ms=r.total_ms / max(r.launches, 1),
+                                    bytes_per_launch=r.bytes / max(r.launches, 1))
+    return out
+
+
+def workspace_status(ws):
+    """DTS_OK, or raise DTSError(DTS_EDEVICE) if a kernel's bounded wait timed out."""
+    _check(library().dts_workspace_status(_ptr(ws), _stream()), "device status")
+    return DTS_OK
+
+
+def filter(guide, src, sigma_s, sigma_r, filter_iters=3, out=None, workspace=None):
+    """DT(src): the edge-aware domain-transform filter guided by ``guide`` (Sec. 3.2)."""
+    g = _as4d(guide, "guide")
+    x = _as4d(src, "src")
+    B, Cs, H, W = x.shape
+    if g.shape[0] != B or g.shape[2:] != x.shape[2:]:
+        raise ValueError("guide and src disagree in batch or image size")
+    lib = library()
+    if out is None:
+        out = torch.empty_like(x)
+    else:
+        out = _as4d(out, "out")
+    if workspace is None:
+        workspace = _workspace(lib.dts_filter_workspace_bytes(B, H, W, Cs), x.device)
+    rc = lib.dts_filter(_ptr(g), g.shape[1], _ptr(x), _ptr(out), Cs, B, H, W, float(sigma_s),
+                        float(sigma_r), int(filter_iters), _ptr(workspace), workspace.numel(),
+                        _stream())
+    _check(rc, "dts_filter")
+    return out if src.dim() == 4 else out[0]
+
+
+def solve(guide, target, conf, sigma_s, sigma_r, filter_iters=3, solver_iters=10, lam=0.99,
+          step=0.99, checkpoints=False, out=None, workspace=None):
+    """z^T of the Eq. (3) gradient descent started at z^0 = target.
+
+    With ``checkpoints=True`` also returns the [T][B][Ct][H][W] tensor of iterates
+    z^0..z^{T-1} that ``solve_backward`` consumes."""
+    g = _as4d(guide, "guide")
+    t = _as4d(target, "target")
+    c = _as4d(conf, "conf")
+    B, Ct, H, W = t.shape
+    if g.shape[0] != B or g.shape[2:] != t.shape[2:] or c.shape[0] != B or c.shape[2:] != t.shape[2:]:
+        raise ValueError("guide/target/conf disagree in batch or image size")
+    p = Params(sigma_s, sigma_r, filter_iters, solver_iters, lam, step).c()
+    lib = library()
+    if out is None:
+        out = torch.empty_like(t)
+    ck = None
+    if checkpoints:
+        ck = torch.empty((max(int(solver_iters), 0),) + tuple(t.shape), dtype=torch.float32,
+                         device=t.device)
+    if workspace is None:
+        workspace = _workspace(lib.dts_solve_workspace_bytes(B, H, W, Ct, ctypes.byref(p)), t.device)
+    rc = lib.dts_solve(_ptr(g), g.shape[1], _ptr(t), _ptr(c), c.shape[1], Ct, B, H, W,
+                       ctypes.byref(p), _ptr(out), _ptr(ck) if ck is not None and ck.numel() else None,
+                       _ptr(workspace), workspace.numel(), _stream())
+    _check(rc, "dts_solve")
+    res = out if target.dim() == 4 else out[0]
+    if checkpoints:
+        return res, ck
+    return res
+
+
+def solve_backward(guide, target, conf, checkpoints, grad_out, sigma_s, sigma_r, filter_iters=3,
+                   solver_iters=10, lam=0.99, step=0.99, need=(True, True, True),
+                   workspace=None):
+    """(dL/dtarget, dL/dconf, dL/dguide) given dL/dz^T and the checkpoints of ``solve``."""
+    g = _as4d(guide, "guide")
+    t = _as4d(target, "target")
+    c = _as4d(conf, "conf")
+    go = _as4d(grad_out, "grad_out")
+    B, Ct, H, W = t.shape
+    T = int(solver_iters)
+    if checkpoints.shape != (T,) + tuple(t.shape) or checkpoints.dtype != torch.float32 \
+            or not checkpoints.is_contiguous() or checkpoints.device != t.device:
+        raise ValueError("checkpoints must be the [T][B][Ct][H][W] float32 tensor from solve()")
+    p = Params(sigma_s, sigma_r, filter_iters, solver_iters, lam, step).c()
+    lib = library()
+    gt = torch.empty_like(t) if need[0] else None
+    gc = torch.empty_like(c) if need[1] else None
+    gg = torch.empty_like(g) if need[2] else None
+    if workspace is None:
+        workspace = _workspace(lib.dts_solve_backward_workspace_bytes(
+            B, H, W, g.shape[1], Ct, ctypes.byref(p)), t.device)
+    rc = lib.dts_solve_backward(_ptr(g), g.shape[1], _ptr(t), _ptr(c), c.shape[1], Ct, B, H, W,
+                                ctypes.byref(p), _ptr(checkpoints) if T else None, _ptr(go),
+                                _ptr(gt), _ptr(gc), _ptr(gg), _ptr(workspace), workspace.numel(),
+                                _stream())
+    _check(rc, "dts_solve_backward")
+    squeeze = target.dim() == 3
+    fix = (lambda x: x[0] if (x is not None and squeeze) else x)
+    return fix(gt), fix(gc), fix(gg)
+
+
+class DTSFunction(torch.autograd.Function):
+    """z^T = solve(guide, target, conf) with gradients for all three inputs through the
+    hand-written adjoint (per-iteration checkpoints, recomputed filter passes)."""
+
+    @staticmethod
+    def forward(ctx, guide, target, conf, params: Params):
+        z, ck = solve(guide, target, conf, params.sigma_s, params.sigma_r, params.filter_iters,
+                      params.solver_iters, params.lam, params.step, checkpoints=True)
+        ctx.save_for_backward(guide, target, conf, ck)
+        ctx.params = params
+        return z
+
+    @staticmethod
+    def backward(ctx, grad_z):
+        guide, target, conf, ck = ctx.saved_tensors
+        p = ctx.params
+        need = ctx.needs_input_grad[:3]
+        gt, gc, gg = solve_backward(guide, target, conf, ck, grad_z.contiguous(), p.sigma_s,
+                                    p.sigma_r, p.filter_iters, p.solver_iters, p.lam, p.step,
+                                    need=(need[1], need[2], need[0]))
+        return gg, gt, gc, None

@@ -1,0 +1,378 @@
+// libdts C ABI: argument checks, workspace layout and pass orchestration.
+//
+// Method: Bapat & Frahm, "The Domain Transform Solver", ECCV 2018.  dts_filter is the
+// edge-aware mean of Sec. 3.2 (the recursive domain-transform filter: distances of
+// Eq. (8)-(9), weights a^d, rows then columns per iteration); dts_solve is gradient
+// descent along the Eq. (3) direction on the objective of Eq. (2), starting from the
+// target (Sec. 3.1), with the hyper-parameters of Sec. 4 as defaults on the Python side.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+
+#include "../../include/dts.h"
+#include "dts_device.hpp"
+#include "dts_internal.hpp"
+
+namespace dts {
+
+static thread_local char g_last_hip[256] = "no HIP error";
+
+int hip_fail(hipError_t e) {
+    if (e == hipSuccess) return DTS_OK;
+    snprintf(g_last_hip, sizeof(g_last_hip), "%s: %s", hipGetErrorName(e), hipGetErrorString(e));
+    return DTS_EHIP;
+}
+
+constexpr size_t kAlign = 256;
+constexpr size_t kHeaderBytes = 256;
+constexpr size_t kTicketOffset = 64;
+constexpr int kMaxFilterIters = 64;
+constexpr long long kMaxSolverIters = 1 << 20;
+
+static size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Workspace: [header | dx | dy | tmp (solve only) | carry words]
+struct Layout {
+    size_t dx = 0, dy = 0, tmp = 0, carry = 0, carry_bytes = 0, total = 0;
+};
+
+static Layout make_layout(int batch, int H, int W, int C, bool with_tmp) {
+    Layout L;
+    const size_t plane = static_cast<size_t>(batch) * H * W * sizeof(float);
+    size_t off = kHeaderBytes;
+    L.dx = off;
+    off = align_up(off + plane);
+    L.dy = off;
+    off = align_up(off + plane);
+    if (with_tmp) {
+        L.tmp = off;
+        off = align_up(off + plane * C);
+    }
+    L.carry = off;
+    L.carry_bytes = align_up(col_carry_words(batch, H, W, C) * sizeof(unsigned long long));
+    off += L.carry_bytes;
+    L.total = off;
+    return L;
+}
+
+static bool finite_pos(float v) { return isfinite(v) && v > 0.f; }
+
+static int check_shape(int batch, int H, int W) {
+    if (batch < 1 || H < 1 || W < 1) return DTS_EINVAL;
+    if (H > DTS_MAX_HEIGHT || W > DTS_MAX_WIDTH) return DTS_ENOTSUP;
+    // column passes address a plane through one buffer resource with 32-bit offsets and
+    // mask lanes by pushing their offset past 2^31: keep every plane offset below 2^31
+    if ((static_cast<size_t>(H) + 64) * static_cast<size_t>(W) * 4 >= (static_cast<size_t>(1) << 31))
+        return DTS_ENOTSUP;
+    // every column pass launch takes one ticket per chunk: keep the counter in 32 bits
+    const double elems = static_cast<double>(batch) * H * W;
+    if (elems * DTS_MAX_CHANNELS > 9.0e15) return DTS_ENOTSUP;
+    return DTS_OK;
+}
+
+static int check_channels(int C) { return (C >= 1 && C <= DTS_MAX_CHANNELS) ? DTS_OK : DTS_EINVAL; }
+
+// log2 of the feedback coefficient of filter iteration i (1-based) of N:
+// a_i = exp(-sqrt(2)/sigma_Hi), sigma_Hi = sigma_s sqrt(3) 2^(N-i) / sqrt(4^N - 1).
+static float log2_feedback(double sigma_s, int i, int N) {
+    const double sigma_h = sigma_s * sqrt(3.0) * ldexp(1.0, N - i) / sqrt(ldexp(1.0, 2 * N) - 1.0);
+    return static_cast<float>(-sqrt(2.0) / sigma_h / log(2.0));
+}
+
+struct Setup {
+    Ctx ctx;
+    Layout L;
+    float* dx;
+    float* dy;
+    float* tmp;
+};
+
+static int begin_call(Setup& S, void* ws, size_t ws_bytes, int batch, int H, int W, int C,
+                      bool with_tmp, void* stream) {
+    S.L = make_layout(batch, H, W, C, with_tmp);
+    if (ws == nullptr || ws_bytes < S.L.total) return DTS_EWORKSPACE;
+    if ((reinterpret_cast<uintptr_t>(ws) & 15u) != 0) return DTS_EWORKSPACE;
+    char* base = static_cast<char*>(ws);
+    S.ctx.stream = static_cast<hipStream_t>(stream);
+    S.ctx.status = reinterpret_cast<int*>(base);
+    S.ctx.ticket = reinterpret_cast<unsigned*>(base + kTicketOffset);
+    S.ctx.carry = reinterpret_cast<unsigned long long*>(base + S.L.carry);
+    S.ctx.carry_words = S.L.carry_bytes / sizeof(unsigned long long);
+    S.dx = reinterpret_cast<float*>(base + S.L.dx);
+    S.dy = reinterpret_cast<float*>(base + S.L.dy);
+    S.tmp = with_tmp ? reinterpret_cast<float*>(base + S.L.tmp) : nullptr;
+    // status word, ticket counter and carry words start from zero on every call, so the
+    // status read back afterwards describes the most recent call on this workspace
+    int rc = launch_zero(base, kHeaderBytes, S.ctx.stream);
+    if (rc) return rc;
+    return launch_zero(base + S.L.carry, S.L.carry_bytes, S.ctx.stream);
+}
+
+}  // namespace dts
+
+using namespace dts;
+
+extern "C" {
+
+size_t dts_filter_workspace_bytes(int batch, int H, int W, int Cs) {
+    if (check_shape(batch, H, W) || check_channels(Cs)) return 0;
+    return make_layout(batch, H, W, Cs, false).total;
+}
+
+size_t dts_solve_workspace_bytes(int batch, int H, int W, int Ct, const dts_params* p) {
+    (void)p;
+    if (check_shape(batch, H, W) || check_channels(Ct)) return 0;
+    return make_layout(batch, H, W, Ct, true).total;
+}
+
+size_t dts_solve_backward_workspace_bytes(int batch, int H, int W, int Cg, int Ct,
+                                          const dts_params* p) {
+    (void)batch;
+    (void)H;
+    (void)W;
+    (void)Cg;
+    (void)Ct;
+    (void)p;
+    return 0;
+}
+
+int dts_filter(const float* guide, int Cg, const float* src, float* dst, int Cs, int batch, int H,
+               int W, float sigma_s, float sigma_r, int filter_iters, void* workspace,
+               size_t workspace_bytes, void* stream) {
+    if (!guide || !src || !dst) return DTS_EINVAL;
+    int rc = check_shape(batch, H, W);
+    if (rc) return rc;
+    if (check_channels(Cg) || check_channels(Cs)) return DTS_EINVAL;
+    if (!finite_pos(sigma_s) || !finite_pos(sigma_r)) return DTS_EINVAL;
+    if (filter_iters < 1 || filter_iters > kMaxFilterIters) return DTS_EINVAL;
+    Setup S;
+    rc = begin_call(S, workspace, workspace_bytes, batch, H, W, Cs, false, stream);
+    if (rc) return rc;
+    const float s2 = static_cast<float>((static_cast<double>(sigma_s) / sigma_r) *
+                                        (static_cast<double>(sigma_s) / sigma_r));
+    for (int i = 1; i <= filter_iters; ++i) {
+        const float l2a = log2_feedback(sigma_s, i, filter_iters);
+        RowPass rp{};
+        rp.src = (i == 1) ? src : dst;
+        rp.dst = dst;
+        rp.d = S.dx;
+        rp.guide = (i == 1) ? guide : nullptr;
+        rp.dx_out = S.dx;
+        rp.dy_out = S.dy;
+        rp.Cg = Cg;
+        rp.s2 = s2;
+        rp.C = Cs;
+        rp.H = H;
+        rp.W = W;
+        rp.batch = batch;
+        rp.log2a = l2a;
+        if ((rc = launch_row_pass(rp, S.ctx))) return rc;
+        ColPass cp{};
+        cp.src = dst;
+        cp.dst = dst;
+        cp.d = S.dy;
+        cp.C = Cs;
+        cp.H = H;
+        cp.W = W;
+        cp.batch = batch;
+        cp.log2a = l2a;
+        cp.epilogue = false;
+        if ((rc = launch_col_pass(cp, S.ctx))) return rc;
+    }
+    return DTS_OK;
+}
+
+int dts_solve(const float* guide, int Cg, const float* target, const float* conf, int Cc, int Ct,
+              int batch, int H, int W, const dts_params* p, float* out, float* checkpoints,
+              void* workspace, size_t workspace_bytes, void* stream) {
+    if (!guide || !target || !conf || !out || !p) return DTS_EINVAL;
+    int rc = check_shape(batch, H, W);
+    if (rc) return rc;
+    if (check_channels(Cg) || check_channels(Ct)) return DTS_EINVAL;
+    if (Cc != 1 && Cc != Ct) return DTS_EINVAL;
+    if (!finite_pos(p->sigma_s) || !finite_pos(p->sigma_r)) return DTS_EINVAL;
+    if (p->filter_iters < 1 || p->filter_iters > kMaxFilterIters) return DTS_EINVAL;
+    if (p->solver_iters < 0 || p->solver_iters > kMaxSolverIters) return DTS_EINVAL;
+    if (!isfinite(p->lambda) || !isfinite(p->step)) return DTS_EINVAL;
+    const int T = p->solver_iters, N = p->filter_iters;
+    Setup S;
+    rc = begin_call(S, workspace, workspace_bytes, batch, H, W, Ct, true, stream);
+    if (rc) return rc;
+    const size_t sig = static_cast<size_t>(batch) * Ct * H * W;
+    if (T == 0) return launch_copy(out, target, sig, S.ctx.stream);
+    if (checkpoints && (rc = launch_copy(checkpoints, target, sig, S.ctx.stream))) return rc;
+    const float s2 = static_cast<float>((static_cast<double>(p->sigma_s) / p->sigma_r) *
+                                        (static_cast<double>(p->sigma_s) / p->sigma_r));
+    for (int k = 0; k < T; ++k) {
+        const float* zk = (k == 0) ? target : (checkpoints ? checkpoints + k * sig : out);
+        float* znext = (k == T - 1) ? out : (checkpoints ? checkpoints + (k + 1) * sig : out);
+        for (int i = 1; i <= N; ++i) {
+            const float l2a = log2_feedback(p->sigma_s, i, N);
+            RowPass rp{};
+            rp.src = (i == 1) ? zk : S.tmp;
+            rp.dst = S.tmp;
+            rp.d = S.dx;
+            rp.guide = (k == 0 && i == 1) ? guide : nullptr;
+            rp.dx_out = S.dx;
+            rp.dy_out = S.dy;
+            rp.Cg = Cg;
+            rp.s2 = s2;
+            rp.C = Ct;
+            rp.H = H;
+            rp.W = W;
+            rp.batch = batch;
+            rp.log2a = l2a;
+            if ((rc = launch_row_pass(rp, S.ctx))) return rc;
+            ColPass cp{};
+            cp.src = S.tmp;
+            cp.dst = (i == N) ? znext : S.tmp;
+            cp.d = S.dy;
+            cp.C = Ct;
+            cp.H = H;
+            cp.W = W;
+            cp.batch = batch;
+            cp.log2a = l2a;
+            cp.epilogue = (i == N);
+            cp.zk = zk;
+            cp.tgt = target;
+            cp.conf = conf;
+            cp.Cc = Cc;
+            cp.dst2 = nullptr;
+            cp.lambda = p->lambda;
+            cp.step = p->step;
+            if ((rc = launch_col_pass(cp, S.ctx))) return rc;
+        }
+    }
+    return DTS_OK;
+}
+
+int dts_solve_backward(const float* guide, int Cg, const float* target, const float* conf, int Cc,
+                       int Ct, int batch, int H, int W, const dts_params* p,
+                       const float* checkpoints, const float* grad_out, float* grad_target,
+                       float* grad_conf, float* grad_guide, void* workspace,
+                       size_t workspace_bytes, void* stream) {
+    (void)guide; (void)Cg; (void)target; (void)conf; (void)Cc; (void)Ct; (void)batch; (void)H;
+    (void)W; (void)p; (void)checkpoints; (void)grad_out; (void)grad_target; (void)grad_conf;
+    (void)grad_guide; (void)workspace; (void)workspace_bytes; (void)stream;
+    return DTS_ENOTSUP;
+}
+
+int dts_distances(const float* guide, int Cg, int batch, int H, int W, float sigma_s,
+                  float sigma_r, float* dx, float* dy, void* stream) {
+    if (!guide || !dx || !dy) return DTS_EINVAL;
+    int rc = check_shape(batch, H, W);
+    if (rc) return rc;
+    if (check_channels(Cg)) return DTS_EINVAL;
+    if (!finite_pos(sigma_s) || !finite_pos(sigma_r)) return DTS_EINVAL;
+    Ctx ctx;
+    ctx.stream = static_cast<hipStream_t>(stream);
+    RowPass rp{};
+    rp.guide = guide;
+    rp.dx_out = dx;
+    rp.dy_out = dy;
+    rp.Cg = Cg;
+    rp.s2 = static_cast<float>((static_cast<double>(sigma_s) / sigma_r) *
+                               (static_cast<double>(sigma_s) / sigma_r));
+    rp.C = 0;  // distances only: no signal channel is filtered
+    rp.H = H;
+    rp.W = W;
+    rp.batch = batch;
+    rp.log2a = 0.f;
+    return launch_row_pass(rp, ctx);
+}
+
+size_t dts_pass_workspace_bytes(int batch, int H, int W, int C) {
+    if (check_shape(batch, H, W) || check_channels(C)) return 0;
+    return kHeaderBytes + align_up(col_carry_words(batch, H, W, C) * sizeof(unsigned long long));
+}
+
+static int check_pass(const float* src, const float* dst, const float* d, int C, int batch, int H,
+                      int W, float sigma_s, int iter, int N) {
+    if (!src || !dst || !d) return DTS_EINVAL;
+    int rc = check_shape(batch, H, W);
+    if (rc) return rc;
+    if (check_channels(C)) return DTS_EINVAL;
+    if (!finite_pos(sigma_s)) return DTS_EINVAL;
+    if (N < 1 || N > kMaxFilterIters || iter < 1 || iter > N) return DTS_EINVAL;
+    return DTS_OK;
+}
+
+int dts_row_pass(const float* src, float* dst, const float* dx, int C, int batch, int H, int W,
+                 float sigma_s, int iter, int filter_iters, void* stream) {
+    int rc = check_pass(src, dst, dx, C, batch, H, W, sigma_s, iter, filter_iters);
+    if (rc) return rc;
+    Ctx ctx;
+    ctx.stream = static_cast<hipStream_t>(stream);
+    RowPass rp{};
+    rp.src = src;
+    rp.dst = dst;
+    rp.d = dx;
+    rp.C = C;
+    rp.H = H;
+    rp.W = W;
+    rp.batch = batch;
+    rp.log2a = log2_feedback(sigma_s, iter, filter_iters);
+    return launch_row_pass(rp, ctx);
+}
+
+int dts_col_pass(const float* src, float* dst, const float* dy, int C, int batch, int H, int W,
+                 float sigma_s, int iter, int filter_iters, void* workspace,
+                 size_t workspace_bytes, void* stream) {
+    int rc = check_pass(src, dst, dy, C, batch, H, W, sigma_s, iter, filter_iters);
+    if (rc) return rc;
+    const size_t need = dts_pass_workspace_bytes(batch, H, W, C);
+    if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 15u))
+        return DTS_EWORKSPACE;
+    char* base = static_cast<char*>(workspace);
+    Ctx ctx;
+    ctx.stream = static_cast<hipStream_t>(stream);
+    ctx.status = reinterpret_cast<int*>(base);
+    ctx.ticket = reinterpret_cast<unsigned*>(base + kTicketOffset);
+    ctx.carry = reinterpret_cast<unsigned long long*>(base + kHeaderBytes);
+    ctx.carry_words = (need - kHeaderBytes) / sizeof(unsigned long long);
+    if ((rc = launch_zero(base, need, ctx.stream))) return rc;
+    ColPass cp{};
+    cp.src = src;
+    cp.dst = dst;
+    cp.d = dy;
+    cp.C = C;
+    cp.H = H;
+    cp.W = W;
+    cp.batch = batch;
+    cp.log2a = log2_feedback(sigma_s, iter, filter_iters);
+    cp.epilogue = false;
+    return launch_col_pass(cp, ctx);
+}
+
+int dts_workspace_status(void* workspace, void* stream) {
+    if (!workspace) return DTS_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int status = 0;
+    int rc = hip_fail(hipMemcpyAsync(&status, workspace, sizeof(int), hipMemcpyDeviceToHost, s));
+    if (rc) return rc;
+    if ((rc = hip_fail(hipStreamSynchronize(s)))) return rc;
+    if (status != 0) {
+        if ((rc = launch_zero(workspace, 16, s))) return rc;
+        if ((rc = hip_fail(hipStreamSynchronize(s)))) return rc;
+        return DTS_EDEVICE;
+    }
+    return DTS_OK;
+}
+
+const char* dts_strerror(int code) {
+    switch (code) {
+        case DTS_OK: return "success";
+        case DTS_EINVAL: return "invalid argument";
+        case DTS_EWORKSPACE: return "workspace missing, misaligned or too small";
+        case DTS_EHIP: return "HIP runtime error (see dts_last_hip_error)";
+        case DTS_ENOTSUP: return "shape or option not supported";
+        case DTS_EDEVICE: return "device-side failure reported by a kernel";
+        default: return "unknown error";
+    }
+}
+
+const char* dts_last_hip_error(void) { return g_last_hip; }
+
+}  // extern "C"

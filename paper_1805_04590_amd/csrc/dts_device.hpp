@@ -1,0 +1,150 @@
+// Device helpers shared by the libdts kernels (gfx950, wave64).
+//
+// Every 1-D recursive pass of the domain-transform filter is a chain of affine maps
+//   causal      J[n] = w[n] J[n-1] + (1 - w[n]) f[n]
+//   anticausal  K[n] = w[n+1] K[n+1] + (1 - w[n+1]) J[n]
+// so a line is scanned by composing maps x -> a x + b:
+//   (a2, b2) o (a1, b1) = (a2 a1, a2 b1 + b2).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dts {
+
+constexpr int kWave = 64;
+
+// Bounded waits: a poll loop gives up after this many polls (each followed by a short
+// sleep), records a device-side failure and lets the wave finish, so no kernel can spin
+// forever even if a co-residency assumption were violated.
+constexpr int kSpinLimit = 1 << 21;
+
+// Status word layout in the workspace header.
+constexpr int kErrSpinTimeout = 1;
+constexpr int kErrBadTicket = 2;
+
+__device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// Weight w = a^d = 2^(d log2 a).
+__device__ __forceinline__ float weight(float d, float log2a) { return exp2_fast(d * log2a); }
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+// Inclusive scan of affine maps from lane 0 upwards: lane l ends with the composition of
+// the maps of lanes 0..l (lane l's map applied last).
+__device__ __forceinline__ void scan_maps_up(float& a, float& b, int lane) {
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const float pa = __shfl_up(a, d);
+        const float pb = __shfl_up(b, d);
+        if (lane >= d) {
+            b = fmaf(a, pb, b);
+            a = a * pa;
+        }
+    }
+}
+
+// Inclusive scan of affine maps from lane 63 downwards: lane l ends with the composition
+// of the maps of lanes 63..l (lane l's map applied last).
+__device__ __forceinline__ void scan_maps_down(float& a, float& b, int lane) {
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const float na = __shfl_down(a, d);
+        const float nb = __shfl_down(b, d);
+        if (lane + d < kWave) {
+            b = fmaf(a, nb, b);
+            a = a * na;
+        }
+    }
+}
+
+// Carry words: a float value tagged with the epoch of the launch that wrote it, stored
+// and loaded as one 64-bit device-scope atomic so a reader never sees a value without its
+// tag.  Words from older launches carry older epochs and read as "not yet written".
+__device__ __forceinline__ void publish(unsigned long long* p, unsigned epoch, float v) {
+    const unsigned long long word =
+        (static_cast<unsigned long long>(epoch) << 32) | __float_as_uint(v);
+    __hip_atomic_store(p, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ bool peek(const unsigned long long* p, unsigned epoch, float& v) {
+    const unsigned long long word = __hip_atomic_load(
+        const_cast<unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    v = __uint_as_float(static_cast<unsigned>(word));
+    return static_cast<unsigned>(word >> 32) == epoch;
+}
+
+__device__ __forceinline__ void flag_error(int* status, int code) {
+    __hip_atomic_fetch_or(status, code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Row loads of 4 consecutive elements starting at n0 (a multiple of 4); elements at or
+// beyond W read as `fill`.  `vec` is true when every row starts 16-byte aligned.
+__device__ __forceinline__ float4 load4(const float* row, int n0, int W, bool vec, float fill) {
+    if (vec && n0 + 3 < W) return *reinterpret_cast<const float4*>(row + n0);
+    float4 v;
+    v.x = (n0 + 0 < W) ? row[n0 + 0] : fill;
+    v.y = (n0 + 1 < W) ? row[n0 + 1] : fill;
+    v.z = (n0 + 2 < W) ? row[n0 + 2] : fill;
+    v.w = (n0 + 3 < W) ? row[n0 + 3] : fill;
+    return v;
+}
+
+__device__ __forceinline__ void store4(float* row, int n0, int W, bool vec, float4 v) {
+    if (vec && n0 + 3 < W) {
+        *reinterpret_cast<float4*>(row + n0) = v;
+        return;
+    }
+    if (n0 + 0 < W) row[n0 + 0] = v.x;
+    if (n0 + 1 < W) row[n0 + 1] = v.y;
+    if (n0 + 2 < W) row[n0 + 2] = v.z;
+    if (n0 + 3 < W) row[n0 + 3] = v.w;
+}
+
+// Raw buffer access.  A resource covers one plane; lanes whose voffset is kInvalidOffset
+// fall outside every plane (planes are < 2 GiB), so their loads return 0 and their stores
+// are dropped by the hardware range check.
+constexpr unsigned kInvalidOffset = 0x80000000u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, size_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0,
+                                             static_cast<int>(bytes), 0x00020000);
+}
+
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff,
+                                       float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 0);
+}
+
+// Scalar add the compiler cannot fold away, so a row offset advances as one running SGPR
+// instead of one precomputed SGPR per unrolled row.
+__device__ __forceinline__ unsigned opaque_add(unsigned x, unsigned y) {
+    unsigned r = x + y;
+    asm volatile("" : "+s"(r));
+    return r;
+}
+
+// Vector add the compiler cannot fold or common up: unrolled row loops advance one running
+// offset register instead of keeping one precomputed address register per row alive.
+__device__ __forceinline__ unsigned opaque_vadd(unsigned x, unsigned y) {
+    unsigned r = x + y;
+    asm volatile("" : "+v"(r));
+    return r;
+}
+
+// A float the compiler cannot see through: starting a product chain from it stops the
+// compiler from keeping every partial product of an identical earlier chain alive.
+__device__ __forceinline__ float opaque(float x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+__device__ __forceinline__ float get(const float4& v, int e) {
+    return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w;
+}
+
+}  // namespace dts

@@ -1,0 +1,78 @@
+// Internal (non-ABI) interface between the libdts entry points and its kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace dts {
+
+// Per-call launch context: the stream, the workspace header words used by the column
+// passes (device status flag, ticket counter) and the carry-word area.  The host counts
+// tickets and epochs so every column-pass launch of one call has a fresh epoch and a
+// disjoint ticket range.
+struct Ctx {
+    hipStream_t stream = nullptr;
+    int* status = nullptr;
+    unsigned* ticket = nullptr;
+    unsigned long long* carry = nullptr;
+    size_t carry_words = 0;
+    unsigned ticket_base = 0;
+    unsigned epoch = 0;
+};
+
+// One pass along rows (fused distance computation when `guide` is non-null).
+struct RowPass {
+    const float* src;
+    float* dst;
+    const float* d;   // dx [batch][H][W]; ignored when computing distances
+    const float* guide;
+    float* dx_out;
+    float* dy_out;
+    int Cg;
+    float s2;         // (sigma_s / sigma_r)^2
+    int C, H, W, batch;
+    float log2a;
+};
+
+// One pass along columns (optional update epilogue of the solver).
+struct ColPass {
+    const float* src;
+    float* dst;
+    const float* d;   // dy [batch][H][W]
+    int C, H, W, batch;
+    float log2a;
+    // epilogue: dst = z - step (lambda (z - K) + c (z - t)), also written to dst2 if set
+    bool epilogue;
+    const float* zk;
+    const float* tgt;
+    const float* conf;
+    int Cc;
+    float* dst2;
+    float lambda, step;
+};
+
+int launch_row_pass(const RowPass& p, Ctx& ctx);
+int launch_col_pass(const ColPass& p, Ctx& ctx);
+size_t col_carry_words(int batch, int H, int W, int C);
+int launch_zero(void* ptr, size_t bytes, hipStream_t s);
+int launch_copy(float* dst, const float* src, size_t n, hipStream_t s);
+
+// RAII launch timer: records a start event on construction and a stop event on
+// destruction (both on `s`) when timing is enabled; a no-op otherwise.
+class ProfScope {
+   public:
+    ProfScope(const char* name, double bytes, hipStream_t s);
+    ~ProfScope();
+    ProfScope(const ProfScope&) = delete;
+    ProfScope& operator=(const ProfScope&) = delete;
+
+   private:
+    hipStream_t stream_;
+    long index_ = -1;
+};
+
+// Error bookkeeping shared by the translation units.
+int hip_fail(hipError_t e);
+
+}  // namespace dts

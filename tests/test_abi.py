@@ -1,0 +1,113 @@
+"""Host-side checks of the C ABI: the library loads, exports what include/dts.h declares,
+and rejects bad arguments before touching the GPU (no kernel is launched here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1805_04590_amd as dts
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dts.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dts_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(dts.library_path()):
+        pytest.fail("libdts.so is not built (run python -m paper_1805_04590_amd.build)")
+    return dts.library()
+
+
+def test_library_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 9
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(dts.EXPORTED_SYMBOLS)
+
+
+def test_exported_symbols_are_in_dynamic_table():
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", dts.library_path()], capture_output=True,
+                         text=True).stdout
+    exported = set(re.findall(r"\bT (dts_\w+)", out))
+    assert set(declared_functions()) <= exported
+
+
+def test_strerror_covers_codes(lib):
+    for code in (0, -1, -2, -3, -4, -5):
+        assert lib.dts_strerror(code)
+    assert b"unknown" in lib.dts_strerror(-99)
+
+
+P = dts._Params
+
+
+def test_workspace_sizes(lib):
+    p = P(8.0, 0.2, 3, 10, 0.99, 0.99)
+    small = lib.dts_solve_workspace_bytes(1, 256, 256, 1, ctypes.byref(p))
+    big = lib.dts_solve_workspace_bytes(1, 1080, 1920, 1, ctypes.byref(p))
+    assert small > 0 and big > small and small % 256 == 0 and big % 256 == 0
+    # at least dx, dy and one temporary plane
+    assert big >= 3 * 1080 * 1920 * 4
+    assert lib.dts_filter_workspace_bytes(1, 256, 256, 1) < small
+    assert lib.dts_solve_workspace_bytes(0, 256, 256, 1, ctypes.byref(p)) == 0
+    assert lib.dts_solve_workspace_bytes(1, 256, 256, 17, ctypes.byref(p)) == 0
+    assert lib.dts_filter_workspace_bytes(1, 256, 256 * 1024, 1) == 0
+
+
+def _fake(n=1):
+    return ctypes.c_void_p(0x1000 * n)
+
+
+def test_filter_rejects_bad_arguments_without_launching(lib):
+    ws = ctypes.c_void_p(0)
+    f = lib.dts_filter
+    assert f(None, 3, _fake(), _fake(2), 1, 1, 8, 8, 8.0, 0.2, 3, ws, 0, None) == dts.DTS_EINVAL
+    assert f(_fake(), 0, _fake(), _fake(2), 1, 1, 8, 8, 8.0, 0.2, 3, ws, 0, None) == dts.DTS_EINVAL
+    assert f(_fake(), 17, _fake(), _fake(2), 1, 1, 8, 8, 8.0, 0.2, 3, ws, 0, None) == dts.DTS_EINVAL
+    assert f(_fake(), 3, _fake(), _fake(2), 1, 1, 0, 8, 8.0, 0.2, 3, ws, 0, None) == dts.DTS_EINVAL
+    assert f(_fake(), 3, _fake(), _fake(2), 1, 1, 8, 8, -1.0, 0.2, 3, ws, 0, None) == dts.DTS_EINVAL
+    assert f(_fake(), 3, _fake(), _fake(2), 1, 1, 8, 8, 8.0, 0.0, 3, ws, 0, None) == dts.DTS_EINVAL
+    assert f(_fake(), 3, _fake(), _fake(2), 1, 1, 8, 8, 8.0, float("nan"), 3, ws, 0, None) == dts.DTS_EINVAL
+    assert f(_fake(), 3, _fake(), _fake(2), 1, 1, 8, 8, 8.0, 0.2, 0, ws, 0, None) == dts.DTS_EINVAL
+    assert f(_fake(), 3, _fake(), _fake(2), 1, 1, 8, 40000, 8.0, 0.2, 3, ws, 0, None) == dts.DTS_ENOTSUP
+    # valid arguments but no / too small workspace
+    assert f(_fake(), 3, _fake(), _fake(2), 1, 1, 8, 8, 8.0, 0.2, 3, ws, 0, None) == dts.DTS_EWORKSPACE
+    assert f(_fake(), 3, _fake(), _fake(2), 1, 1, 8, 8, 8.0, 0.2, 3, _fake(3), 64, None) == dts.DTS_EWORKSPACE
+
+
+def test_solve_rejects_bad_arguments_without_launching(lib):
+    ws = ctypes.c_void_p(0)
+    s = lib.dts_solve
+    good = P(8.0, 0.2, 3, 10, 0.99, 0.99)
+
+    def call(p=good, Cc=1, Ct=1, conf=_fake(3), out=_fake(4), H=8, W=8):
+        return s(_fake(), 3, _fake(2), conf, Cc, Ct, 1, H, W, ctypes.byref(p), out, None, ws, 0, None)
+
+    assert call(conf=None) == dts.DTS_EINVAL
+    assert call(out=None) == dts.DTS_EINVAL
+    assert call(Cc=2, Ct=3) == dts.DTS_EINVAL
+    assert call(p=P(8.0, 0.2, 3, -1, 0.99, 0.99)) == dts.DTS_EINVAL
+    assert call(p=P(8.0, 0.2, 0, 1, 0.99, 0.99)) == dts.DTS_EINVAL
+    assert call(p=P(0.0, 0.2, 3, 1, 0.99, 0.99)) == dts.DTS_EINVAL
+    assert call(p=P(8.0, 0.2, 3, 1, float("inf"), 0.99)) == dts.DTS_EINVAL
+    assert call() == dts.DTS_EWORKSPACE
+    assert call(Cc=3, Ct=3) == dts.DTS_EWORKSPACE
+    assert s(_fake(), 3, _fake(2), _fake(3), 1, 1, 1, 8, 8, None, _fake(4), None, ws, 0, None) == dts.DTS_EINVAL
+
+
+def test_binding_refuses_cpu_tensors():
+    import torch
+    g = torch.zeros(3, 8, 8)
+    with pytest.raises(ValueError, match="GPU"):
+        dts.filter(g, g[:1], 8.0, 0.2)
+    with pytest.raises(ValueError, match="GPU"):
+        dts.solve(g, g[:1], g[:1], 8.0, 0.2)
