@@ -58,6 +58,69 @@ __device__ __forceinline__ void scan_maps_down(float& a, float& b, int lane) {
     }
 }
 
+// DPP move of a float within rows of 16 lanes; lanes whose source lane is outside their
+// row (or outside ROWMASK) receive `old`.
+template <int CTRL, int ROWMASK = 0xf>
+__device__ __forceinline__ float dpp_f(float old, float src) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(src), CTRL,
+                                                      ROWMASK, 0xf, false));
+}
+
+__device__ __forceinline__ float readlane_f(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+// Compose the map (pa, pb) in front of (a, b): x -> a (pa x + pb) + b.
+__device__ __forceinline__ void compose_after(float& a, float& b, float pa, float pb) {
+    b = fmaf(a, pb, b);
+    a = a * pa;
+}
+
+// Inclusive scan of affine maps, lane 0 upwards (lane l: maps of lanes 0..l, lane l's
+// applied last): DPP shifts inside each row of 16 lanes, then the row totals (lanes 15,
+// 31, 47) are read as scalars and composed in front of the later rows.
+__device__ __forceinline__ void scan_up_dpp(float& a, float& b, int lane) {
+    compose_after(a, b, dpp_f<0x111>(1.f, a), dpp_f<0x111>(0.f, b));
+    compose_after(a, b, dpp_f<0x112>(1.f, a), dpp_f<0x112>(0.f, b));
+    compose_after(a, b, dpp_f<0x114>(1.f, a), dpp_f<0x114>(0.f, b));
+    compose_after(a, b, dpp_f<0x118>(1.f, a), dpp_f<0x118>(0.f, b));
+    const float a0 = readlane_f(a, 15), b0 = readlane_f(b, 15);
+    const float a1 = readlane_f(a, 31), b1 = readlane_f(b, 31);
+    const float a2 = readlane_f(a, 47), b2 = readlane_f(b, 47);
+    // prefixes of rows: row 1 gets row 0; row 2 gets rows 0..1; row 3 gets rows 0..2
+    float p1a = a0, p1b = b0;
+    float p2a = a1, p2b = b1;
+    compose_after(p2a, p2b, p1a, p1b);
+    float p3a = a2, p3b = b2;
+    compose_after(p3a, p3b, p2a, p2b);
+    const int row = lane >> 4;
+    const float pa = row == 0 ? 1.f : row == 1 ? p1a : row == 2 ? p2a : p3a;
+    const float pb = row == 0 ? 0.f : row == 1 ? p1b : row == 2 ? p2b : p3b;
+    compose_after(a, b, pa, pb);
+}
+
+// Inclusive scan of affine maps, lane 63 downwards (lane l: maps of lanes 63..l, lane l's
+// applied last).
+__device__ __forceinline__ void scan_down_dpp(float& a, float& b, int lane) {
+    compose_after(a, b, dpp_f<0x101>(1.f, a), dpp_f<0x101>(0.f, b));
+    compose_after(a, b, dpp_f<0x102>(1.f, a), dpp_f<0x102>(0.f, b));
+    compose_after(a, b, dpp_f<0x104>(1.f, a), dpp_f<0x104>(0.f, b));
+    compose_after(a, b, dpp_f<0x108>(1.f, a), dpp_f<0x108>(0.f, b));
+    const float a1 = readlane_f(a, 16), b1 = readlane_f(b, 16);
+    const float a2 = readlane_f(a, 32), b2 = readlane_f(b, 32);
+    const float a3 = readlane_f(a, 48), b3 = readlane_f(b, 48);
+    // suffixes of rows: row 2 gets row 3; row 1 gets rows 3..2; row 0 gets rows 3..1
+    float s2a = a3, s2b = b3;
+    float s1a = a2, s1b = b2;
+    compose_after(s1a, s1b, s2a, s2b);
+    float s0a = a1, s0b = b1;
+    compose_after(s0a, s0b, s1a, s1b);
+    const int row = lane >> 4;
+    const float sa = row == 3 ? 1.f : row == 2 ? s2a : row == 1 ? s1a : s0a;
+    const float sb = row == 3 ? 0.f : row == 2 ? s2b : row == 1 ? s1b : s0b;
+    compose_after(a, b, sa, sb);
+}
+
 // Carry words: a float value tagged with the epoch of the launch that wrote it, stored
 // and loaded as one 64-bit device-scope atomic so a reader never sees a value without its
 // tag.  Words from older launches carry older epochs and read as "not yet written".

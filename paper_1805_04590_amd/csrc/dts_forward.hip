@@ -5,11 +5,11 @@
 // distances from the guide's channel differences (Eq. (8)-(9)), weights a^d, and
 // alternating causal+anticausal first-order recursive passes along rows and columns.
 //
-// Row pass: one workgroup per row.  The row is cut into tiles of 256 elements; lane l of a
-// wave owns elements 4l..4l+3 of a tile (one coalesced float4 access per lane).  Each
-// tile is scanned as a chain of affine maps: a serial composition over the lane's four
-// elements, then a 64-lane shuffle scan, then the carry from the previous tile.  Waves own
-// consecutive tiles; wave carries cross through LDS once per direction.
+// Row pass: one workgroup per row.  Lane l of wave v owns S consecutive pixels (float4
+// accesses).  Each direction of the recurrence is a chain of affine maps: a serial
+// composition over the lane's S pixels, one 64-lane scan (DPP inside rows of 16 lanes,
+// scalar reads across rows), one exchange of wave totals through LDS, then a serial sweep
+// from the lane's exact carry-in.
 //
 // Column pass: lanes are columns (every access is a coalesced 256-byte row segment per
 // wave), each workgroup owns a chunk of R rows of its strip and keeps it in registers.
@@ -38,18 +38,50 @@ struct RowArgs {
     float s2;
     int C, H, W;
     float log2a;
-    int tpw;  // tiles per wave
 };
 
-constexpr int kTile = 256;
 constexpr int kMaxRowWaves = 16;
 
-// Up to 16 waves of 64 lanes per row, each owning up to TPW tiles of 256 elements.
-template <int TPW, bool DIST>
+template <int S>
+__device__ __forceinline__ void load_seg(const float* row, int n0, int W, bool vec, float fill,
+                                         float (&v)[S]) {
+    if (vec && n0 + S <= W) {
+#pragma unroll
+        for (int e = 0; e < S; e += 4) {
+            const float4 q = *reinterpret_cast<const float4*>(row + n0 + e);
+            v[e] = q.x;
+            v[e + 1] = q.y;
+            v[e + 2] = q.z;
+            v[e + 3] = q.w;
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < S; ++e) v[e] = (n0 + e < W) ? row[n0 + e] : fill;
+    }
+}
+
+template <int S>
+__device__ __forceinline__ void store_seg(float* row, int n0, int W, bool vec, const float (&v)[S]) {
+    if (vec && n0 + S <= W) {
+#pragma unroll
+        for (int e = 0; e < S; e += 4)
+            *reinterpret_cast<float4*>(row + n0 + e) = make_float4(v[e], v[e + 1], v[e + 2], v[e + 3]);
+    } else {
+#pragma unroll
+        for (int e = 0; e < S; ++e)
+            if (n0 + e < W) row[n0 + e] = v[e];
+    }
+}
+
+// One workgroup per row; lane l of wave v owns the S consecutive pixels starting at
+// (64 v + l) S.  Per direction: a serial composition of the lane's S maps, one 64-lane
+// scan, one exchange of wave totals through LDS, and a serial sweep that produces the
+// final values.
+template <int S, bool DIST>
 __global__ void __launch_bounds__(1024) row_pass_kernel(RowArgs a) {
     __shared__ float2 fagg[kMaxRowWaves];
     __shared__ float2 bagg[kMaxRowWaves];
-    __shared__ float wfirst[kMaxRowWaves];
+    __shared__ float wfirst[kMaxRowWaves + 1];
 
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
@@ -58,228 +90,133 @@ __global__ void __launch_bounds__(1024) row_pass_kernel(RowArgs a) {
     const int b = blockIdx.y;
     const int H = a.H, W = a.W;
     const size_t plane = static_cast<size_t>(H) * W;
-    const int ntiles = (W + kTile - 1) / kTile;
-    const int t0 = wave * a.tpw;
-    const int nt = max(0, min(a.tpw, ntiles - t0));
+    const int n0 = (wave * kWave + lane) * S;
     const bool vec = (W & 3) == 0;
 
-    float w[TPW][4];
+    float w[S];
     if constexpr (DIST) {
-        float ax[TPW][4], ay[TPW][4];
+        float ax[S], ay[S];
 #pragma unroll
-        for (int i = 0; i < TPW; ++i)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) ax[i][e] = ay[i][e] = 0.f;
+        for (int e = 0; e < S; ++e) ax[e] = ay[e] = 0.f;
         for (int k = 0; k < a.Cg; ++k) {
             const float* g = a.guide + (static_cast<size_t>(b) * a.Cg + k) * plane +
                              static_cast<size_t>(y) * W;
             const float* gu = (y > 0) ? g - W : g;
+            float v[S], u[S];
+            load_seg<S>(g, n0, W, vec, 0.f, v);
+            load_seg<S>(gu, n0, W, vec, 0.f, u);
+            float prev = __shfl_up(v[S - 1], 1);
+            if (lane == 0) prev = (n0 > 0 && n0 <= W) ? g[n0 - 1] : v[0];
 #pragma unroll
-            for (int i = 0; i < TPW; ++i) {
-                if (i < nt) {
-                    const int n0 = (t0 + i) * kTile + 4 * lane;
-                    const float4 v = load4(g, n0, W, vec, 0.f);
-                    const float4 u = load4(gu, n0, W, vec, 0.f);
-                    float prev = __shfl_up(v.w, 1);
-                    if (lane == 0) prev = (n0 > 0) ? g[n0 - 1] : v.x;
-                    const float ex0 = v.x - prev, ex1 = v.y - v.x, ex2 = v.z - v.y,
-                                ex3 = v.w - v.z;
-                    ax[i][0] = fmaf(ex0, ex0, ax[i][0]);
-                    ax[i][1] = fmaf(ex1, ex1, ax[i][1]);
-                    ax[i][2] = fmaf(ex2, ex2, ax[i][2]);
-                    ax[i][3] = fmaf(ex3, ex3, ax[i][3]);
-                    const float ey0 = v.x - u.x, ey1 = v.y - u.y, ey2 = v.z - u.z,
-                                ey3 = v.w - u.w;
-                    ay[i][0] = fmaf(ey0, ey0, ay[i][0]);
-                    ay[i][1] = fmaf(ey1, ey1, ay[i][1]);
-                    ay[i][2] = fmaf(ey2, ey2, ay[i][2]);
-                    ay[i][3] = fmaf(ey3, ey3, ay[i][3]);
-                }
+            for (int e = 0; e < S; ++e) {
+                const float ex = v[e] - (e == 0 ? prev : v[e > 0 ? e - 1 : 0]);
+                const float ey = v[e] - u[e];
+                ax[e] = fmaf(ex, ex, ax[e]);
+                ay[e] = fmaf(ey, ey, ay[e]);
             }
         }
         float* dxr = a.dx_out + static_cast<size_t>(b) * plane + static_cast<size_t>(y) * W;
         float* dyr = a.dy_out + static_cast<size_t>(b) * plane + static_cast<size_t>(y) * W;
 #pragma unroll
-        for (int i = 0; i < TPW; ++i) {
-            if (i < nt) {
-                const int n0 = (t0 + i) * kTile + 4 * lane;
-                float4 vx, vy;
-                vx.x = sqrtf(fmaf(a.s2, ax[i][0], 1.f));
-                vx.y = sqrtf(fmaf(a.s2, ax[i][1], 1.f));
-                vx.z = sqrtf(fmaf(a.s2, ax[i][2], 1.f));
-                vx.w = sqrtf(fmaf(a.s2, ax[i][3], 1.f));
-                vy.x = sqrtf(fmaf(a.s2, ay[i][0], 1.f));
-                vy.y = sqrtf(fmaf(a.s2, ay[i][1], 1.f));
-                vy.z = sqrtf(fmaf(a.s2, ay[i][2], 1.f));
-                vy.w = sqrtf(fmaf(a.s2, ay[i][3], 1.f));
-                store4(dxr, n0, W, vec, vx);
-                store4(dyr, n0, W, vec, vy);
+        for (int e = 0; e < S; ++e) {
+            ax[e] = sqrtf(fmaf(a.s2, ax[e], 1.f));
+            ay[e] = sqrtf(fmaf(a.s2, ay[e], 1.f));
+        }
+        store_seg<S>(dxr, n0, W, vec, ax);
+        store_seg<S>(dyr, n0, W, vec, ay);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int n = n0 + e;
-                    w[i][e] = (n > 0 && n < W) ? weight(get(vx, e), a.log2a) : 0.f;
-                }
-            }
+        for (int e = 0; e < S; ++e) {
+            const int n = n0 + e;
+            w[e] = (n > 0 && n < W) ? weight(ax[e], a.log2a) : 0.f;
         }
     } else {
         const float* dr = a.d + static_cast<size_t>(b) * plane + static_cast<size_t>(y) * W;
+        float dv[S];
+        load_seg<S>(dr, n0, W, vec, 1.f, dv);
 #pragma unroll
-        for (int i = 0; i < TPW; ++i) {
-            if (i < nt) {
-                const int n0 = (t0 + i) * kTile + 4 * lane;
-                const float4 dv = load4(dr, n0, W, vec, 1.f);
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int n = n0 + e;
-                    w[i][e] = (n > 0 && n < W) ? weight(get(dv, e), a.log2a) : 0.f;
-                }
-            }
+        for (int e = 0; e < S; ++e) {
+            const int n = n0 + e;
+            w[e] = (n > 0 && n < W) ? weight(dv[e], a.log2a) : 0.f;
         }
     }
-
-    // weight of the first element after this wave's tiles (0 past the end of the row)
-    if (lane == 0 && nt > 0) wfirst[wave] = w[0][0];
+    // weight linking each lane's last pixel to the next pixel (0 past the end of the row)
+    if (lane == 0) wfirst[wave] = w[0];
+    if (threadIdx.x == 0) wfirst[nw] = 0.f;
     __syncthreads();
-    float w_after = 0.f;
-    if (nt > 0 && (t0 + nt) * kTile < W) w_after = wfirst[wave + 1];
+    float wlast = __shfl_down(w[0], 1);
+    if (lane == kWave - 1) wlast = wfirst[wave + 1];
 
     for (int c = 0; c < a.C; ++c) {
         const size_t roff = (static_cast<size_t>(b) * a.C + c) * plane + static_cast<size_t>(y) * W;
-        const float* srow = a.src + roff;
-        float* drow = a.dst + roff;
-        float f[TPW][4];
-        float qs[TPW];     // causal: the lane's state factor just before its first element
-        float ps[TPW];     // anticausal: the lane's state factor just after its last element
-        float wl[TPW];     // weight linking the lane's last element to the next element
+        float f[S];
+        load_seg<S>(a.src + roff, n0, W, vec, 0.f, f);
+
+        // causal: J[n] = w[n] J[n-1] + (1 - w[n]) f[n]
+        float la = 1.f, lb = 0.f;
 #pragma unroll
-        for (int i = 0; i < TPW; ++i) {
-            if (i < nt) {
-                const float4 v = load4(srow, (t0 + i) * kTile + 4 * lane, W, vec, 0.f);
-                f[i][0] = v.x;
-                f[i][1] = v.y;
-                f[i][2] = v.z;
-                f[i][3] = v.w;
-            }
+        for (int e = 0; e < S; ++e) {
+            lb = fmaf(w[e], lb - f[e], f[e]);
+            la *= w[e];
         }
-        // causal: state (Q, J) with J_actual = J + Q * J_in, J_in = J before the wave's tiles
-        float SQ = 1.f, SJ = 0.f;
-#pragma unroll
-        for (int i = 0; i < TPW; ++i) {
-            if (i < nt) {
-                float la = 1.f, lb = 0.f;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    lb = fmaf(w[i][e], lb - f[i][e], f[i][e]);
-                    la *= w[i][e];
-                }
-                scan_maps_up(la, lb, lane);
-                float xa = __shfl_up(la, 1), xb = __shfl_up(lb, 1);
-                if (lane == 0) {
-                    xa = 1.f;
-                    xb = 0.f;
-                }
-                float qq = xa * SQ, jj = fmaf(xa, SJ, xb);
-                qs[i] = qq;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    qq *= w[i][e];
-                    jj = fmaf(w[i][e], jj - f[i][e], f[i][e]);
-                    f[i][e] = jj;
-                }
-                SQ = __shfl(qq, kWave - 1);
-                SJ = __shfl(jj, kWave - 1);
-            }
-        }
-        if (lane == 0) fagg[wave] = make_float2(SQ, SJ);
+        scan_up_dpp(la, lb, lane);
+        if (lane == kWave - 1) fagg[wave] = make_float2(la, lb);
+        float xa = __shfl_up(la, 1), xb = __shfl_up(lb, 1);
         __syncthreads();
         float jin = 0.f;
         for (int u = 0; u < wave; ++u) {
             const float2 g = fagg[u];
             jin = fmaf(g.x, jin, g.y);
         }
+        float j = (lane == 0) ? jin : fmaf(xa, jin, xb);
 #pragma unroll
-        for (int i = 0; i < TPW; ++i) {
-            if (i < nt) {
-                float qq = qs[i];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    qq *= w[i][e];
-                    f[i][e] = fmaf(qq, jin, f[i][e]);
-                }
-            }
+        for (int e = 0; e < S; ++e) {
+            j = fmaf(w[e], j - f[e], f[e]);
+            f[e] = j;
         }
 
-        // anticausal: state (P, K) with K_actual = K + P * K_in, K_in = K after the tiles
-        float SP = 1.f, SK = 0.f;
+        // anticausal: K[n] = w[n+1] K[n+1] + (1 - w[n+1]) J[n]
+        la = 1.f;
+        lb = 0.f;
 #pragma unroll
-        for (int i = TPW - 1; i >= 0; --i) {
-            if (i < nt) {
-                const float from_next_lane = __shfl_down(w[i][0], 1);
-                float tile_next = w_after;
-                if (i + 1 < TPW && i + 1 < nt) tile_next = __shfl(w[(i + 1 < TPW) ? i + 1 : i][0], 0);
-                const float wn3 = (lane == kWave - 1) ? tile_next : from_next_lane;
-                wl[i] = wn3;
-                const float wn[4] = {w[i][1], w[i][2], w[i][3], wn3};
-                float la = 1.f, lb = 0.f;
-#pragma unroll
-                for (int e = 3; e >= 0; --e) {
-                    lb = fmaf(wn[e], lb - f[i][e], f[i][e]);
-                    la *= wn[e];
-                }
-                scan_maps_down(la, lb, lane);
-                float xa = __shfl_down(la, 1), xb = __shfl_down(lb, 1);
-                if (lane == kWave - 1) {
-                    xa = 1.f;
-                    xb = 0.f;
-                }
-                float pp = xa * SP, kk = fmaf(xa, SK, xb);
-                ps[i] = pp;
-#pragma unroll
-                for (int e = 3; e >= 0; --e) {
-                    pp *= wn[e];
-                    kk = fmaf(wn[e], kk - f[i][e], f[i][e]);
-                    f[i][e] = kk;
-                }
-                SP = __shfl(pp, 0);
-                SK = __shfl(kk, 0);
-            }
+        for (int e = S - 1; e >= 0; --e) {
+            const float wn = (e == S - 1) ? wlast : w[e < S - 1 ? e + 1 : e];
+            lb = fmaf(wn, lb - f[e], f[e]);
+            la *= wn;
         }
-        if (lane == 0) bagg[wave] = make_float2(SP, SK);
+        scan_down_dpp(la, lb, lane);
+        if (lane == 0) bagg[wave] = make_float2(la, lb);
+        xa = __shfl_down(la, 1);
+        xb = __shfl_down(lb, 1);
         __syncthreads();
         float kin = 0.f;
         for (int u = nw - 1; u > wave; --u) {
             const float2 g = bagg[u];
             kin = fmaf(g.x, kin, g.y);
         }
+        float k = (lane == kWave - 1) ? kin : fmaf(xa, kin, xb);
 #pragma unroll
-        for (int i = 0; i < TPW; ++i) {
-            if (i < nt) {
-                const float wn[4] = {w[i][1], w[i][2], w[i][3], wl[i]};
-                float pp = ps[i];
-                float4 v;
-                pp *= wn[3];
-                v.w = fmaf(pp, kin, f[i][3]);
-                pp *= wn[2];
-                v.z = fmaf(pp, kin, f[i][2]);
-                pp *= wn[1];
-                v.y = fmaf(pp, kin, f[i][1]);
-                pp *= wn[0];
-                v.x = fmaf(pp, kin, f[i][0]);
-                store4(drow, (t0 + i) * kTile + 4 * lane, W, vec, v);
-            }
+        for (int e = S - 1; e >= 0; --e) {
+            const float wn = (e == S - 1) ? wlast : w[e < S - 1 ? e + 1 : e];
+            k = fmaf(wn, k - f[e], f[e]);
+            f[e] = k;
         }
+        store_seg<S>(a.dst + roff, n0, W, vec, f);
     }
 }
 
-template <int TPW, bool DIST>
+template <int S, bool DIST>
 static void launch_row_t(const RowArgs& a, int nw, int batch, int H, hipStream_t s) {
     // algorithmic bytes: signal in and out (C planes), distances in -- or, on the fused
     // first pass, the guide in (Cg planes) and both distance planes out instead
     const double px = static_cast<double>(batch) * H * a.W;
     const double bytes = DIST ? px * 4.0 * (2.0 * a.C + a.Cg + 2.0) : px * 4.0 * (2.0 * a.C + 1.0);
     ProfScope prof(DIST ? "row_pass_dist" : "row_pass", bytes, s);
-    hipLaunchKernelGGL((row_pass_kernel<TPW, DIST>), dim3(H, batch), dim3(nw * kWave), 0, s, a);
+    hipLaunchKernelGGL((row_pass_kernel<S, DIST>), dim3(H, batch), dim3(nw * kWave), 0, s, a);
 }
+
+// Pixels per lane for a row of width W: long rows use longer lane segments so one wave
+// scan covers more pixels; at most 16 waves per row.
+static int row_segment(int W) { return W > 4096 ? 16 : W > 1024 ? 8 : 4; }
 
 int launch_row_pass(const RowPass& p, Ctx& ctx) {
     RowArgs a;
@@ -295,21 +232,15 @@ int launch_row_pass(const RowPass& p, Ctx& ctx) {
     a.H = p.H;
     a.W = p.W;
     a.log2a = p.log2a;
-    const int ntiles = (p.W + kTile - 1) / kTile;
     const bool dist = p.guide != nullptr;
     const hipStream_t s = ctx.stream;
-    int tpw = 1;
-    if (ntiles <= 16) tpw = 1;
-    else if (ntiles <= 32) tpw = 2;
-    else if (ntiles <= 64) tpw = 4;
-    else return DTS_ENOTSUP;
-    const int nw = (ntiles + tpw - 1) / tpw;
-    a.tpw = tpw;
-    switch (tpw) {
-        case 1: dist ? launch_row_t<1, true>(a, nw, p.batch, p.H, s) : launch_row_t<1, false>(a, nw, p.batch, p.H, s); break;
-        case 2: dist ? launch_row_t<2, true>(a, nw, p.batch, p.H, s) : launch_row_t<2, false>(a, nw, p.batch, p.H, s); break;
+    const int S = row_segment(p.W);
+    const int nw = (p.W + kWave * S - 1) / (kWave * S);
+    if (nw > kMaxRowWaves) return DTS_ENOTSUP;
+    switch (S) {
         case 4: dist ? launch_row_t<4, true>(a, nw, p.batch, p.H, s) : launch_row_t<4, false>(a, nw, p.batch, p.H, s); break;
-        default: dist ? launch_row_t<4, true>(a, nw, p.batch, p.H, s) : launch_row_t<4, false>(a, nw, p.batch, p.H, s); break;
+        case 8: dist ? launch_row_t<8, true>(a, nw, p.batch, p.H, s) : launch_row_t<8, false>(a, nw, p.batch, p.H, s); break;
+        default: dist ? launch_row_t<16, true>(a, nw, p.batch, p.H, s) : launch_row_t<16, false>(a, nw, p.batch, p.H, s); break;
     }
     return hip_fail(hipGetLastError());
 }
@@ -349,11 +280,104 @@ struct CarryWords {
     static constexpr int kWords = 2 + 4 * CT;
 };
 
-template <int CT, int R, int NWC, bool EPI>
-__global__ void __launch_bounds__(kWave * NWC) col_pass_kernel(ColArgs a) {
+// Look-back and look-ahead read this many neighbouring chunks per round trip.
+constexpr int kLookBatch = 4;
+
+// Resolve one chunk's carry from its neighbours (run by one wave, one column per lane).
+// Going away from the chunk (towards chunk 0 for the causal carry, towards the last chunk
+// for the anticausal one), each neighbour j contributes either its inclusive value
+// (which ends the walk) or its affine aggregate x -> A x + B (composed in, walk on).
+template <int CT>
+__device__ void resolve_carry(const ColArgs& a, unsigned long long* (*word)(const ColArgs&, size_t,
+                                                                          int, int, int, int),
+                              size_t strip_base, int col, int chunk, int dir, int wA, int wB,
+                              int wIncl, int ncv, float (&carry)[CT]) {
+    const unsigned ep = a.epoch;
+    float GA = 1.f, GB[CT];
+#pragma unroll
+    for (int c = 0; c < CT; ++c) GB[c] = 0.f;
+    int j = chunk + dir;
+    int spins = 0;
+    const int G = a.G;
+    while (true) {
+        unsigned long long wi[kLookBatch][CT], wa[kLookBatch], wb[kLookBatch][CT];
+#pragma unroll
+        for (int q = 0; q < kLookBatch; ++q) {
+            const int jq = j + q * dir;
+            if (jq >= 0 && jq < G) {
+#pragma unroll
+                for (int c = 0; c < CT; ++c)
+                    if (c < ncv) {
+                        wi[q][c] = __hip_atomic_load(word(a, strip_base, jq, wIncl + c, col, 0),
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        wb[q][c] = __hip_atomic_load(word(a, strip_base, jq, wB + c, col, 0),
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                wa[q] = __hip_atomic_load(word(a, strip_base, jq, wA, col, 0), __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        bool done = false, stalled = false;
+#pragma unroll
+        for (int q = 0; q < kLookBatch; ++q) {
+            if (done || stalled || j < 0 || j >= G) continue;
+            bool inc_ok = true, agg_ok = static_cast<unsigned>(wa[q] >> 32) == ep;
+#pragma unroll
+            for (int c = 0; c < CT; ++c)
+                if (c < ncv) {
+                    inc_ok = inc_ok && static_cast<unsigned>(wi[q][c] >> 32) == ep;
+                    agg_ok = agg_ok && static_cast<unsigned>(wb[q][c] >> 32) == ep;
+                }
+            if (inc_ok) {
+#pragma unroll
+                for (int c = 0; c < CT; ++c)
+                    carry[c] = fmaf(GA, (c < ncv) ? __uint_as_float(static_cast<unsigned>(wi[q][c])) : 0.f, GB[c]);
+                done = true;
+            } else if (agg_ok) {
+#pragma unroll
+                for (int c = 0; c < CT; ++c)
+                    GB[c] = fmaf(GA, (c < ncv) ? __uint_as_float(static_cast<unsigned>(wb[q][c])) : 0.f, GB[c]);
+                GA *= __uint_as_float(static_cast<unsigned>(wa[q]));
+                j += dir;
+            } else {
+                stalled = true;
+            }
+        }
+        if (done) break;
+        if (j < 0 || j >= G) {  // walked past the first / last chunk: the aggregate is exact
+#pragma unroll
+            for (int c = 0; c < CT; ++c) carry[c] = GB[c];
+            break;
+        }
+        if (stalled) {
+            if (++spins > kSpinLimit) {
+                flag_error(a.status, kErrSpinTimeout);
+#pragma unroll
+                for (int c = 0; c < CT; ++c) carry[c] = GB[c];
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        } else {
+            spins = 0;
+        }
+    }
+}
+
+template <int CT>
+__device__ unsigned long long* carry_word(const ColArgs& a, size_t strip_base, int j, int k, int col,
+                                          int) {
+    return a.carry + ((strip_base + j) * CarryWords<CT>::kWords + k) * kWave + col;
+}
+
+// One workgroup = NWV waves stacked vertically over one 64-column strip: wave v owns rows
+// [r0 + v R, r0 + (v+1) R) of the chunk, one column per lane, all in registers.
+template <int CT, int R, int NWV, bool EPI>
+__global__ void __launch_bounds__(kWave * NWV) col_pass_kernel(ColArgs a) {
     using CW = CarryWords<CT>;
-    constexpr int SW = kWave * NWC;
     __shared__ unsigned s_ticket;
+    __shared__ float s_A[NWV][kWave], s_P[NWV][kWave], s_BQ[NWV][kWave];
+    __shared__ float s_B[NWV][CT][kWave], s_BJ[NWV][CT][kWave];
+    __shared__ float s_Jin[NWV][CT][kWave], s_Kin[NWV][CT][kWave];
     if (threadIdx.x == 0) s_ticket = atomicAdd(a.ticket, 1u) - a.ticket_base;
     __syncthreads();
     const unsigned t = __builtin_amdgcn_readfirstlane(s_ticket);
@@ -369,26 +393,28 @@ __global__ void __launch_bounds__(kWave * NWC) col_pass_kernel(ColArgs a) {
     const int b = static_cast<int>(rest / a.NG);
 
     const int lane = lane_id();
-    const int col = (threadIdx.x >> 6) * kWave + lane;
+    const int wave = threadIdx.x >> 6;
     const int H = a.H, W = a.W;
-    const int x = strip * SW + col;
+    const int x = strip * kWave + lane;
     const bool valid = x < W;
-    const int r0 = chunk * R;
-    const int nr = min(R, H - r0);
+    const int r0 = (chunk * NWV + wave) * R;   // first row of this wave
+    const int nr = min(R, max(H - r0, 0));
     const size_t plane = static_cast<size_t>(H) * W;
     const size_t pbytes = plane * sizeof(float);
     const int c0 = grp * CT;
     const int ncv = min(CT, a.C - c0);
-    // Row r of the chunk sits at byte offset voff + r * rowb of a plane; lanes past the
+
+    // Row r of the wave sits at byte offset voff + r * rowb of a plane; lanes past the
     // right edge and rows past the bottom edge fall outside the plane's buffer range, so
     // their loads read 0 and their stores are dropped.
-    const unsigned voff = (valid ? static_cast<unsigned>(x) * 4u : kInvalidOffset) +
-                          static_cast<unsigned>(r0) * static_cast<unsigned>(W) * 4u;
     const unsigned rowb = static_cast<unsigned>(W) * 4u;
+    const unsigned voff = (valid ? static_cast<unsigned>(x) * 4u : kInvalidOffset) +
+                          static_cast<unsigned>(min(r0, H)) * rowb;
 
-    // Weights of the chunk's rows.  The first row of the image and rows past the bottom
-    // edge get weight 0: that is the boundary J[0] = f[0] going down and K[H-1] = J[H-1]
-    // going up, and it makes padded rows drop out of both recurrences.
+    // Weights of the wave's rows and of the row after them.  The first row of the image
+    // and rows past the bottom edge get weight 0: that is the boundary J[0] = f[0] going
+    // down and K[H-1] = J[H-1] going up, and it makes padded rows drop out of both
+    // recurrences.
     float w[R];
     const auto drs = plane_rsrc(a.d + static_cast<size_t>(b) * plane, pbytes);
     {
@@ -401,7 +427,7 @@ __global__ void __launch_bounds__(kWave * NWC) col_pass_kernel(ColArgs a) {
         }
     }
     if (r0 == 0) w[0] = 0.f;
-    const float wnext = weight(bload(drs, voff + static_cast<unsigned>(R) * rowb, 0), a.log2a) *
+    const float wnext = weight(bload(drs, voff + static_cast<unsigned>(nr) * rowb, 0), a.log2a) *
                         ((r0 + R < H) ? 1.f : 0.f);
 
     float f[CT][R];
@@ -417,8 +443,8 @@ __global__ void __launch_bounds__(kWave * NWC) col_pass_kernel(ColArgs a) {
         }
     }
 
-    // phase 1: causal scan with zero carry-in, plus the anticausal coefficients
-    //   K[first] = BJ + BQ * J_carry + P * K_carry
+    // phase 1: causal scan of the wave's rows with zero carry-in, plus the anticausal
+    // coefficients:  K[first] = BJ + BQ * J_carry + P * K_carry
     float Q = 1.f, pi = 1.f, BQ = 0.f;
     float J[CT], BJ[CT];
 #pragma unroll
@@ -438,129 +464,112 @@ __global__ void __launch_bounds__(kWave * NWC) col_pass_kernel(ColArgs a) {
         BQ = fmaf(coef, Q, BQ);
         pi *= wn;
     }
-
-    const size_t strip_base =
-        ((static_cast<size_t>(b) * a.NG + grp) * a.S + strip) * static_cast<size_t>(a.G);
-    auto word = [&](int j, int k) -> unsigned long long* {
-        return a.carry + ((strip_base + j) * CW::kWords + k) * SW + col;
-    };
-    const unsigned ep = a.epoch;
-
-    // causal carry: decoupled look-back over earlier chunks
-    float Jc[CT];
-#pragma unroll
-    for (int c = 0; c < CT; ++c) Jc[c] = 0.f;
-    if (chunk > 0 && valid) {
-        publish(word(chunk, CW::kFwdA), ep, Q);
-#pragma unroll
-        for (int c = 0; c < CT; ++c)
-            if (c < ncv) publish(word(chunk, CW::kFwdB + c), ep, J[c]);
-        float GA = 1.f, GB[CT];
-#pragma unroll
-        for (int c = 0; c < CT; ++c) GB[c] = 0.f;
-        int j = chunk - 1;
-        int spins = 0;
-        while (true) {
-            float v[CT];
-            bool ok = true;
-#pragma unroll
-            for (int c = 0; c < CT; ++c)
-                if (c < ncv) ok = peek(word(j, CW::kFwdIncl + c), ep, v[c]) && ok;
-            if (ok) {
-#pragma unroll
-                for (int c = 0; c < CT; ++c) Jc[c] = fmaf(GA, (c < ncv) ? v[c] : 0.f, GB[c]);
-                break;
-            }
-            float A;
-            ok = peek(word(j, CW::kFwdA), ep, A);
-#pragma unroll
-            for (int c = 0; c < CT; ++c)
-                if (c < ncv) ok = peek(word(j, CW::kFwdB + c), ep, v[c]) && ok;
-            if (ok) {
-#pragma unroll
-                for (int c = 0; c < CT; ++c) GB[c] = fmaf(GA, (c < ncv) ? v[c] : 0.f, GB[c]);
-                GA *= A;
-                spins = 0;
-                if (--j < 0) {
-#pragma unroll
-                    for (int c = 0; c < CT; ++c) Jc[c] = GB[c];
-                    break;
-                }
-                continue;
-            }
-            if (++spins > kSpinLimit) {
-                flag_error(a.status, kErrSpinTimeout);
-#pragma unroll
-                for (int c = 0; c < CT; ++c) Jc[c] = GB[c];
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-    }
-    if (valid) {
-#pragma unroll
-        for (int c = 0; c < CT; ++c)
-            if (c < ncv) publish(word(chunk, CW::kFwdIncl + c), ep, fmaf(Q, Jc[c], J[c]));
-    }
-
-    // anticausal carry: look-ahead over later chunks
-    float alpha[CT], Kc[CT];
+    s_A[wave][lane] = Q;
+    s_P[wave][lane] = pi;
+    s_BQ[wave][lane] = BQ;
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
-        alpha[c] = fmaf(BQ, Jc[c], BJ[c]);
-        Kc[c] = 0.f;
+        s_B[wave][c][lane] = J[c];
+        s_BJ[wave][c][lane] = BJ[c];
     }
-    if (chunk < a.G - 1 && valid) {
-        publish(word(chunk, CW::kBwdP), ep, pi);
+    __syncthreads();
+
+    if (wave == 0) {
+        const size_t strip_base =
+            ((static_cast<size_t>(b) * a.NG + grp) * a.S + strip) * static_cast<size_t>(a.G);
+        const unsigned ep = a.epoch;
+        // chunk-level causal aggregate: compose the waves in order
+        float CA = 1.f, CB[CT];
 #pragma unroll
-        for (int c = 0; c < CT; ++c)
-            if (c < ncv) publish(word(chunk, CW::kBwdAlpha + c), ep, alpha[c]);
-        float GA = 1.f, GB[CT];
+        for (int c = 0; c < CT; ++c) CB[c] = 0.f;
 #pragma unroll
-        for (int c = 0; c < CT; ++c) GB[c] = 0.f;
-        int j = chunk + 1;
-        int spins = 0;
-        while (true) {
-            float v[CT];
-            bool ok = true;
+        for (int v = 0; v < NWV; ++v) {
+            const float Av = s_A[v][lane];
+#pragma unroll
+            for (int c = 0; c < CT; ++c) CB[c] = fmaf(Av, CB[c], s_B[v][c][lane]);
+            CA *= Av;
+        }
+        float Jc[CT];
+#pragma unroll
+        for (int c = 0; c < CT; ++c) Jc[c] = 0.f;
+        if (chunk > 0 && valid) {
+            publish(carry_word<CT>(a, strip_base, chunk, CW::kFwdA, lane, 0), ep, CA);
 #pragma unroll
             for (int c = 0; c < CT; ++c)
-                if (c < ncv) ok = peek(word(j, CW::kBwdIncl + c), ep, v[c]) && ok;
-            if (ok) {
-#pragma unroll
-                for (int c = 0; c < CT; ++c) Kc[c] = fmaf(GA, (c < ncv) ? v[c] : 0.f, GB[c]);
-                break;
-            }
-            float P;
-            ok = peek(word(j, CW::kBwdP), ep, P);
+                if (c < ncv) publish(carry_word<CT>(a, strip_base, chunk, CW::kFwdB + c, lane, 0), ep, CB[c]);
+            resolve_carry<CT>(a, carry_word<CT>, strip_base, lane, chunk, -1, CW::kFwdA, CW::kFwdB,
+                              CW::kFwdIncl, ncv, Jc);
+        }
+        if (valid) {
 #pragma unroll
             for (int c = 0; c < CT; ++c)
-                if (c < ncv) ok = peek(word(j, CW::kBwdAlpha + c), ep, v[c]) && ok;
-            if (ok) {
+                if (c < ncv)
+                    publish(carry_word<CT>(a, strip_base, chunk, CW::kFwdIncl + c, lane, 0), ep,
+                            fmaf(CA, Jc[c], CB[c]));
+        }
+        // causal carry into every wave, and the chunk-level anticausal aggregate
+        float jv[CT];
 #pragma unroll
-                for (int c = 0; c < CT; ++c) GB[c] = fmaf(GA, (c < ncv) ? v[c] : 0.f, GB[c]);
-                GA *= P;
-                spins = 0;
-                if (++j >= a.G) {
+        for (int c = 0; c < CT; ++c) jv[c] = Jc[c];
 #pragma unroll
-                    for (int c = 0; c < CT; ++c) Kc[c] = GB[c];
-                    break;
-                }
-                continue;
+        for (int v = 0; v < NWV; ++v) {
+            const float Av = s_A[v][lane];
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+                s_Jin[v][c][lane] = jv[c];
+                jv[c] = fmaf(Av, jv[c], s_B[v][c][lane]);
             }
-            if (++spins > kSpinLimit) {
-                flag_error(a.status, kErrSpinTimeout);
+        }
+        float CP = 1.f, alpha[CT];
 #pragma unroll
-                for (int c = 0; c < CT; ++c) Kc[c] = GB[c];
-                break;
+        for (int c = 0; c < CT; ++c) alpha[c] = 0.f;
+#pragma unroll
+        for (int v = NWV - 1; v >= 0; --v) {
+            const float Pv = s_P[v][lane], BQv = s_BQ[v][lane];
+#pragma unroll
+            for (int c = 0; c < CT; ++c)
+                alpha[c] = fmaf(Pv, alpha[c], fmaf(BQv, s_Jin[v][c][lane], s_BJ[v][c][lane]));
+            CP *= Pv;
+        }
+        float Kc[CT];
+#pragma unroll
+        for (int c = 0; c < CT; ++c) Kc[c] = 0.f;
+        if (chunk < a.G - 1 && valid) {
+            publish(carry_word<CT>(a, strip_base, chunk, CW::kBwdP, lane, 0), ep, CP);
+#pragma unroll
+            for (int c = 0; c < CT; ++c)
+                if (c < ncv) publish(carry_word<CT>(a, strip_base, chunk, CW::kBwdAlpha + c, lane, 0), ep, alpha[c]);
+            resolve_carry<CT>(a, carry_word<CT>, strip_base, lane, chunk, +1, CW::kBwdP,
+                              CW::kBwdAlpha, CW::kBwdIncl, ncv, Kc);
+        }
+        if (valid) {
+#pragma unroll
+            for (int c = 0; c < CT; ++c)
+                if (c < ncv)
+                    publish(carry_word<CT>(a, strip_base, chunk, CW::kBwdIncl + c, lane, 0), ep,
+                            fmaf(CP, Kc[c], alpha[c]));
+        }
+        // anticausal carry into every wave (K at the row after the wave's last row)
+        float kv[CT];
+#pragma unroll
+        for (int c = 0; c < CT; ++c) kv[c] = Kc[c];
+#pragma unroll
+        for (int v = NWV - 1; v >= 0; --v) {
+            const float Pv = s_P[v][lane], BQv = s_BQ[v][lane];
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+                s_Kin[v][c][lane] = kv[c];
+                kv[c] = fmaf(Pv, kv[c], fmaf(BQv, s_Jin[v][c][lane], s_BJ[v][c][lane]));
             }
-            __builtin_amdgcn_s_sleep(1);
         }
     }
-    if (valid) {
+    __syncthreads();
+
+    float Jin[CT], Kin[CT];
 #pragma unroll
-        for (int c = 0; c < CT; ++c)
-            if (c < ncv) publish(word(chunk, CW::kBwdIncl + c), ep, fmaf(pi, Kc[c], alpha[c]));
+    for (int c = 0; c < CT; ++c) {
+        Jin[c] = s_Jin[wave][c][lane];
+        Kin[c] = s_Kin[wave][c][lane];
     }
 
     // phase 3: causal values with the true carry, then the anticausal sweep and the store
@@ -570,13 +579,13 @@ __global__ void __launch_bounds__(kWave * NWC) col_pass_kernel(ColArgs a) {
         for (int r = 0; r < R; ++r) {
             q *= w[r];
 #pragma unroll
-            for (int c = 0; c < CT; ++c) f[c][r] = fmaf(q, Jc[c], f[c][r]);
+            for (int c = 0; c < CT; ++c) f[c][r] = fmaf(q, Jin[c], f[c][r]);
         }
     }
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
         if (c < ncv) {
-            float K = Kc[c];
+            float K = Kin[c];
             const size_t pidx = static_cast<size_t>(b) * a.C + c0 + c;
             const auto ors = plane_rsrc(a.dst + pidx * plane, pbytes);
             unsigned vo = voff + static_cast<unsigned>(R - 1) * rowb;
@@ -612,35 +621,34 @@ __global__ void __launch_bounds__(kWave * NWC) col_pass_kernel(ColArgs a) {
     }
 }
 
+// Rows per wave and waves per workgroup: a chunk is R * NWV rows.
 template <int CT>
 struct ColShape;
 template <>
 struct ColShape<1> {
-    static constexpr int R = 32;
+    static constexpr int R = 32, NWV = 8;
 };
 template <>
 struct ColShape<2> {
-    static constexpr int R = 24;
+    static constexpr int R = 24, NWV = 8;
 };
 template <>
 struct ColShape<3> {
-    static constexpr int R = 16;
+    static constexpr int R = 16, NWV = 8;
 };
 template <>
 struct ColShape<4> {
-    static constexpr int R = 16;
+    static constexpr int R = 16, NWV = 8;
 };
-
-constexpr int kColWaves = 1;
 
 static int col_group(int C) { return C < 4 ? C : 4; }
 
-static int col_rows(int C) {
+static int col_rows(int C) {  // rows per chunk
     switch (col_group(C)) {
-        case 1: return ColShape<1>::R;
-        case 2: return ColShape<2>::R;
-        case 3: return ColShape<3>::R;
-        default: return ColShape<4>::R;
+        case 1: return ColShape<1>::R * ColShape<1>::NWV;
+        case 2: return ColShape<2>::R * ColShape<2>::NWV;
+        case 3: return ColShape<3>::R * ColShape<3>::NWV;
+        default: return ColShape<4>::R * ColShape<4>::NWV;
     }
 }
 
@@ -648,7 +656,7 @@ size_t col_carry_words(int batch, int H, int W, int C) {
     const int ct = col_group(C);
     const int R = col_rows(C);
     const size_t G = (H + R - 1) / R;
-    const size_t SW = kWave * kColWaves;
+    const size_t SW = kWave;
     const size_t S = (W + SW - 1) / SW;
     const size_t NG = (C + ct - 1) / ct;
     return static_cast<size_t>(batch) * NG * S * G * (2 + 4 * ct) * SW;
@@ -668,8 +676,8 @@ static int col_capacity() {
     if (cached[dev] == 0) {
         int per_cu = 0, cus = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, col_pass_kernel<CT, ColShape<CT>::R, kColWaves, EPI>,
-                kWave * kColWaves, 0) != hipSuccess)
+                &per_cu, col_pass_kernel<CT, ColShape<CT>::R, ColShape<CT>::NWV, EPI>,
+                kWave * ColShape<CT>::NWV, 0) != hipSuccess)
             return 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             return 0;
@@ -689,8 +697,8 @@ static int launch_col_t(const ColArgs& a, unsigned n, hipStream_t s) {
     const double bytes = EPI ? px * 4.0 * (4.0 * a.C + 1.0 + (a.Cc == 1 ? 1.0 : a.C))
                              : px * 4.0 * (2.0 * a.C + 1.0);
     ProfScope prof(EPI ? "col_pass_update" : "col_pass", bytes, s);
-    hipLaunchKernelGGL((col_pass_kernel<CT, ColShape<CT>::R, kColWaves, EPI>), dim3(n),
-                       dim3(kWave * kColWaves), 0, s, a);
+    hipLaunchKernelGGL((col_pass_kernel<CT, ColShape<CT>::R, ColShape<CT>::NWV, EPI>), dim3(n),
+                       dim3(kWave * ColShape<CT>::NWV), 0, s, a);
     return hip_fail(hipGetLastError());
 }
 
@@ -705,7 +713,7 @@ int launch_col_pass(const ColPass& p, Ctx& ctx) {
     a.log2a = p.log2a;
     const int ct = col_group(p.C);
     const int R = col_rows(p.C);
-    const int SW = kWave * kColWaves;
+    const int SW = kWave;
     a.G = (p.H + R - 1) / R;
     a.S = (p.W + SW - 1) / SW;
     a.NG = (p.C + ct - 1) / ct;

@@ -45,6 +45,10 @@ STEP_SHAPES = [
     (513, 600, 16, 3),
     (61, 4096, 1, 4),
     (33, 1000, 3, 6),
+    (3000, 65, 2, 2),
+    (4099, 3, 1, 1),
+    (1500, 130, 3, 3),
+    (700, 200, 2, 4),
 ]
 
 
