@@ -119,6 +119,21 @@ int dts_col_pass(const float* src, float* dst, const float* dy, int C, int batch
                  float sigma_s, int iter, int filter_iters, void* workspace,
                  size_t workspace_bytes, void* stream);
 
+/* ---- Launch-shape tuning (process-wide; set before enqueuing work) ---- */
+
+/* The column pass runs in one of several workgroup shapes per channel-group size (a
+ * group is up to 4 target channels processed together): rows per wave x waves per
+ * workgroup, a chunk of rows per workgroup.  Variants differ only in speed; results agree
+ * to fp32 rounding.  info() returns DTS_EINVAL for an unknown index. */
+int dts_col_variant_count(void);
+int dts_col_variant_info(int variant, int* group_channels, int* rows_per_wave, int* waves);
+/* Pin `variant` for channel groups of `group_channels` (1..4); -1 restores the default. */
+int dts_tune_col_variant(int group_channels, int variant);
+/* Pixels per lane of the row pass: 4, 8 or 16; 0 restores the default, which depends on
+ * the row width.  Rows whose width needs more than 16 waves at this setting fall back to
+ * the default. */
+int dts_tune_row_segment(int pixels_per_lane);
+
 /* ---- Kernel timing (HIP events around each launch, on the launch's own stream) ---- */
 
 /* One row of the timing table: a kernel variant, how many launches were recorded, their

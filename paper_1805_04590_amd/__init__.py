@@ -37,6 +37,9 @@ __all__ = [
     "col_pass",
     "profile_enable",
     "profile_read",
+    "col_variants",
+    "tune_col_variant",
+    "tune_row_segment",
     "EXPORTED_SYMBOLS",
 ]
 
@@ -66,6 +69,10 @@ EXPORTED_SYMBOLS = (
     "dts_col_pass",
     "dts_profile_enable",
     "dts_profile_read",
+    "dts_col_variant_count",
+    "dts_col_variant_info",
+    "dts_tune_col_variant",
+    "dts_tune_row_segment",
 )
 
 
@@ -150,6 +157,15 @@ def library():
     lib.dts_row_pass.restype = i
     lib.dts_col_pass.argtypes = [fp, fp, fp, i, i, i, i, f, i, i, vp, sz, vp]
     lib.dts_col_pass.restype = i
+    ip = ctypes.POINTER(ctypes.c_int)
+    lib.dts_col_variant_count.argtypes = []
+    lib.dts_col_variant_count.restype = i
+    lib.dts_col_variant_info.argtypes = [i, ip, ip, ip]
+    lib.dts_col_variant_info.restype = i
+    lib.dts_tune_col_variant.argtypes = [i, i]
+    lib.dts_tune_col_variant.restype = i
+    lib.dts_tune_row_segment.argtypes = [i]
+    lib.dts_tune_row_segment.restype = i
     lib.dts_profile_enable.argtypes = [i]
     lib.dts_profile_enable.restype = i
     lib.dts_profile_read.argtypes = [ctypes.POINTER(_KernelStat), i]
@@ -269,6 +285,26 @@ def profile_read():
                                     avg_ms=r.total_ms / max(r.launches, 1),
                                     bytes_per_launch=r.bytes / max(r.launches, 1))
     return out
+
+
+def col_variants():
+    """[(index, group_channels, rows_per_wave, waves)] of the column-pass shapes."""
+    lib = library()
+    out = []
+    for v in range(lib.dts_col_variant_count()):
+        ct, r, nw = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib.dts_col_variant_info(v, ctypes.byref(ct), ctypes.byref(r), ctypes.byref(nw)),
+               "dts_col_variant_info")
+        out.append((v, ct.value, r.value, nw.value))
+    return out
+
+
+def tune_col_variant(group_channels, variant):
+    _check(library().dts_tune_col_variant(int(group_channels), int(variant)), "dts_tune_col_variant")
+
+
+def tune_row_segment(pixels_per_lane):
+    _check(library().dts_tune_row_segment(int(pixels_per_lane)), "dts_tune_row_segment")
 
 
 def workspace_status(ws):

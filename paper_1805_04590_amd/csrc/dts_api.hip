@@ -346,6 +346,19 @@ int dts_col_pass(const float* src, float* dst, const float* dy, int C, int batch
     return launch_col_pass(cp, ctx);
 }
 
+int dts_col_variant_count(void) { return num_col_variants(); }
+
+int dts_col_variant_info(int variant, int* group_channels, int* rows_per_wave, int* waves) {
+    if (!group_channels || !rows_per_wave || !waves) return DTS_EINVAL;
+    return col_variant_info(variant, group_channels, rows_per_wave, waves);
+}
+
+int dts_tune_col_variant(int group_channels, int variant) {
+    return tune_col_variant(group_channels, variant);
+}
+
+int dts_tune_row_segment(int pixels_per_lane) { return tune_row_segment(pixels_per_lane); }
+
 int dts_workspace_status(void* workspace, void* stream) {
     if (!workspace) return DTS_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);

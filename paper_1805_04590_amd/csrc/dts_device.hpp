@@ -199,6 +199,17 @@ __device__ __forceinline__ unsigned opaque_vadd(unsigned x, unsigned y) {
     return r;
 }
 
+// Integers the compiler cannot see through (VGPR / SGPR); used inside persistent loops so
+// per-row constants are rebuilt each iteration instead of being hoisted and kept live.
+__device__ __forceinline__ int opaque_v(int x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+__device__ __forceinline__ int opaque_s(int x) {
+    asm volatile("" : "+s"(x));
+    return x;
+}
+
 // A float the compiler cannot see through: starting a product chain from it stops the
 // compiler from keeping every partial product of an identical earlier chain alive.
 __device__ __forceinline__ float opaque(float x) {

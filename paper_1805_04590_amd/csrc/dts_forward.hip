@@ -16,6 +16,7 @@
 // Chunks exchange carries through tagged 64-bit words in device memory: a decoupled
 // look-back resolves the causal carry from earlier chunks, then a look-ahead resolves the
 // anticausal carry from later chunks, so every element is read and written exactly once.
+#include <algorithm>
 #include <mutex>
 
 #include "../../include/dts.h"
@@ -216,7 +217,18 @@ static void launch_row_t(const RowArgs& a, int nw, int batch, int H, hipStream_t
 
 // Pixels per lane for a row of width W: long rows use longer lane segments so one wave
 // scan covers more pixels; at most 16 waves per row.
-static int row_segment(int W) { return W > 4096 ? 16 : W > 1024 ? 8 : 4; }
+static int g_row_pin = 0;
+
+static int row_segment(int W) {
+    if (g_row_pin && (W + kWave * g_row_pin - 1) / (kWave * g_row_pin) <= kMaxRowWaves) return g_row_pin;
+    return W > 4096 ? 16 : W > 1024 ? 8 : 4;
+}
+
+int tune_row_segment(int S) {
+    if (S != 0 && S != 4 && S != 8 && S != 16) return DTS_EINVAL;
+    g_row_pin = S;
+    return DTS_OK;
+}
 
 int launch_row_pass(const RowPass& p, Ctx& ctx) {
     RowArgs a;
@@ -254,10 +266,8 @@ struct ColArgs {
     const float* d;
     int C, H, W;
     float log2a;
-    int G, S, NG;
-    unsigned n_tickets;
-    unsigned* ticket;
-    unsigned ticket_base;
+    int G, S, NG, batch;
+    int groups;  // strips processed at once: the grid holds groups * G workgroups
     unsigned long long* carry;
     unsigned epoch;
     int* status;
@@ -350,13 +360,31 @@ __device__ void resolve_carry(const ColArgs& a, unsigned long long* (*word)(cons
             break;
         }
         if (stalled) {
-            if (++spins > kSpinLimit) {
+            // Wait for the blocking neighbour j gently: poll only its first inclusive word
+            // and its aggregate factor, sleeping longer and longer between polls, and
+            // re-read the whole batch only once one of them has been written.
+            unsigned long long* pi0 = word(a, strip_base, j, wIncl, col, 0);
+            unsigned long long* pa0 = word(a, strip_base, j, wA, col, 0);
+            int backoff = 1;
+            bool seen = false;
+            while (!seen) {
+                const unsigned long long u =
+                    __hip_atomic_load(pi0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const unsigned long long v =
+                    __hip_atomic_load(pa0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                seen = static_cast<unsigned>(u >> 32) == ep || static_cast<unsigned>(v >> 32) == ep;
+                if (seen) break;
+                spins += backoff;
+                if (spins > kSpinLimit) break;
+                for (int i = 0; i < backoff; ++i) __builtin_amdgcn_s_sleep(2);
+                backoff = backoff < 32 ? backoff * 2 : 32;
+            }
+            if (spins > kSpinLimit) {
                 flag_error(a.status, kErrSpinTimeout);
 #pragma unroll
                 for (int c = 0; c < CT; ++c) carry[c] = GB[c];
                 break;
             }
-            __builtin_amdgcn_s_sleep(1);
         } else {
             spins = 0;
         }
@@ -374,26 +402,23 @@ __device__ unsigned long long* carry_word(const ColArgs& a, size_t strip_base, i
 template <int CT, int R, int NWV, bool EPI>
 __global__ void __launch_bounds__(kWave * NWV) col_pass_kernel(ColArgs a) {
     using CW = CarryWords<CT>;
-    __shared__ unsigned s_ticket;
     __shared__ float s_A[NWV][kWave], s_P[NWV][kWave], s_BQ[NWV][kWave];
     __shared__ float s_B[NWV][CT][kWave], s_BJ[NWV][CT][kWave];
     __shared__ float s_Jin[NWV][CT][kWave], s_Kin[NWV][CT][kWave];
-    if (threadIdx.x == 0) s_ticket = atomicAdd(a.ticket, 1u) - a.ticket_base;
-    __syncthreads();
-    const unsigned t = __builtin_amdgcn_readfirstlane(s_ticket);
-    if (t >= a.n_tickets) {  // never taken when the counter was cleared for this call
-        if (threadIdx.x == 0) flag_error(a.status, kErrBadTicket);
-        return;
-    }
-    const int chunk = static_cast<int>(t % a.G);
-    unsigned rest = t / a.G;
-    const int strip = static_cast<int>(rest % a.S);
-    rest /= a.S;
-    const int grp = static_cast<int>(rest % a.NG);
-    const int b = static_cast<int>(rest / a.NG);
+    // Persistent grid: workgroup p always processes chunk p % G, for the strips
+    // p / G, p / G + groups, ...; every strip's chunks are thus held by G workgroups of
+    // the same launch that are all running, and none ever waits on one not yet started.
+    const int chunk = static_cast<int>(blockIdx.x % a.G);
+    const int group = static_cast<int>(blockIdx.x / a.G);
+    const int n_strips = a.batch * a.NG * a.S;
+#pragma unroll 1
+    for (int sid = group; sid < n_strips; sid += a.groups) {
+    const int strip = sid % a.S;
+    const int grp = (sid / a.S) % a.NG;
+    const int b = sid / (a.S * a.NG);
 
-    const int lane = lane_id();
-    const int wave = threadIdx.x >> 6;
+    const int lane = opaque_v(lane_id());
+    const int wave = opaque_s(__builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
     const int H = a.H, W = a.W;
     const int x = strip * kWave + lane;
     const bool valid = x < W;
@@ -595,18 +620,32 @@ __global__ void __launch_bounds__(kWave * NWV) col_pass_kernel(ColArgs a) {
                 const auto trs = plane_rsrc(a.tgt + pidx * plane, pbytes);
                 const auto crs = plane_rsrc(a.conf + (static_cast<size_t>(b) * a.Cc + cc) * plane, pbytes);
                 const auto o2rs = plane_rsrc(a.dst2 ? a.dst2 + pidx * plane : a.dst, a.dst2 ? pbytes : 0);
+                // rows in blocks of kEpiBlock, bottom block first: all loads of a block are
+                // issued before any of its stores, so a block costs one memory round trip
+                constexpr int kEpiBlock = R < 8 ? R : 8;
+                static_assert(R % kEpiBlock == 0, "chunk rows must be a multiple of the block");
 #pragma unroll
-                for (int r = R - 1; r >= 0; --r) {
-                    const float wn = (r + 1 < R) ? w[(r + 1 < R) ? r + 1 : r] : wnext;
-                    K = fmaf(wn, K - f[c][r], f[c][r]);
-                    const float z = bload(zrs, vo, 0);
-                    const float tt = bload(trs, vo, 0);
-                    const float cf = bload(crs, vo, 0);
-                    const float upd = fmaf(a.lambda, z - K, cf * (z - tt));
-                    const float zn = fmaf(-a.step, upd, z);
-                    bstore(ors, vo, 0, zn);
-                    bstore(o2rs, vo, 0, zn);
-                    vo = opaque_vadd(vo, 0u - rowb);
+                for (int blk = R / kEpiBlock - 1; blk >= 0; --blk) {
+                    float z[kEpiBlock], tt[kEpiBlock], cf[kEpiBlock];
+                    unsigned vl = voff + static_cast<unsigned>(blk * kEpiBlock) * rowb;
+#pragma unroll
+                    for (int q = 0; q < kEpiBlock; ++q) {
+                        z[q] = bload(zrs, vl, 0);
+                        tt[q] = bload(trs, vl, 0);
+                        cf[q] = bload(crs, vl, 0);
+                        vl = opaque_vadd(vl, rowb);
+                    }
+#pragma unroll
+                    for (int q = kEpiBlock - 1; q >= 0; --q) {
+                        const int r = blk * kEpiBlock + q;
+                        const float wn = (r + 1 < R) ? w[(r + 1 < R) ? r + 1 : r] : wnext;
+                        K = fmaf(wn, K - f[c][r], f[c][r]);
+                        const float upd = fmaf(a.lambda, z[q] - K, cf[q] * (z[q] - tt[q]));
+                        const float zn = fmaf(-a.step, upd, z[q]);
+                        bstore(ors, vo, 0, zn);
+                        bstore(o2rs, vo, 0, zn);
+                        vo = opaque_vadd(vo, 0u - rowb);
+                    }
                 }
             } else {
 #pragma unroll
@@ -619,55 +658,22 @@ __global__ void __launch_bounds__(kWave * NWV) col_pass_kernel(ColArgs a) {
             }
         }
     }
+    }  // strips of this group
 }
 
-// Rows per wave and waves per workgroup: a chunk is R * NWV rows.
-template <int CT>
-struct ColShape;
-template <>
-struct ColShape<1> {
-    static constexpr int R = 32, NWV = 8;
-};
-template <>
-struct ColShape<2> {
-    static constexpr int R = 24, NWV = 8;
-};
-template <>
-struct ColShape<3> {
-    static constexpr int R = 16, NWV = 8;
-};
-template <>
-struct ColShape<4> {
-    static constexpr int R = 16, NWV = 8;
+// ---------------------------------------------------------------------------------------
+// Column-pass variants: rows per wave R and waves per workgroup NWV (a chunk is R * NWV
+// rows of one 64-column strip) for each channel-group size CT.  The default choice per
+// shape comes from col_variant(); dts_tune_col_variant() can pin another one.
+// ---------------------------------------------------------------------------------------
+struct ColVariant {
+    int ct, R, nwv;
+    int (*launch)(const ColArgs&, unsigned, hipStream_t, bool);
+    int (*capacity)(bool);
 };
 
-static int col_group(int C) { return C < 4 ? C : 4; }
-
-static int col_rows(int C) {  // rows per chunk
-    switch (col_group(C)) {
-        case 1: return ColShape<1>::R * ColShape<1>::NWV;
-        case 2: return ColShape<2>::R * ColShape<2>::NWV;
-        case 3: return ColShape<3>::R * ColShape<3>::NWV;
-        default: return ColShape<4>::R * ColShape<4>::NWV;
-    }
-}
-
-size_t col_carry_words(int batch, int H, int W, int C) {
-    const int ct = col_group(C);
-    const int R = col_rows(C);
-    const size_t G = (H + R - 1) / R;
-    const size_t SW = kWave;
-    const size_t S = (W + SW - 1) / SW;
-    const size_t NG = (C + ct - 1) / ct;
-    return static_cast<size_t>(batch) * NG * S * G * (2 + 4 * ct) * SW;
-}
-
-// Workgroups of one column-pass launch that can be resident at once on this device.  A
-// strip's chunks wait on each other (earlier ones for the causal carry, later ones for
-// the anticausal carry), and tickets are handed out in order to running workgroups only,
-// so the launch always completes when a whole strip's chunks fit on the device at once.
-template <int CT, bool EPI>
-static int col_capacity() {
+template <int CT, int R, int NWV, bool EPI>
+static int col_capacity_t() {
     static int cached[64] = {0};
     static std::mutex mu;
     int dev = 0;
@@ -675,9 +681,8 @@ static int col_capacity() {
     std::lock_guard<std::mutex> lock(mu);
     if (cached[dev] == 0) {
         int per_cu = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, col_pass_kernel<CT, ColShape<CT>::R, ColShape<CT>::NWV, EPI>,
-                kWave * ColShape<CT>::NWV, 0) != hipSuccess)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, col_pass_kernel<CT, R, NWV, EPI>,
+                                                         kWave * NWV, 0) != hipSuccess)
             return 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             return 0;
@@ -686,23 +691,82 @@ static int col_capacity() {
     return cached[dev];
 }
 
-template <int CT, bool EPI>
-static int launch_col_t(const ColArgs& a, unsigned n, hipStream_t s) {
-    const int cap = col_capacity<CT, EPI>();
-    if (cap <= 0) return hip_fail(hipErrorNoDevice);
-    if (a.G > cap) return DTS_ENOTSUP;
-    // algorithmic bytes: signal in and out, distances in; the update epilogue also reads
-    // z^k, the target and the confidence
-    const double px = static_cast<double>(n) / (static_cast<double>(a.NG) * a.S * a.G) * a.H * a.W;
-    const double bytes = EPI ? px * 4.0 * (4.0 * a.C + 1.0 + (a.Cc == 1 ? 1.0 : a.C))
-                             : px * 4.0 * (2.0 * a.C + 1.0);
-    ProfScope prof(EPI ? "col_pass_update" : "col_pass", bytes, s);
-    hipLaunchKernelGGL((col_pass_kernel<CT, ColShape<CT>::R, ColShape<CT>::NWV, EPI>), dim3(n),
-                       dim3(kWave * ColShape<CT>::NWV), 0, s, a);
+template <int CT, int R, int NWV>
+static int col_capacity_v(bool epi) {
+    return epi ? col_capacity_t<CT, R, NWV, true>() : col_capacity_t<CT, R, NWV, false>();
+}
+
+template <int CT, int R, int NWV>
+static int col_launch_v(const ColArgs& a, unsigned n, hipStream_t s, bool epi) {
+    if (epi)
+        hipLaunchKernelGGL((col_pass_kernel<CT, R, NWV, true>), dim3(n), dim3(kWave * NWV), 0, s, a);
+    else
+        hipLaunchKernelGGL((col_pass_kernel<CT, R, NWV, false>), dim3(n), dim3(kWave * NWV), 0, s, a);
     return hip_fail(hipGetLastError());
 }
 
+#define DTS_COL_VARIANT(CT, R, NWV) \
+    ColVariant { CT, R, NWV, col_launch_v<CT, R, NWV>, col_capacity_v<CT, R, NWV> }
+
+static const ColVariant kColVariants[] = {
+    DTS_COL_VARIANT(1, 32, 8),   // 0: 256-row chunks
+    DTS_COL_VARIANT(1, 16, 8),   // 1: 128
+    DTS_COL_VARIANT(1, 32, 4),   // 2: 128
+    DTS_COL_VARIANT(1, 16, 16),  // 3: 256
+    DTS_COL_VARIANT(1, 32, 16),  // 4: 512
+    DTS_COL_VARIANT(2, 24, 8),   // 5: 192
+    DTS_COL_VARIANT(2, 16, 8),   // 6: 128
+    DTS_COL_VARIANT(3, 16, 8),   // 7: 128
+    DTS_COL_VARIANT(3, 8, 16),   // 8: 128
+    DTS_COL_VARIANT(4, 16, 8),   // 9: 128
+};
+constexpr int kNumColVariants = sizeof(kColVariants) / sizeof(kColVariants[0]);
+constexpr int kMinChunkRows = 128;   // smallest R * NWV above: sizes the carry area
+
+static int col_group(int C) { return C < 4 ? C : 4; }
+
+static int g_col_pin[5] = {-1, -1, -1, -1, -1};   // per channel-group size, -1 = default
+
+static int col_variant(int C) {
+    const int ct = col_group(C);
+    const int pin = g_col_pin[ct];
+    if (pin >= 0 && pin < kNumColVariants && kColVariants[pin].ct == ct) return pin;
+    switch (ct) {
+        case 1: return 0;
+        case 2: return 5;
+        case 3: return 7;
+        default: return 9;
+    }
+}
+
+int tune_col_variant(int ct, int variant) {
+    if (ct < 1 || ct > 4) return DTS_EINVAL;
+    if (variant >= kNumColVariants || (variant >= 0 && kColVariants[variant].ct != ct)) return DTS_EINVAL;
+    g_col_pin[ct] = variant < 0 ? -1 : variant;
+    return DTS_OK;
+}
+
+int col_variant_info(int variant, int* ct, int* rows_per_wave, int* waves) {
+    if (variant < 0 || variant >= kNumColVariants) return DTS_EINVAL;
+    *ct = kColVariants[variant].ct;
+    *rows_per_wave = kColVariants[variant].R;
+    *waves = kColVariants[variant].nwv;
+    return DTS_OK;
+}
+
+int num_col_variants() { return kNumColVariants; }
+
+size_t col_carry_words(int batch, int H, int W, int C) {
+    // sized for the smallest chunk of any variant so every variant fits
+    const int ct = col_group(C);
+    const size_t G = (H + kMinChunkRows - 1) / kMinChunkRows;
+    const size_t S = (W + kWave - 1) / kWave;
+    const size_t NG = (C + ct - 1) / ct;
+    return static_cast<size_t>(batch) * NG * S * G * (2 + 4 * ct) * kWave;
+}
+
 int launch_col_pass(const ColPass& p, Ctx& ctx) {
+    const ColVariant& v = kColVariants[col_variant(p.C)];
     ColArgs a;
     a.src = p.src;
     a.dst = p.dst;
@@ -711,14 +775,12 @@ int launch_col_pass(const ColPass& p, Ctx& ctx) {
     a.H = p.H;
     a.W = p.W;
     a.log2a = p.log2a;
-    const int ct = col_group(p.C);
-    const int R = col_rows(p.C);
-    const int SW = kWave;
-    a.G = (p.H + R - 1) / R;
-    a.S = (p.W + SW - 1) / SW;
+    const int ct = v.ct;
+    const int rows = v.R * v.nwv;
+    a.G = (p.H + rows - 1) / rows;
+    a.S = (p.W + kWave - 1) / kWave;
     a.NG = (p.C + ct - 1) / ct;
-    a.ticket = ctx.ticket;
-    a.ticket_base = ctx.ticket_base;
+    a.batch = p.batch;
     a.carry = ctx.carry;
     a.epoch = ++ctx.epoch;
     a.status = ctx.status;
@@ -729,15 +791,21 @@ int launch_col_pass(const ColPass& p, Ctx& ctx) {
     a.dst2 = p.dst2;
     a.lambda = p.lambda;
     a.step = p.step;
-    const unsigned n = static_cast<unsigned>(p.batch) * a.NG * a.S * a.G;
-    a.n_tickets = n;
-    ctx.ticket_base += n;
-    switch (ct) {
-        case 1: return p.epilogue ? launch_col_t<1, true>(a, n, ctx.stream) : launch_col_t<1, false>(a, n, ctx.stream);
-        case 2: return p.epilogue ? launch_col_t<2, true>(a, n, ctx.stream) : launch_col_t<2, false>(a, n, ctx.stream);
-        case 3: return p.epilogue ? launch_col_t<3, true>(a, n, ctx.stream) : launch_col_t<3, false>(a, n, ctx.stream);
-        default: return p.epilogue ? launch_col_t<4, true>(a, n, ctx.stream) : launch_col_t<4, false>(a, n, ctx.stream);
-    }
+    // every workgroup of the grid must be resident at once: size the grid to the
+    // device's capacity for this kernel, in whole strips of G chunks
+    const int cap = v.capacity(p.epilogue);
+    if (cap <= 0) return hip_fail(hipErrorNoDevice);
+    if (a.G > cap) return DTS_ENOTSUP;
+    const long long n_strips = static_cast<long long>(p.batch) * a.NG * a.S;
+    a.groups = static_cast<int>(std::min<long long>(cap / a.G, n_strips));
+    const unsigned n = static_cast<unsigned>(a.groups) * a.G;
+    // algorithmic bytes: signal in and out, distances in; the update epilogue also reads
+    // z^k, the target and the confidence
+    const double px = static_cast<double>(p.batch) * a.H * a.W;
+    const double bytes = p.epilogue ? px * 4.0 * (4.0 * a.C + 1.0 + (a.Cc == 1 ? 1.0 : a.C))
+                                    : px * 4.0 * (2.0 * a.C + 1.0);
+    ProfScope prof(p.epilogue ? "col_pass_update" : "col_pass", bytes, ctx.stream);
+    return v.launch(a, n, ctx.stream, p.epilogue);
 }
 
 // ---------------------------------------------------------------------------------------
