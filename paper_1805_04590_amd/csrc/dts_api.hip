@@ -9,6 +9,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 
 #include "../../include/dts.h"
@@ -52,6 +53,43 @@ static Layout make_layout(int batch, int H, int W, int C, bool with_tmp) {
     }
     L.carry = off;
     L.carry_bytes = align_up(col_carry_words(batch, H, W, C) * sizeof(unsigned long long));
+    off += L.carry_bytes;
+    L.total = off;
+    return L;
+}
+
+// Backward workspace: [header | dx | dy | gdx | gdy (one plane set per adjoint channel
+// group) | tape of the 2N-1 pass inputs after the first | gz | ga | gb | carry words]
+struct BwdLayout {
+    size_t dx, dy, gdx, gdy, tape, gz, ga, gb, carry, carry_bytes, total;
+    int ngy;
+};
+
+static BwdLayout make_backward_layout(int batch, int H, int W, int Ct, int N) {
+    BwdLayout L;
+    const size_t plane = static_cast<size_t>(batch) * H * W * sizeof(float);
+    const size_t sig = plane * Ct;
+    L.ngy = col_adjoint_groups(Ct);
+    size_t off = kHeaderBytes;
+    L.dx = off;
+    off = align_up(off + plane);
+    L.dy = off;
+    off = align_up(off + plane);
+    L.gdx = off;
+    off = align_up(off + plane);
+    L.gdy = off;
+    off = align_up(off + plane * L.ngy);
+    L.tape = off;
+    off = align_up(off + sig * (2 * N - 1));
+    L.gz = off;
+    off = align_up(off + sig);
+    L.ga = off;
+    off = align_up(off + sig);
+    L.gb = off;
+    off = align_up(off + sig);
+    L.carry = off;
+    const size_t words = std::max(col_carry_words(batch, H, W, Ct), col_adjoint_carry_words(batch, H, W, Ct));
+    L.carry_bytes = align_up(words * sizeof(unsigned long long));
     off += L.carry_bytes;
     L.total = off;
     return L;
@@ -129,13 +167,9 @@ size_t dts_solve_workspace_bytes(int batch, int H, int W, int Ct, const dts_para
 
 size_t dts_solve_backward_workspace_bytes(int batch, int H, int W, int Cg, int Ct,
                                           const dts_params* p) {
-    (void)batch;
-    (void)H;
-    (void)W;
-    (void)Cg;
-    (void)Ct;
-    (void)p;
-    return 0;
+    if (!p || check_shape(batch, H, W) || check_channels(Cg) || check_channels(Ct)) return 0;
+    if (p->filter_iters < 1 || p->filter_iters > kMaxFilterIters) return 0;
+    return make_backward_layout(batch, H, W, Ct, p->filter_iters).total;
 }
 
 int dts_filter(const float* guide, int Cg, const float* src, float* dst, int Cs, int batch, int H,
@@ -253,10 +287,158 @@ int dts_solve_backward(const float* guide, int Cg, const float* target, const fl
                        const float* checkpoints, const float* grad_out, float* grad_target,
                        float* grad_conf, float* grad_guide, void* workspace,
                        size_t workspace_bytes, void* stream) {
-    (void)guide; (void)Cg; (void)target; (void)conf; (void)Cc; (void)Ct; (void)batch; (void)H;
-    (void)W; (void)p; (void)checkpoints; (void)grad_out; (void)grad_target; (void)grad_conf;
-    (void)grad_guide; (void)workspace; (void)workspace_bytes; (void)stream;
-    return DTS_ENOTSUP;
+    if (!guide || !target || !conf || !grad_out || !p) return DTS_EINVAL;
+    int rc = check_shape(batch, H, W);
+    if (rc) return rc;
+    if (check_channels(Cg) || check_channels(Ct)) return DTS_EINVAL;
+    if (Cc != 1 && Cc != Ct) return DTS_EINVAL;
+    if (!finite_pos(p->sigma_s) || !finite_pos(p->sigma_r)) return DTS_EINVAL;
+    if (p->filter_iters < 1 || p->filter_iters > kMaxFilterIters) return DTS_EINVAL;
+    if (p->solver_iters < 0 || p->solver_iters > kMaxSolverIters) return DTS_EINVAL;
+    if (!isfinite(p->lambda) || !isfinite(p->step)) return DTS_EINVAL;
+    const int T = p->solver_iters, N = p->filter_iters;
+    if (T > 0 && !checkpoints) return DTS_EINVAL;
+    const BwdLayout L = make_backward_layout(batch, H, W, Ct, N);
+    if (!workspace || workspace_bytes < L.total || (reinterpret_cast<uintptr_t>(workspace) & 15u))
+        return DTS_EWORKSPACE;
+    char* base = static_cast<char*>(workspace);
+    Ctx ctx;
+    ctx.stream = static_cast<hipStream_t>(stream);
+    ctx.status = reinterpret_cast<int*>(base);
+    ctx.ticket = reinterpret_cast<unsigned*>(base + kTicketOffset);
+    ctx.carry = reinterpret_cast<unsigned long long*>(base + L.carry);
+    ctx.carry_words = L.carry_bytes / sizeof(unsigned long long);
+    float* dx = reinterpret_cast<float*>(base + L.dx);
+    float* dy = reinterpret_cast<float*>(base + L.dy);
+    float* gdx = grad_guide ? reinterpret_cast<float*>(base + L.gdx) : nullptr;
+    float* gdy = grad_guide ? reinterpret_cast<float*>(base + L.gdy) : nullptr;
+    float* tape = reinterpret_cast<float*>(base + L.tape);
+    float* gz = reinterpret_cast<float*>(base + L.gz);
+    float* gab[2] = {reinterpret_cast<float*>(base + L.ga), reinterpret_cast<float*>(base + L.gb)};
+    const size_t plane = static_cast<size_t>(batch) * H * W;
+    const size_t sig = plane * Ct;
+    const hipStream_t s = ctx.stream;
+
+    if ((rc = launch_zero(base, kHeaderBytes, s))) return rc;
+    if ((rc = launch_zero(base + L.carry, L.carry_bytes, s))) return rc;
+    if (grad_guide && (rc = launch_zero(base + L.gdx, L.tape - L.gdx, s))) return rc;
+    if (grad_target && (rc = launch_zero(grad_target, sig * sizeof(float), s))) return rc;
+    if (grad_conf && (rc = launch_zero(grad_conf, plane * Cc * sizeof(float), s))) return rc;
+    if (T == 0) {
+        if (grad_target && (rc = launch_copy(grad_target, grad_out, sig, s))) return rc;
+        if (grad_guide && (rc = launch_zero(grad_guide, plane * Cg * sizeof(float), s))) return rc;
+        return DTS_OK;
+    }
+    const float s2 = static_cast<float>((static_cast<double>(p->sigma_s) / p->sigma_r) *
+                                        (static_cast<double>(p->sigma_s) / p->sigma_r));
+    // distances once
+    {
+        RowPass rp{};
+        rp.guide = guide;
+        rp.dx_out = dx;
+        rp.dy_out = dy;
+        rp.Cg = Cg;
+        rp.s2 = s2;
+        rp.C = 0;
+        rp.H = H;
+        rp.W = W;
+        rp.batch = batch;
+        if ((rc = launch_row_pass(rp, ctx))) return rc;
+    }
+    if ((rc = launch_copy(gz, grad_out, sig, s))) return rc;
+    const int npass = 2 * N;
+    for (int k = T - 1; k >= 0; --k) {
+        const float* zk = checkpoints + static_cast<size_t>(k) * sig;
+        // recompute the inputs of passes 2..2N of DT(z^k): pass p reads in(p), writes in(p+1)
+        auto in = [&](int pass) -> const float* {
+            return pass == 1 ? zk : tape + static_cast<size_t>(pass - 2) * sig;
+        };
+        for (int pass = 1; pass < npass; ++pass) {
+            const int i = (pass + 1) / 2;
+            const float l2a = log2_feedback(p->sigma_s, i, N);
+            float* out = tape + static_cast<size_t>(pass - 1) * sig;
+            if (pass & 1) {
+                RowPass rp{};
+                rp.src = in(pass);
+                rp.dst = out;
+                rp.d = dx;
+                rp.C = Ct;
+                rp.H = H;
+                rp.W = W;
+                rp.batch = batch;
+                rp.log2a = l2a;
+                if ((rc = launch_row_pass(rp, ctx))) return rc;
+            } else {
+                ColPass cp{};
+                cp.src = in(pass);
+                cp.dst = out;
+                cp.d = dy;
+                cp.C = Ct;
+                cp.H = H;
+                cp.W = W;
+                cp.batch = batch;
+                cp.log2a = l2a;
+                if ((rc = launch_col_pass(cp, ctx))) return rc;
+            }
+        }
+        // adjoint passes in reverse order; the last one carries the update adjoint
+        const float* gin = gz;
+        float gscale = p->step * p->lambda;
+        int flip = 0;
+        for (int pass = npass; pass >= 1; --pass) {
+            const int i = (pass + 1) / 2;
+            const float l2a = log2_feedback(p->sigma_s, i, N);
+            float* gout = gab[flip];
+            if (pass & 1) {
+                RowAdj ra{};
+                ra.gk = gin;
+                ra.gk_scale = gscale;
+                ra.f = in(pass);
+                ra.d = dx;
+                ra.gout = gout;
+                ra.gd = gdx;
+                ra.C = Ct;
+                ra.H = H;
+                ra.W = W;
+                ra.batch = batch;
+                ra.log2a = l2a;
+                if (pass == 1) {
+                    ra.gz = gz;
+                    ra.tgt = target;
+                    ra.conf = conf;
+                    ra.gt = grad_target;
+                    ra.gc = grad_conf;
+                    ra.Cc = Cc;
+                    ra.lambda = p->lambda;
+                    ra.step = p->step;
+                    ra.last = (k == 0);
+                }
+                if ((rc = launch_row_adjoint(ra, ctx))) return rc;
+            } else {
+                ColAdj ca{};
+                ca.gk = gin;
+                ca.gk_scale = gscale;
+                ca.f = in(pass);
+                ca.d = dy;
+                ca.gout = gout;
+                ca.gd = gdy;
+                ca.C = Ct;
+                ca.H = H;
+                ca.W = W;
+                ca.batch = batch;
+                ca.log2a = l2a;
+                if ((rc = launch_col_adjoint(ca, ctx))) return rc;
+            }
+            gin = gout;
+            gscale = 1.f;
+            flip ^= 1;
+        }
+    }
+    if (grad_guide) {
+        DistAdj da{guide, dx, dy, gdx, gdy, L.ngy, grad_guide, Cg, H, W, batch, s2};
+        if ((rc = launch_dist_adjoint(da, ctx))) return rc;
+    }
+    return DTS_OK;
 }
 
 int dts_distances(const float* guide, int Cg, int batch, int H, int W, float sigma_s,

@@ -222,3 +222,103 @@ __device__ __forceinline__ float get(const float4& v, int e) {
 }
 
 }  // namespace dts
+
+namespace dts {
+
+// Affine-map scans with one shared factor and NB offsets: lane l ends with the maps of
+// lanes 0..l (up) or 63..l (down), its own applied last.  Used where several recurrences
+// share their weights (a signal and its adjoint, or several channels).
+template <int NB>
+__device__ __forceinline__ void compose_after_n(float& a, float (&b)[NB], float pa, const float (&pb)[NB]) {
+#pragma unroll
+    for (int i = 0; i < NB; ++i) b[i] = fmaf(a, pb[i], b[i]);
+    a = a * pa;
+}
+
+template <int CTRL, int NB>
+__device__ __forceinline__ void dpp_step_n(float& a, float (&b)[NB]) {
+    float pb[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) pb[i] = dpp_f<CTRL>(0.f, b[i]);
+    compose_after_n<NB>(a, b, dpp_f<CTRL>(1.f, a), pb);
+}
+
+template <int NB>
+__device__ __forceinline__ void scan_up_dpp_n(float& a, float (&b)[NB], int lane) {
+    dpp_step_n<0x111, NB>(a, b);
+    dpp_step_n<0x112, NB>(a, b);
+    dpp_step_n<0x114, NB>(a, b);
+    dpp_step_n<0x118, NB>(a, b);
+    float ra[3], rb[3][NB];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        ra[r] = readlane_f(a, 16 * r + 15);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) rb[r][i] = readlane_f(b[i], 16 * r + 15);
+    }
+    // prefix of rows before row r: row 1 <- row 0, row 2 <- rows 0..1, row 3 <- rows 0..2
+    float pa[4], pb[4][NB];
+    pa[0] = 1.f;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) pb[0][i] = 0.f;
+#pragma unroll
+    for (int r = 1; r < 4; ++r) {
+        pa[r] = ra[r - 1];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) pb[r][i] = rb[r - 1][i];
+        compose_after_n<NB>(pa[r], pb[r], pa[r - 1], pb[r - 1]);
+    }
+    const int row = lane >> 4;
+    float qa = pa[0], qb[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) qb[i] = pb[0][i];
+#pragma unroll
+    for (int r = 1; r < 4; ++r)
+        if (row == r) {
+            qa = pa[r];
+#pragma unroll
+            for (int i = 0; i < NB; ++i) qb[i] = pb[r][i];
+        }
+    compose_after_n<NB>(a, b, qa, qb);
+}
+
+template <int NB>
+__device__ __forceinline__ void scan_down_dpp_n(float& a, float (&b)[NB], int lane) {
+    dpp_step_n<0x101, NB>(a, b);
+    dpp_step_n<0x102, NB>(a, b);
+    dpp_step_n<0x104, NB>(a, b);
+    dpp_step_n<0x108, NB>(a, b);
+    float ra[4], rb[4][NB];
+#pragma unroll
+    for (int r = 1; r < 4; ++r) {
+        ra[r] = readlane_f(a, 16 * r);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) rb[r][i] = readlane_f(b[i], 16 * r);
+    }
+    // suffix of rows after row r: row 2 <- row 3, row 1 <- rows 3..2, row 0 <- rows 3..1
+    float sa[4], sb[4][NB];
+    sa[3] = 1.f;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) sb[3][i] = 0.f;
+#pragma unroll
+    for (int r = 2; r >= 0; --r) {
+        sa[r] = ra[r + 1];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) sb[r][i] = rb[r + 1][i];
+        compose_after_n<NB>(sa[r], sb[r], sa[r + 1], sb[r + 1]);
+    }
+    const int row = lane >> 4;
+    float qa = sa[3], qb[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) qb[i] = sb[3][i];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+        if (row == r) {
+            qa = sa[r];
+#pragma unroll
+            for (int i = 0; i < NB; ++i) qb[i] = sb[r][i];
+        }
+    compose_after_n<NB>(a, b, qa, qb);
+}
+
+}  // namespace dts

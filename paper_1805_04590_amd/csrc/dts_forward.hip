@@ -20,6 +20,7 @@
 #include <mutex>
 
 #include "../../include/dts.h"
+#include "dts_chunks.hpp"
 #include "dts_device.hpp"
 #include "dts_internal.hpp"
 
@@ -279,132 +280,12 @@ struct ColArgs {
     float lambda, step;
 };
 
-template <int CT>
-struct CarryWords {
-    static constexpr int kFwdA = 0;                 // product of the chunk's weights
-    static constexpr int kFwdB = 1;                 // + c: causal output, zero carry-in
-    static constexpr int kFwdIncl = 1 + CT;         // + c: causal output at the chunk end
-    static constexpr int kBwdP = 1 + 2 * CT;        // anticausal carry factor
-    static constexpr int kBwdAlpha = 2 + 2 * CT;    // + c: anticausal output, zero carry-in
-    static constexpr int kBwdIncl = 2 + 3 * CT;     // + c: anticausal output at chunk start
-    static constexpr int kWords = 2 + 4 * CT;
-};
-
-// Look-back and look-ahead read this many neighbouring chunks per round trip.
-constexpr int kLookBatch = 4;
-
-// Resolve one chunk's carry from its neighbours (run by one wave, one column per lane).
-// Going away from the chunk (towards chunk 0 for the causal carry, towards the last chunk
-// for the anticausal one), each neighbour j contributes either its inclusive value
-// (which ends the walk) or its affine aggregate x -> A x + B (composed in, walk on).
-template <int CT>
-__device__ void resolve_carry(const ColArgs& a, unsigned long long* (*word)(const ColArgs&, size_t,
-                                                                          int, int, int, int),
-                              size_t strip_base, int col, int chunk, int dir, int wA, int wB,
-                              int wIncl, int ncv, float (&carry)[CT]) {
-    const unsigned ep = a.epoch;
-    float GA = 1.f, GB[CT];
-#pragma unroll
-    for (int c = 0; c < CT; ++c) GB[c] = 0.f;
-    int j = chunk + dir;
-    int spins = 0;
-    const int G = a.G;
-    while (true) {
-        unsigned long long wi[kLookBatch][CT], wa[kLookBatch], wb[kLookBatch][CT];
-#pragma unroll
-        for (int q = 0; q < kLookBatch; ++q) {
-            const int jq = j + q * dir;
-            if (jq >= 0 && jq < G) {
-#pragma unroll
-                for (int c = 0; c < CT; ++c)
-                    if (c < ncv) {
-                        wi[q][c] = __hip_atomic_load(word(a, strip_base, jq, wIncl + c, col, 0),
-                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        wb[q][c] = __hip_atomic_load(word(a, strip_base, jq, wB + c, col, 0),
-                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    }
-                wa[q] = __hip_atomic_load(word(a, strip_base, jq, wA, col, 0), __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
-            }
-        }
-        bool done = false, stalled = false;
-#pragma unroll
-        for (int q = 0; q < kLookBatch; ++q) {
-            if (done || stalled || j < 0 || j >= G) continue;
-            bool inc_ok = true, agg_ok = static_cast<unsigned>(wa[q] >> 32) == ep;
-#pragma unroll
-            for (int c = 0; c < CT; ++c)
-                if (c < ncv) {
-                    inc_ok = inc_ok && static_cast<unsigned>(wi[q][c] >> 32) == ep;
-                    agg_ok = agg_ok && static_cast<unsigned>(wb[q][c] >> 32) == ep;
-                }
-            if (inc_ok) {
-#pragma unroll
-                for (int c = 0; c < CT; ++c)
-                    carry[c] = fmaf(GA, (c < ncv) ? __uint_as_float(static_cast<unsigned>(wi[q][c])) : 0.f, GB[c]);
-                done = true;
-            } else if (agg_ok) {
-#pragma unroll
-                for (int c = 0; c < CT; ++c)
-                    GB[c] = fmaf(GA, (c < ncv) ? __uint_as_float(static_cast<unsigned>(wb[q][c])) : 0.f, GB[c]);
-                GA *= __uint_as_float(static_cast<unsigned>(wa[q]));
-                j += dir;
-            } else {
-                stalled = true;
-            }
-        }
-        if (done) break;
-        if (j < 0 || j >= G) {  // walked past the first / last chunk: the aggregate is exact
-#pragma unroll
-            for (int c = 0; c < CT; ++c) carry[c] = GB[c];
-            break;
-        }
-        if (stalled) {
-            // Wait for the blocking neighbour j gently: poll only its first inclusive word
-            // and its aggregate factor, sleeping longer and longer between polls, and
-            // re-read the whole batch only once one of them has been written.
-            unsigned long long* pi0 = word(a, strip_base, j, wIncl, col, 0);
-            unsigned long long* pa0 = word(a, strip_base, j, wA, col, 0);
-            int backoff = 1;
-            bool seen = false;
-            while (!seen) {
-                const unsigned long long u =
-                    __hip_atomic_load(pi0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const unsigned long long v =
-                    __hip_atomic_load(pa0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                seen = static_cast<unsigned>(u >> 32) == ep || static_cast<unsigned>(v >> 32) == ep;
-                if (seen) break;
-                spins += backoff;
-                if (spins > kSpinLimit) break;
-                for (int i = 0; i < backoff; ++i) __builtin_amdgcn_s_sleep(2);
-                backoff = backoff < 32 ? backoff * 2 : 32;
-            }
-            if (spins > kSpinLimit) {
-                flag_error(a.status, kErrSpinTimeout);
-#pragma unroll
-                for (int c = 0; c < CT; ++c) carry[c] = GB[c];
-                break;
-            }
-        } else {
-            spins = 0;
-        }
-    }
-}
-
-template <int CT>
-__device__ unsigned long long* carry_word(const ColArgs& a, size_t strip_base, int j, int k, int col,
-                                          int) {
-    return a.carry + ((strip_base + j) * CarryWords<CT>::kWords + k) * kWave + col;
-}
-
 // One workgroup = NWV waves stacked vertically over one 64-column strip: wave v owns rows
 // [r0 + v R, r0 + (v+1) R) of the chunk, one column per lane, all in registers.
 template <int CT, int R, int NWV, bool EPI>
 __global__ void __launch_bounds__(kWave * NWV) col_pass_kernel(ColArgs a) {
-    using CW = CarryWords<CT>;
-    __shared__ float s_A[NWV][kWave], s_P[NWV][kWave], s_BQ[NWV][kWave];
-    __shared__ float s_B[NWV][CT][kWave], s_BJ[NWV][CT][kWave];
-    __shared__ float s_Jin[NWV][CT][kWave], s_Kin[NWV][CT][kWave];
+    __shared__ ChunkLds<CT, NWV> L;
+    const CarryCtx cctx{a.carry, a.epoch, a.status, a.G, a.S, a.NG};
     // Persistent grid: workgroup p always processes chunk p % G, for the strips
     // p / G, p / G + groups, ...; every strip's chunks are thus held by G workgroups of
     // the same launch that are all running, and none ever waits on one not yet started.
@@ -489,112 +370,23 @@ __global__ void __launch_bounds__(kWave * NWV) col_pass_kernel(ColArgs a) {
         BQ = fmaf(coef, Q, BQ);
         pi *= wn;
     }
-    s_A[wave][lane] = Q;
-    s_P[wave][lane] = pi;
-    s_BQ[wave][lane] = BQ;
+    L.A[wave][lane] = Q;
+    L.P[wave][lane] = pi;
+    L.BQ[wave][lane] = BQ;
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
-        s_B[wave][c][lane] = J[c];
-        s_BJ[wave][c][lane] = BJ[c];
+        L.B[wave][c][lane] = J[c];
+        L.BJ[wave][c][lane] = BJ[c];
     }
     __syncthreads();
-
-    if (wave == 0) {
-        const size_t strip_base =
-            ((static_cast<size_t>(b) * a.NG + grp) * a.S + strip) * static_cast<size_t>(a.G);
-        const unsigned ep = a.epoch;
-        // chunk-level causal aggregate: compose the waves in order
-        float CA = 1.f, CB[CT];
-#pragma unroll
-        for (int c = 0; c < CT; ++c) CB[c] = 0.f;
-#pragma unroll
-        for (int v = 0; v < NWV; ++v) {
-            const float Av = s_A[v][lane];
-#pragma unroll
-            for (int c = 0; c < CT; ++c) CB[c] = fmaf(Av, CB[c], s_B[v][c][lane]);
-            CA *= Av;
-        }
-        float Jc[CT];
-#pragma unroll
-        for (int c = 0; c < CT; ++c) Jc[c] = 0.f;
-        if (chunk > 0 && valid) {
-            publish(carry_word<CT>(a, strip_base, chunk, CW::kFwdA, lane, 0), ep, CA);
-#pragma unroll
-            for (int c = 0; c < CT; ++c)
-                if (c < ncv) publish(carry_word<CT>(a, strip_base, chunk, CW::kFwdB + c, lane, 0), ep, CB[c]);
-            resolve_carry<CT>(a, carry_word<CT>, strip_base, lane, chunk, -1, CW::kFwdA, CW::kFwdB,
-                              CW::kFwdIncl, ncv, Jc);
-        }
-        if (valid) {
-#pragma unroll
-            for (int c = 0; c < CT; ++c)
-                if (c < ncv)
-                    publish(carry_word<CT>(a, strip_base, chunk, CW::kFwdIncl + c, lane, 0), ep,
-                            fmaf(CA, Jc[c], CB[c]));
-        }
-        // causal carry into every wave, and the chunk-level anticausal aggregate
-        float jv[CT];
-#pragma unroll
-        for (int c = 0; c < CT; ++c) jv[c] = Jc[c];
-#pragma unroll
-        for (int v = 0; v < NWV; ++v) {
-            const float Av = s_A[v][lane];
-#pragma unroll
-            for (int c = 0; c < CT; ++c) {
-                s_Jin[v][c][lane] = jv[c];
-                jv[c] = fmaf(Av, jv[c], s_B[v][c][lane]);
-            }
-        }
-        float CP = 1.f, alpha[CT];
-#pragma unroll
-        for (int c = 0; c < CT; ++c) alpha[c] = 0.f;
-#pragma unroll
-        for (int v = NWV - 1; v >= 0; --v) {
-            const float Pv = s_P[v][lane], BQv = s_BQ[v][lane];
-#pragma unroll
-            for (int c = 0; c < CT; ++c)
-                alpha[c] = fmaf(Pv, alpha[c], fmaf(BQv, s_Jin[v][c][lane], s_BJ[v][c][lane]));
-            CP *= Pv;
-        }
-        float Kc[CT];
-#pragma unroll
-        for (int c = 0; c < CT; ++c) Kc[c] = 0.f;
-        if (chunk < a.G - 1 && valid) {
-            publish(carry_word<CT>(a, strip_base, chunk, CW::kBwdP, lane, 0), ep, CP);
-#pragma unroll
-            for (int c = 0; c < CT; ++c)
-                if (c < ncv) publish(carry_word<CT>(a, strip_base, chunk, CW::kBwdAlpha + c, lane, 0), ep, alpha[c]);
-            resolve_carry<CT>(a, carry_word<CT>, strip_base, lane, chunk, +1, CW::kBwdP,
-                              CW::kBwdAlpha, CW::kBwdIncl, ncv, Kc);
-        }
-        if (valid) {
-#pragma unroll
-            for (int c = 0; c < CT; ++c)
-                if (c < ncv)
-                    publish(carry_word<CT>(a, strip_base, chunk, CW::kBwdIncl + c, lane, 0), ep,
-                            fmaf(CP, Kc[c], alpha[c]));
-        }
-        // anticausal carry into every wave (K at the row after the wave's last row)
-        float kv[CT];
-#pragma unroll
-        for (int c = 0; c < CT; ++c) kv[c] = Kc[c];
-#pragma unroll
-        for (int v = NWV - 1; v >= 0; --v) {
-            const float Pv = s_P[v][lane], BQv = s_BQ[v][lane];
-#pragma unroll
-            for (int c = 0; c < CT; ++c) {
-                s_Kin[v][c][lane] = kv[c];
-                kv[c] = fmaf(Pv, kv[c], fmaf(BQv, s_Jin[v][c][lane], s_BJ[v][c][lane]));
-            }
-        }
-    }
+    if (wave == 0) chunk_carries<CT, NWV>(cctx, L, b, grp, strip, chunk, lane, valid, ncv);
     __syncthreads();
 
     float Jin[CT], Kin[CT];
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
-        Jin[c] = s_Jin[wave][c][lane];
-        Kin[c] = s_Kin[wave][c][lane];
+        Jin[c] = L.Jin[wave][c][lane];
+        Kin[c] = L.Kin[wave][c][lane];
     }
 
     // phase 3: causal values with the true carry, then the anticausal sweep and the store
@@ -762,7 +554,7 @@ size_t col_carry_words(int batch, int H, int W, int C) {
     const size_t G = (H + kMinChunkRows - 1) / kMinChunkRows;
     const size_t S = (W + kWave - 1) / kWave;
     const size_t NG = (C + ct - 1) / ct;
-    return static_cast<size_t>(batch) * NG * S * G * (2 + 4 * ct) * kWave;
+    return static_cast<size_t>(batch) * NG * S * G * carry_words_per_chunk(ct) * kWave;
 }
 
 int launch_col_pass(const ColPass& p, Ctx& ctx) {
@@ -817,18 +609,33 @@ __global__ void zero_kernel(uint4* p, size_t n16) {
         p[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
+__global__ void zero_bytes_kernel(unsigned char* p, size_t n) {
+    const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+    for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
+        p[i] = 0;
+}
+
 __global__ void copy_kernel(float* __restrict__ dst, const float* __restrict__ src, size_t n) {
     const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
     for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
         dst[i] = src[i];
 }
 
+// Clears `bytes` bytes at any alignment: 16-byte stores over the aligned middle, byte
+// stores over the unaligned head and tail.
 int launch_zero(void* ptr, size_t bytes, hipStream_t s) {
-    const size_t n16 = bytes / 16;
-    if (n16 == 0) return 0;
-    const size_t blocks = (n16 + 255) / 256;
-    const unsigned g = static_cast<unsigned>(blocks < 8192 ? blocks : 8192);
-    hipLaunchKernelGGL(zero_kernel, dim3(g), dim3(256), 0, s, static_cast<uint4*>(ptr), n16);
+    if (bytes == 0) return 0;
+    unsigned char* p = static_cast<unsigned char*>(ptr);
+    const size_t head = std::min<size_t>((16 - (reinterpret_cast<uintptr_t>(p) & 15u)) & 15u, bytes);
+    const size_t n16 = (bytes - head) / 16;
+    const size_t tail = bytes - head - n16 * 16;
+    if (n16) {
+        const size_t blocks = (n16 + 255) / 256;
+        const unsigned g = static_cast<unsigned>(blocks < 8192 ? blocks : 8192);
+        hipLaunchKernelGGL(zero_kernel, dim3(g), dim3(256), 0, s, reinterpret_cast<uint4*>(p + head), n16);
+    }
+    if (head) hipLaunchKernelGGL(zero_bytes_kernel, dim3(1), dim3(64), 0, s, p, head);
+    if (tail) hipLaunchKernelGGL(zero_bytes_kernel, dim3(1), dim3(64), 0, s, p + head + n16 * 16, tail);
     return hip_fail(hipGetLastError());
 }
 

@@ -52,6 +52,57 @@ struct ColPass {
     float lambda, step;
 };
 
+// Adjoint of one row pass (update-adjoint epilogue when gz is set).
+struct RowAdj {
+    const float* gk;
+    float gk_scale;
+    const float* f;
+    const float* d;
+    float* gout;
+    float* gd;
+    int C, H, W, batch;
+    float log2a;
+    float* gz;
+    const float* tgt;
+    const float* conf;
+    float* gt;
+    float* gc;
+    int Cc;
+    float lambda, step;
+    int last;
+};
+
+// Adjoint of one column pass.
+struct ColAdj {
+    const float* gk;
+    float gk_scale;
+    const float* f;
+    const float* d;
+    float* gout;
+    float* gd;
+    int C, H, W, batch;
+    float log2a;
+};
+
+// Guide gradient from the distance gradients.
+struct DistAdj {
+    const float* guide;
+    const float* dx;
+    const float* dy;
+    const float* gdx;
+    const float* gdy;
+    int ngy;
+    float* gg;
+    int Cg, H, W, batch;
+    float s2;
+};
+
+int launch_row_adjoint(const RowAdj& p, Ctx& ctx);
+int launch_col_adjoint(const ColAdj& p, Ctx& ctx);
+int launch_dist_adjoint(const DistAdj& p, Ctx& ctx);
+int col_adjoint_groups(int C);
+size_t col_adjoint_carry_words(int batch, int H, int W, int C);
+
 int launch_row_pass(const RowPass& p, Ctx& ctx);
 int launch_col_pass(const ColPass& p, Ctx& ctx);
 size_t col_carry_words(int batch, int H, int W, int C);
