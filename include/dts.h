@@ -96,6 +96,47 @@ int dts_solve_backward(const float* guide, int Cg, const float* target, const fl
                        float* grad_conf, float* grad_guide, void* workspace,
                        size_t workspace_bytes, void* stream);
 
+/* ---- Many uneven solves in one persistent launch ---- */
+
+/* One independent solve: device pointers, shape and parameters (1 <= T, 1 <= N <= 8,
+ * W <= 8192).  Layouts as above with batch 1. */
+typedef struct dts_problem {
+    const float* guide;
+    const float* target;
+    const float* conf;
+    float* out;
+    int H, W, Cg, Ct, Cc;
+    float sigma_s, sigma_r;
+    int filter_iters, solver_iters;
+} dts_problem;
+
+/* Filled by dts_batched_prepare, read by dts_solve_batched (host memory, plain data). */
+typedef struct dts_batched_plan {
+    int n, variant, n_phases, total_tiles, grid;
+    float lambda, step;
+    size_t workspace_bytes;
+    size_t off_inst, off_base, off_prefix, off_need, off_done;
+} dts_batched_plan;
+
+/* Launch shapes of the batched kernel: rows per wave of the column chunks and target
+ * channels per column group.  The autotuner of the Python package picks one. */
+int dts_batched_variant_count(void);
+int dts_batched_variant_info(int variant, int* rows_per_wave, int* group_channels);
+size_t dts_batched_workspace_bytes(const dts_problem* probs, int n, int variant);
+
+/* Writes the instance table and the tile schedule for `probs` (host array of n problems)
+ * into the workspace and waits for the copy on `stream`: call it outside graph capture.
+ * The problems' device buffers must stay valid while the plan is used. */
+int dts_batched_prepare(const dts_problem* probs, int n, float lambda, float step, int variant,
+                        void* workspace, size_t workspace_bytes, dts_batched_plan* plan, void* stream);
+
+/* Runs every planned solve (not in the paper; each instance is exactly what dts_solve
+ * computes): one small reset kernel and one persistent kernel whose workgroups take the
+ * row and column tiles of all instances in pass order, each tile waiting on its
+ * instance's earlier passes through device-side counters.  Allocates and copies nothing,
+ * so it can be captured into a HIP graph and replayed. */
+int dts_solve_batched(const dts_batched_plan* plan, void* workspace, void* stream);
+
 /* ---- The individual steps of the filter (each also runs inside the calls above) ---- */
 
 /* dts_distances -- transformed distances of the domain transform (Sec. 3.2, Eq. (8)-(9)):

@@ -40,6 +40,8 @@ __all__ = [
     "col_variants",
     "tune_col_variant",
     "tune_row_segment",
+    "batched_variants",
+    "BatchedSolver",
     "EXPORTED_SYMBOLS",
 ]
 
@@ -73,6 +75,11 @@ EXPORTED_SYMBOLS = (
     "dts_col_variant_info",
     "dts_tune_col_variant",
     "dts_tune_row_segment",
+    "dts_batched_variant_count",
+    "dts_batched_variant_info",
+    "dts_batched_workspace_bytes",
+    "dts_batched_prepare",
+    "dts_solve_batched",
 )
 
 
@@ -90,6 +97,42 @@ class _Params(ctypes.Structure):
         ("solver_iters", ctypes.c_int),
         ("lam", ctypes.c_float),
         ("step", ctypes.c_float),
+    ]
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [
+        ("guide", ctypes.c_void_p),
+        ("target", ctypes.c_void_p),
+        ("conf", ctypes.c_void_p),
+        ("out", ctypes.c_void_p),
+        ("H", ctypes.c_int),
+        ("W", ctypes.c_int),
+        ("Cg", ctypes.c_int),
+        ("Ct", ctypes.c_int),
+        ("Cc", ctypes.c_int),
+        ("sigma_s", ctypes.c_float),
+        ("sigma_r", ctypes.c_float),
+        ("filter_iters", ctypes.c_int),
+        ("solver_iters", ctypes.c_int),
+    ]
+
+
+class _BatchedPlan(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int),
+        ("variant", ctypes.c_int),
+        ("n_phases", ctypes.c_int),
+        ("total_tiles", ctypes.c_int),
+        ("grid", ctypes.c_int),
+        ("lam", ctypes.c_float),
+        ("step", ctypes.c_float),
+        ("workspace_bytes", ctypes.c_size_t),
+        ("off_inst", ctypes.c_size_t),
+        ("off_base", ctypes.c_size_t),
+        ("off_prefix", ctypes.c_size_t),
+        ("off_need", ctypes.c_size_t),
+        ("off_done", ctypes.c_size_t),
     ]
 
 
@@ -166,6 +209,18 @@ def library():
     lib.dts_tune_col_variant.restype = i
     lib.dts_tune_row_segment.argtypes = [i]
     lib.dts_tune_row_segment.restype = i
+    PP = ctypes.POINTER(_Problem)
+    BP = ctypes.POINTER(_BatchedPlan)
+    lib.dts_batched_variant_count.argtypes = []
+    lib.dts_batched_variant_count.restype = i
+    lib.dts_batched_variant_info.argtypes = [i, ip, ip]
+    lib.dts_batched_variant_info.restype = i
+    lib.dts_batched_workspace_bytes.argtypes = [PP, i, i]
+    lib.dts_batched_workspace_bytes.restype = sz
+    lib.dts_batched_prepare.argtypes = [PP, i, f, f, i, vp, sz, BP, vp]
+    lib.dts_batched_prepare.restype = i
+    lib.dts_solve_batched.argtypes = [BP, vp, vp]
+    lib.dts_solve_batched.restype = i
     lib.dts_profile_enable.argtypes = [i]
     lib.dts_profile_enable.restype = i
     lib.dts_profile_read.argtypes = [ctypes.POINTER(_KernelStat), i]
@@ -305,6 +360,92 @@ def tune_col_variant(group_channels, variant):
 
 def tune_row_segment(pixels_per_lane):
     _check(library().dts_tune_row_segment(int(pixels_per_lane)), "dts_tune_row_segment")
+
+
+def batched_variants():
+    """[(index, rows_per_wave, group_channels)] of the batched kernel's shapes."""
+    lib = library()
+    out = []
+    for v in range(lib.dts_batched_variant_count()):
+        r, ct = ctypes.c_int(), ctypes.c_int()
+        _check(lib.dts_batched_variant_info(v, ctypes.byref(r), ctypes.byref(ct)),
+               "dts_batched_variant_info")
+        out.append((v, r.value, ct.value))
+    return out
+
+
+class BatchedSolver:
+    """Many independent solves of uneven size in one persistent launch.
+
+    ``problems`` is a list of dicts with GPU tensors ``guide`` [Cg][H][W], ``target``
+    [Ct][H][W], ``conf`` [Cc][H][W] and floats ``sigma_s``, ``sigma_r`` plus ints
+    ``filter_iters`` (default 3) and ``solver_iters`` (default 10).  Outputs are allocated
+    here (``self.outputs``).  ``run()`` enqueues the solve on the current stream and is
+    capturable; ``variant=None`` asks the autotuner."""
+
+    def __init__(self, problems, lam=0.99, step=0.99, variant=None, tune_iters=2):
+        self.problems = []
+        for q in problems:
+            g = _as4d(q["guide"], "guide")[0]
+            t = _as4d(q["target"], "target")[0]
+            c = _as4d(q["conf"], "conf")[0]
+            if g.shape[1:] != t.shape[1:] or c.shape[1:] != t.shape[1:]:
+                raise ValueError("guide/target/conf disagree in image size")
+            self.problems.append(dict(guide=g, target=t, conf=c, sigma_s=float(q["sigma_s"]),
+                                      sigma_r=float(q["sigma_r"]),
+                                      filter_iters=int(q.get("filter_iters", 3)),
+                                      solver_iters=int(q.get("solver_iters", 10))))
+        self.lam, self.step = float(lam), float(step)
+        self.outputs = [torch.empty_like(q["target"]) for q in self.problems]
+        if variant is None:
+            from . import autotune
+            variant = autotune.batched_variant(self, iters=tune_iters)
+        self._prepare(int(variant))
+
+    def _ctable(self):
+        arr = (_Problem * len(self.problems))()
+        for k, (q, o) in enumerate(zip(self.problems, self.outputs)):
+            Cg, H, W = q["guide"].shape
+            arr[k] = _Problem(q["guide"].data_ptr(), q["target"].data_ptr(), q["conf"].data_ptr(),
+                              o.data_ptr(), H, W, Cg, q["target"].shape[0], q["conf"].shape[0],
+                              q["sigma_s"], q["sigma_r"], q["filter_iters"], q["solver_iters"])
+        return arr
+
+    def _prepare(self, variant):
+        lib = library()
+        table = self._ctable()
+        nbytes = lib.dts_batched_workspace_bytes(table, len(self.problems), variant)
+        if nbytes == 0:
+            raise DTSError(DTS_EINVAL, "dts_batched_workspace_bytes")
+        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8,
+                                     device=self.problems[0]["target"].device)
+        self.plan = _BatchedPlan()
+        _check(lib.dts_batched_prepare(table, len(self.problems), self.lam, self.step, variant,
+                                       _ptr(self.workspace), self.workspace.numel(),
+                                       ctypes.byref(self.plan), _stream()),
+               "dts_batched_prepare")
+        self.variant = variant
+
+    def run(self):
+        _check(library().dts_solve_batched(ctypes.byref(self.plan), _ptr(self.workspace), _stream()),
+               "dts_solve_batched")
+        return self.outputs
+
+    def status(self):
+        return workspace_status(self.workspace)
+
+    def capture(self):
+        """A torch.cuda.CUDAGraph (a HIP graph) holding one run(); replay() repeats it."""
+        graph = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            self.run()  # warm-up outside the graph on the capture stream
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph):
+            self.run()
+        return graph
 
 
 def workspace_status(ws):

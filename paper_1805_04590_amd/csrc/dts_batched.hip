@@ -1,0 +1,451 @@
+// Many independent solves of uneven size in one persistent launch (not in the paper;
+// every instance is the Eq. (3) gradient descent with the recursive domain-transform
+// filter of Sec. 3.2, exactly as dts_solve runs it).
+//
+// Work is a list of tiles in phase-major order: phase p is the p-th pass of every
+// instance (the row and column passes of each filter iteration, solver iteration after
+// solver iteration), and within a phase the tiles of instance 0, then instance 1, ...
+// A row tile is one image row; a column tile is one chunk of one 64-column strip (chunks
+// of a strip are consecutive).  Workgroups of a persistent grid that fits on the device
+// at once take tiles in order from an atomic ticket counter.  A tile of phase p of
+// instance i waits until all tiles of the instance's earlier phases are done (a
+// per-instance counter, released after the tile's stores and acquired before its
+// loads); chunks of one strip exchange carries through epoch-tagged words.  Every wait
+// is on an earlier ticket or on a chunk of the same strip, whose tickets are consecutive
+// and fit in the grid, so the launch always completes.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "../../include/dts.h"
+#include "dts_batched.hpp"
+#include "dts_chunks.hpp"
+#include "dts_device.hpp"
+#include "dts_internal.hpp"
+#include "dts_tiles.hpp"
+
+namespace dts {
+
+__device__ __forceinline__ int upper_index(const int* v, int n, int x) {
+    // largest j in [0, n) with v[j] <= x (v sorted ascending, v[0] <= x)
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (v[mid] <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int S>
+__device__ __forceinline__ void row_tile_any(const RowArgs& ra, bool dist, int y) {
+    if (dist) row_tile<S, true>(ra, y, 0);
+    else row_tile<S, false>(ra, y, 0);
+}
+
+template <int R, int CTM>
+__global__ void __launch_bounds__(kWave * kBatchWaves) batched_kernel(BatchArgs a) {
+    __shared__ ChunkLds<CTM, kBatchWaves> L;
+    __shared__ int s_t;
+    const unsigned launch = __hip_atomic_load(const_cast<unsigned*>(a.launch), __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+    while (true) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_t = static_cast<int>(atomicAdd(a.ticket, 1u));
+        __syncthreads();
+        const int t = __builtin_amdgcn_readfirstlane(s_t);
+        if (t >= a.total) break;
+        const int p = upper_index(a.phase_base, a.n_phases + 1, t);
+        const int local = t - a.phase_base[p];
+        const int* pre = a.phase_prefix + static_cast<size_t>(p) * (a.n + 1);
+        const int i = upper_index(pre, a.n + 1, local);
+        const int tile = local - pre[i];
+        const BInst& I = a.inst[i];
+
+        // wait until the instance's earlier phases are complete
+        if (threadIdx.x == 0) {
+            const unsigned need = static_cast<unsigned>(a.need[static_cast<size_t>(p) * a.n + i]);
+            int spins = 0, backoff = 1;
+            while (__hip_atomic_load(&a.done[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                spins += backoff;
+                if (spins > kSpinLimit) {
+                    flag_error(a.status, kErrSpinTimeout);
+                    break;
+                }
+                for (int q = 0; q < backoff; ++q) __builtin_amdgcn_s_sleep(2);
+                backoff = backoff < 32 ? backoff * 2 : 32;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        __syncthreads();
+
+        const int per_iter = 2 * I.N;
+        const int k = p / per_iter;
+        const int q = p % per_iter;
+        const int fi = q / 2 + 1;  // filter iteration 1..N
+        const float* zk = (k == 0) ? I.target : I.out;
+        if ((q & 1) == 0) {
+            RowArgs ra;
+            ra.src = (fi == 1) ? zk : I.tmp;
+            ra.dst = I.tmp;
+            ra.d = I.dx;
+            ra.guide = I.guide;
+            ra.dx_out = I.dx;
+            ra.dy_out = I.dy;
+            ra.Cg = I.Cg;
+            ra.s2 = I.s2;
+            ra.C = I.Ct;
+            ra.H = I.H;
+            ra.W = I.W;
+            ra.log2a = I.log2a[fi - 1];
+            const bool dist = (k == 0 && fi == 1);
+            if (I.row_S == 4) row_tile_any<4>(ra, dist, tile);
+            else if (I.row_S == 8) row_tile_any<8>(ra, dist, tile);
+            else row_tile_any<16>(ra, dist, tile);
+        } else {
+            ColArgs ca;
+            const bool epi = (fi == I.N);
+            ca.src = I.tmp;
+            ca.dst = epi ? I.out : I.tmp;
+            ca.d = I.dy;
+            ca.C = I.Ct;
+            ca.H = I.H;
+            ca.W = I.W;
+            ca.log2a = I.log2a[fi - 1];
+            ca.G = I.G;
+            ca.S = I.S;
+            ca.NG = I.NG;
+            ca.batch = 1;
+            ca.groups = 1;
+            ca.carry = I.carry;
+            ca.epoch = launch * static_cast<unsigned>(a.n_phases + 1) + static_cast<unsigned>(p) + 1u;
+            ca.status = a.status;
+            ca.zk = zk;
+            ca.tgt = I.target;
+            ca.conf = I.conf;
+            ca.Cc = I.Cc;
+            ca.dst2 = nullptr;
+            ca.lambda = a.lambda;
+            ca.step = a.step;
+            const CarryCtx cctx{ca.carry, ca.epoch, ca.status, ca.G, ca.S, ca.NG};
+            const int chunk = tile % I.G;
+            const int rest = tile / I.G;
+            const int strip = rest % I.S;
+            const int grp = rest / I.S;
+            if (epi) col_tile<CTM, R, kBatchWaves, true>(ca, cctx, L, chunk, strip, grp, 0);
+            else col_tile<CTM, R, kBatchWaves, false>(ca, cctx, L, chunk, strip, grp, 0);
+        }
+
+        // publish completion: every wave's stores precede the barrier, the release makes
+        // them visible device-wide before the counter moves
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __hip_atomic_fetch_add(&a.done[i], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+__global__ void batched_reset_kernel(unsigned* ticket, unsigned* launch, unsigned* done, int n, int* status) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) done[i] = 0u;
+    if (threadIdx.x == 0) {
+        *ticket = 0u;
+        *launch = *launch + 1u;
+        *status = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Variants (chosen by the autotuner): rows per wave R and channels per column group CTM
+// ---------------------------------------------------------------------------------------
+struct BatchVariant {
+    int R, ctm;
+    void (*launch)(const BatchArgs&, unsigned, hipStream_t);
+    int (*capacity)();
+};
+
+template <int R, int CTM>
+static void batched_launch_v(const BatchArgs& a, unsigned grid, hipStream_t s) {
+    hipLaunchKernelGGL((batched_kernel<R, CTM>), dim3(grid), dim3(kWave * kBatchWaves), 0, s, a);
+}
+
+template <int R, int CTM>
+static int batched_capacity_v() {
+    static int cached[64] = {0};
+    static std::mutex mu;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    std::lock_guard<std::mutex> lock(mu);
+    if (cached[dev] == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_kernel<R, CTM>,
+                                                         kWave * kBatchWaves, 0) != hipSuccess)
+            return 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return 0;
+        cached[dev] = per_cu * cus;
+    }
+    return cached[dev];
+}
+
+static const BatchVariant kBatchVariants[] = {
+    {16, 1, batched_launch_v<16, 1>, batched_capacity_v<16, 1>},
+    {32, 1, batched_launch_v<32, 1>, batched_capacity_v<32, 1>},
+    {16, 3, batched_launch_v<16, 3>, batched_capacity_v<16, 3>},
+    {8, 3, batched_launch_v<8, 3>, batched_capacity_v<8, 3>},
+};
+constexpr int kNumBatchVariants = sizeof(kBatchVariants) / sizeof(kBatchVariants[0]);
+
+int num_batch_variants() { return kNumBatchVariants; }
+
+int batch_variant_info(int v, int* rows_per_wave, int* group_channels) {
+    if (v < 0 || v >= kNumBatchVariants) return DTS_EINVAL;
+    *rows_per_wave = kBatchVariants[v].R;
+    *group_channels = kBatchVariants[v].ctm;
+    return DTS_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// Host planning
+// ---------------------------------------------------------------------------------------
+namespace {
+constexpr size_t kBAlign = 256;
+size_t bal(size_t v) { return (v + kBAlign - 1) / kBAlign * kBAlign; }
+
+struct Geo {
+    int row_S, G, S, NG, rows_tiles, col_tiles, phases;
+    size_t dx, dy, tmp, carry, carry_bytes;
+};
+}  // namespace
+
+static int check_problem(const dts_problem& q) {
+    if (!q.guide || !q.target || !q.conf || !q.out) return DTS_EINVAL;
+    if (q.H < 1 || q.W < 1 || q.Cg < 1 || q.Cg > DTS_MAX_CHANNELS || q.Ct < 1 || q.Ct > DTS_MAX_CHANNELS)
+        return DTS_EINVAL;
+    if (q.Cc != 1 && q.Cc != q.Ct) return DTS_EINVAL;
+    if (!(std::isfinite(q.sigma_s) && q.sigma_s > 0) || !(std::isfinite(q.sigma_r) && q.sigma_r > 0))
+        return DTS_EINVAL;
+    if (q.filter_iters < 1 || q.solver_iters < 1) return DTS_EINVAL;
+    if (q.filter_iters > kBatchMaxN || q.W > kBatchMaxWidth || q.H > DTS_MAX_HEIGHT) return DTS_ENOTSUP;
+    if ((static_cast<size_t>(q.H) + 64) * static_cast<size_t>(q.W) * 4 >= (static_cast<size_t>(1) << 31))
+        return DTS_ENOTSUP;
+    return DTS_OK;
+}
+
+static Geo geometry(const dts_problem& q, const BatchVariant& v) {
+    Geo g{};
+    g.row_S = q.W > 4096 ? 16 : q.W > 2048 ? 8 : 4;
+    const int rows = v.R * kBatchWaves;
+    g.G = (q.H + rows - 1) / rows;
+    g.S = (q.W + kWave - 1) / kWave;
+    g.NG = (q.Ct + v.ctm - 1) / v.ctm;
+    g.rows_tiles = q.H;
+    g.col_tiles = g.NG * g.S * g.G;
+    g.phases = 2 * q.filter_iters * q.solver_iters;
+    return g;
+}
+
+struct BatchLayout {
+    size_t hdr = 0, inst = 0, base = 0, prefix = 0, need = 0, done = 0, bufs = 0, total = 0;
+    int n_phases = 0, total_tiles = 0, max_G = 0;
+    std::vector<Geo> geo;
+};
+
+static int make_batch_layout(const dts_problem* probs, int n, const BatchVariant& v, BatchLayout& L) {
+    L.geo.resize(n);
+    long long tiles = 0;
+    for (int i = 0; i < n; ++i) {
+        int rc = check_problem(probs[i]);
+        if (rc) return rc;
+        L.geo[i] = geometry(probs[i], v);
+        L.n_phases = std::max(L.n_phases, L.geo[i].phases);
+        L.max_G = std::max(L.max_G, L.geo[i].G);
+        tiles += static_cast<long long>(probs[i].filter_iters) * probs[i].solver_iters *
+                 (L.geo[i].rows_tiles + L.geo[i].col_tiles);
+    }
+    if (tiles > (1LL << 30)) return DTS_ENOTSUP;
+    L.total_tiles = static_cast<int>(tiles);
+    size_t off = 256;  // header: status, ticket, launch
+    L.inst = off;
+    off = bal(off + sizeof(BInst) * n);
+    L.base = off;
+    off = bal(off + sizeof(int) * (L.n_phases + 1));
+    L.prefix = off;
+    off = bal(off + sizeof(int) * static_cast<size_t>(L.n_phases) * (n + 1));
+    L.need = off;
+    off = bal(off + sizeof(int) * static_cast<size_t>(L.n_phases) * n);
+    L.done = off;
+    off = bal(off + sizeof(unsigned) * n);
+    L.bufs = off;
+    for (int i = 0; i < n; ++i) {
+        const dts_problem& q = probs[i];
+        Geo& g = L.geo[i];
+        const size_t plane = static_cast<size_t>(q.H) * q.W * sizeof(float);
+        g.dx = off;
+        off = bal(off + plane);
+        g.dy = off;
+        off = bal(off + plane);
+        g.tmp = off;
+        off = bal(off + plane * q.Ct);
+        g.carry = off;
+        g.carry_bytes = bal(static_cast<size_t>(g.NG) * g.S * g.G * carry_words_per_chunk(v.ctm) * kWave *
+                            sizeof(unsigned long long));
+        off += g.carry_bytes;
+    }
+    L.total = off;
+    return DTS_OK;
+}
+
+constexpr size_t kBTicket = 64, kBLaunch = 128;
+
+}  // namespace dts
+
+using namespace dts;
+
+extern "C" {
+
+int dts_batched_variant_count(void) { return num_batch_variants(); }
+
+int dts_batched_variant_info(int variant, int* rows_per_wave, int* group_channels) {
+    if (!rows_per_wave || !group_channels) return DTS_EINVAL;
+    return batch_variant_info(variant, rows_per_wave, group_channels);
+}
+
+size_t dts_batched_workspace_bytes(const dts_problem* probs, int n, int variant) {
+    if (!probs || n < 1 || variant < 0 || variant >= kNumBatchVariants) return 0;
+    BatchLayout L;
+    if (make_batch_layout(probs, n, kBatchVariants[variant], L)) return 0;
+    return L.total;
+}
+
+int dts_batched_prepare(const dts_problem* probs, int n, float lambda, float step, int variant,
+                        void* workspace, size_t workspace_bytes, dts_batched_plan* plan, void* stream) {
+    if (!probs || n < 1 || !plan || !std::isfinite(lambda) || !std::isfinite(step)) return DTS_EINVAL;
+    if (variant < 0 || variant >= kNumBatchVariants) return DTS_EINVAL;
+    const BatchVariant& v = kBatchVariants[variant];
+    BatchLayout L;
+    int rc = make_batch_layout(probs, n, v, L);
+    if (rc) return rc;
+    if (!workspace || workspace_bytes < L.total || (reinterpret_cast<uintptr_t>(workspace) & 255u))
+        return DTS_EWORKSPACE;
+    const int cap = v.capacity();
+    if (cap <= 0) return hip_fail(hipErrorNoDevice);
+    if (L.max_G > cap) return DTS_ENOTSUP;
+    char* base = static_cast<char*>(workspace);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    // tables, built on the host and copied once
+    std::vector<char> img(L.bufs - L.inst, 0);
+    auto at = [&](size_t off) { return img.data() + (off - L.inst); };
+    BInst* inst = reinterpret_cast<BInst*>(at(L.inst));
+    for (int i = 0; i < n; ++i) {
+        const dts_problem& q = probs[i];
+        const Geo& g = L.geo[i];
+        BInst& I = inst[i];
+        I.guide = q.guide;
+        I.target = q.target;
+        I.conf = q.conf;
+        I.out = q.out;
+        I.dx = reinterpret_cast<float*>(base + g.dx);
+        I.dy = reinterpret_cast<float*>(base + g.dy);
+        I.tmp = reinterpret_cast<float*>(base + g.tmp);
+        I.carry = reinterpret_cast<unsigned long long*>(base + g.carry);
+        I.H = q.H;
+        I.W = q.W;
+        I.Cg = q.Cg;
+        I.Ct = q.Ct;
+        I.Cc = q.Cc;
+        I.N = q.filter_iters;
+        I.T = q.solver_iters;
+        I.row_S = g.row_S;
+        I.G = g.G;
+        I.S = g.S;
+        I.NG = g.NG;
+        const double r = static_cast<double>(q.sigma_s) / q.sigma_r;
+        I.s2 = static_cast<float>(r * r);
+        for (int f = 0; f < kBatchMaxN; ++f) {
+            if (f < q.filter_iters) {
+                const double sh = q.sigma_s * std::sqrt(3.0) * std::ldexp(1.0, q.filter_iters - 1 - f) /
+                                  std::sqrt(std::ldexp(1.0, 2 * q.filter_iters) - 1.0);
+                I.log2a[f] = static_cast<float>(-std::sqrt(2.0) / sh / std::log(2.0));
+            } else {
+                I.log2a[f] = 0.f;
+            }
+        }
+    }
+    int* pbase = reinterpret_cast<int*>(at(L.base));
+    int* pre = reinterpret_cast<int*>(at(L.prefix));
+    int* need = reinterpret_cast<int*>(at(L.need));
+    std::vector<long long> done_before(n, 0);
+    long long acc = 0;
+    for (int p = 0; p < L.n_phases; ++p) {
+        pbase[p] = static_cast<int>(acc);
+        int local = 0;
+        for (int i = 0; i < n; ++i) {
+            const Geo& g = L.geo[i];
+            pre[static_cast<size_t>(p) * (n + 1) + i] = local;
+            need[static_cast<size_t>(p) * n + i] = static_cast<int>(done_before[i]);
+            int tiles = 0;
+            if (p < g.phases) tiles = (p & 1) ? g.col_tiles : g.rows_tiles;
+            local += tiles;
+            done_before[i] += tiles;
+        }
+        pre[static_cast<size_t>(p) * (n + 1) + n] = local;
+        acc += local;
+    }
+    pbase[L.n_phases] = static_cast<int>(acc);
+    if ((rc = launch_zero(base, L.inst, s))) return rc;
+    if ((rc = hip_fail(hipMemcpyAsync(base + L.inst, img.data(), img.size(), hipMemcpyHostToDevice, s))))
+        return rc;
+    for (int i = 0; i < n; ++i)
+        if ((rc = launch_zero(base + L.geo[i].carry, L.geo[i].carry_bytes, s))) return rc;
+    if ((rc = hip_fail(hipStreamSynchronize(s)))) return rc;  // img is host memory
+
+    memset(plan, 0, sizeof(*plan));
+    plan->n = n;
+    plan->variant = variant;
+    plan->n_phases = L.n_phases;
+    plan->total_tiles = L.total_tiles;
+    plan->grid = std::min(cap, L.total_tiles);
+    plan->workspace_bytes = L.total;
+    plan->off_inst = L.inst;
+    plan->off_base = L.base;
+    plan->off_prefix = L.prefix;
+    plan->off_need = L.need;
+    plan->off_done = L.done;
+    plan->lambda = lambda;
+    plan->step = step;
+    return DTS_OK;
+}
+
+int dts_solve_batched(const dts_batched_plan* plan, void* workspace, void* stream) {
+    if (!plan || !workspace || plan->n < 1 || plan->variant < 0 || plan->variant >= kNumBatchVariants)
+        return DTS_EINVAL;
+    char* base = static_cast<char*>(workspace);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    BatchArgs a;
+    a.inst = reinterpret_cast<const BInst*>(base + plan->off_inst);
+    a.phase_base = reinterpret_cast<const int*>(base + plan->off_base);
+    a.phase_prefix = reinterpret_cast<const int*>(base + plan->off_prefix);
+    a.need = reinterpret_cast<const int*>(base + plan->off_need);
+    a.done = reinterpret_cast<unsigned*>(base + plan->off_done);
+    a.ticket = reinterpret_cast<unsigned*>(base + kBTicket);
+    a.launch = reinterpret_cast<const unsigned*>(base + kBLaunch);
+    a.status = reinterpret_cast<int*>(base);
+    a.n = plan->n;
+    a.n_phases = plan->n_phases;
+    a.total = plan->total_tiles;
+    a.lambda = plan->lambda;
+    a.step = plan->step;
+    hipLaunchKernelGGL(batched_reset_kernel, dim3(1), dim3(256), 0, s, a.ticket,
+                       reinterpret_cast<unsigned*>(base + kBLaunch), a.done, a.n, a.status);
+    int rc = hip_fail(hipGetLastError());
+    if (rc) return rc;
+    ProfScope prof("batched_solve", 0.0, s);
+    kBatchVariants[plan->variant].launch(a, static_cast<unsigned>(plan->grid), s);
+    return hip_fail(hipGetLastError());
+}
+
+}  // extern "C"

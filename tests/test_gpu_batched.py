@@ -1,0 +1,114 @@
+"""Batched persistent solve (dts_solve_batched) against the oracle and the single solve,
+graph capture and replay, and the autotuner."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import dts_inputs
+import oracle
+import paper_1805_04590_amd as dts
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def small_set(seed0=900, n=6, T=3):
+    rng = np.random.default_rng(seed0)
+    cases = []
+    for i in range(n):
+        H = int(rng.integers(20, 300))
+        W = int(rng.integers(30, 700))
+        Cg = int(rng.choice([1, 3, 8, 16]))
+        Ct = int(rng.integers(1, 4))
+        Cc = int(rng.choice([1, Ct]))
+        case = dts_inputs.random_case(seed0 + 10 + i, H, W, Cg, Ct, Cc=Cc,
+                                      sigma_s=float(rng.uniform(4, 32)),
+                                      sigma_r=float(rng.uniform(0.05, 0.3)), T=T)
+        cases.append(case)
+    return cases
+
+
+def problems_of(cases):
+    return [dict(guide=dev(c["guide"]), target=dev(c["target"]), conf=dev(c["conf"]),
+                 sigma_s=c["sigma_s"], sigma_r=c["sigma_r"], filter_iters=3,
+                 solver_iters=c["solver_iters"]) for c in cases]
+
+
+@pytest.mark.parametrize("variant", range(4))
+def test_batched_matches_oracle_and_single(variant):
+    cases = small_set()
+    print("CASE batched variant", variant, [c["name"] for c in cases], flush=True)
+    probs = problems_of(cases)
+    bs = dts.BatchedSolver(probs, variant=variant)
+    outs = bs.run()
+    torch.cuda.synchronize()
+    bs.status()
+    for c, q, o in zip(cases, probs, outs):
+        single = dts.solve(q["guide"], q["target"], q["conf"], c["sigma_s"], c["sigma_r"], 3,
+                           c["solver_iters"])
+        ref = oracle.solve(c["guide"], c["target"], c["conf"], c["sigma_s"], c["sigma_r"], 3,
+                           c["solver_iters"])
+        got = o.cpu().numpy()
+        assert np.abs(got - ref).max() <= 1e-4, c["name"]
+        assert np.abs(got - single.cpu().numpy()).max() <= 1e-5, c["name"]
+
+
+def test_graph_replays_match_eager():
+    cases = small_set(seed0=950, n=5, T=2)
+    print("CASE batched graph", flush=True)
+    probs = problems_of(cases)
+    bs = dts.BatchedSolver(probs, variant=0)
+    eager = [o.clone() for o in bs.run()]
+    torch.cuda.synchronize()
+    graph = bs.capture()
+    for rep in range(4):
+        for o in bs.outputs:
+            o.fill_(-1.0)  # eager work between replays
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        bs.status()
+        for e, o in zip(eager, bs.outputs):
+            assert torch.equal(e, o), rep
+
+
+def test_autotuner_picks_and_caches(tmp_path):
+    os.environ["DTS_TUNE_CACHE"] = str(tmp_path / "tune.json")
+    try:
+        cases = small_set(seed0=970, n=4, T=2)
+        probs = problems_of(cases)
+        bs = dts.BatchedSolver(probs)  # variant=None -> autotune
+        assert 0 <= bs.variant < len(dts.batched_variants())
+        assert (tmp_path / "tune.json").exists()
+        bs2 = dts.BatchedSolver(probs)
+        assert bs2.variant == bs.variant
+        ref = oracle.solve(cases[0]["guide"], cases[0]["target"], cases[0]["conf"],
+                           cases[0]["sigma_s"], cases[0]["sigma_r"], 3, 2)
+        out = bs2.run()[0]
+        torch.cuda.synchronize()
+        assert np.abs(out.cpu().numpy() - ref).max() <= 1e-4
+    finally:
+        del os.environ["DTS_TUNE_CACHE"]
+
+
+def test_config4_full_matches_single_solves():
+    cases = dts_inputs.config4()
+    print("CASE config 4 (64 uneven solves)", flush=True)
+    probs = problems_of(cases)
+    bs = dts.BatchedSolver(probs, variant=0)
+    outs = bs.run()
+    torch.cuda.synchronize()
+    bs.status()
+    for i, (c, q, o) in enumerate(zip(cases, probs, outs)):
+        single = dts.solve(q["guide"], q["target"], q["conf"], c["sigma_s"], c["sigma_r"], 3, 10)
+        assert (o - single).abs().max().item() <= 1e-5, c["name"]
+    # a few instances against the FP64 oracle
+    for i in (0, 17, 63):
+        c = cases[i]
+        ref = oracle.solve(c["guide"], c["target"], c["conf"], c["sigma_s"], c["sigma_r"], 3, 10)
+        assert np.abs(outs[i].cpu().numpy() - ref).max() <= 1e-4, c["name"]
