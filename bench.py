@@ -32,6 +32,8 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=512,
                     help="rows of the workload the CPU oracle baseline solves (0 = skip)")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel timing run")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched (64 uneven solves) and forward+backward legs")
     return ap.parse_args()
 
 
@@ -61,6 +63,108 @@ def cpu_baseline(rows):
                         f"{dt:.1f} s; elementwise NumPy runs on one core "
                         f"(BLAS pool {threads} threads unused)"),
                 seconds=dt)
+
+
+def timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def batched_leg(steps, warmup):
+    """64 uneven solves: one graph-captured persistent launch against the same solves
+    run one by one through dts_solve (workspaces preallocated)."""
+    import ctypes
+
+    import torch
+
+    import dts_inputs
+    import paper_1805_04590_amd as dts
+
+    cases = dts_inputs.config4()
+    dev = torch.device("cuda:0")
+    probs = [dict(guide=torch.from_numpy(c["guide"]).to(dev), target=torch.from_numpy(c["target"]).to(dev),
+                  conf=torch.from_numpy(c["conf"]).to(dev), sigma_s=c["sigma_s"], sigma_r=c["sigma_r"],
+                  filter_iters=3, solver_iters=10) for c in cases]
+    px = sum(c["target"].shape[1] * c["target"].shape[2] for c in cases)
+    bs = dts.BatchedSolver(probs)  # autotuned variant
+    graph = bs.capture()
+    ms_b = timed(graph.replay, steps, warmup)
+    bs.status()
+    outs = [torch.empty_like(q["target"]) for q in probs]
+    wss = []
+    for q in probs:
+        Ct, H, W = q["target"].shape
+        p = dts.Params(q["sigma_s"], q["sigma_r"], 3, 10).c()
+        wss.append(torch.empty(dts.library().dts_solve_workspace_bytes(1, H, W, Ct, ctypes.byref(p)),
+                               dtype=torch.uint8, device=dev))
+
+    def seq():
+        for q, o, w in zip(probs, outs, wss):
+            dts.solve(q["guide"], q["target"], q["conf"], q["sigma_s"], q["sigma_r"], 3, 10,
+                      out=o[None], workspace=w)
+
+    ms_s = timed(seq, steps, warmup)
+    err = max((o - b).abs().max().item() for o, b in zip(outs, bs.outputs))
+    return dict(workload="64 uneven solves 320-1920 x 240-1080, Cg in {1,3,8,16}, Ct 1-3, T=10",
+                pixels=px, variant=bs.variant, batched_ms=round(ms_b, 3),
+                batched_mpix_s=round(px / ms_b / 1e3, 1), sequential_ms=round(ms_s, 3),
+                sequential_mpix_s=round(px / ms_s / 1e3, 1), speedup=round(ms_s / ms_b, 3),
+                max_abs_diff=err)
+
+
+def fwd_bwd_leg(steps, warmup):
+    """Batch of 8 1024x1024 RGB -> 3-channel solves, T=15: forward with checkpoints alone,
+    and forward + hand-written adjoint for the loss sum((z - r)^2)."""
+    import ctypes
+
+    import torch
+
+    import dts_inputs
+    import paper_1805_04590_amd as dts
+
+    c = dts_inputs.config5()
+    dev = torch.device("cuda:0")
+    g = torch.from_numpy(c["guide"]).to(dev)
+    t = torch.from_numpy(c["target"]).to(dev)
+    cf = torch.from_numpy(c["conf"]).to(dev)
+    r = torch.from_numpy(c["ref"]).to(dev)
+    B, Ct, H, W = t.shape
+    T = c["solver_iters"]
+    p = dts.Params(c["sigma_s"], c["sigma_r"], 3, T).c()
+    ws = torch.empty(dts.library().dts_solve_workspace_bytes(B, H, W, Ct, ctypes.byref(p)),
+                     dtype=torch.uint8, device=dev)
+    wsb = torch.empty(dts.library().dts_solve_backward_workspace_bytes(B, H, W, g.shape[1], Ct,
+                                                                       ctypes.byref(p)),
+                      dtype=torch.uint8, device=dev)
+    out = torch.empty_like(t)
+    state = {}
+
+    def fwd():
+        state["z"], state["ck"] = dts.solve(g, t, cf, c["sigma_s"], c["sigma_r"], 3, T,
+                                            checkpoints=True, out=out, workspace=ws)
+
+    def fwd_bwd():
+        fwd()
+        go = 2.0 * (state["z"] - r)
+        dts.solve_backward(g, t, cf, state["ck"], go, c["sigma_s"], c["sigma_r"], 3, T,
+                           workspace=wsb)
+
+    ms_f = timed(fwd, steps, warmup)
+    ms_fb = timed(fwd_bwd, steps, warmup)
+    px = B * H * W
+    return dict(workload="8 x 1024x1024 RGB -> 3 channels, T=15, loss sum((z-r)^2)", pixels=px,
+                fwd_ms=round(ms_f, 3), fwd_mpix_s=round(px / ms_f / 1e3, 1),
+                fwd_bwd_ms=round(ms_fb, 3), fwd_bwd_mpix_s=round(px / ms_fb / 1e3, 1),
+                fwd_bwd_over_fwd=round(ms_fb / ms_f, 3))
 
 
 def main():
@@ -146,6 +250,18 @@ def main():
                         bytes_per_launch=s["bytes_per_launch"], avg_us=round(s["avg_ms"] * 1e3, 2))
         log("  " + json.dumps(kernels))
 
+    extras = {}
+    if not args.no_extras:
+        del guide, target, conf, out, ws
+        torch.cuda.empty_cache()
+        log("batched leg (64 uneven solves) ...")
+        extras["batched"] = batched_leg(max(3, args.steps // 2), 2)
+        log("  " + json.dumps(extras["batched"]))
+        torch.cuda.empty_cache()
+        log("forward+backward leg (8 x 1024^2, T=15) ...")
+        extras["fwd_bwd"] = fwd_bwd_leg(max(3, args.steps // 2), 2)
+        log("  " + json.dumps(extras["fwd_bwd"]))
+
     cpu = None
     if args.cpu_rows > 0:
         log(f"CPU oracle baseline on {args.cpu_rows} rows ...")
@@ -177,6 +293,7 @@ def main():
         "cpu_baseline": cpu,
         "kernels": kernels,
     }
+    res.update(extras)
     print(json.dumps(res), flush=True)
 
 

@@ -294,11 +294,13 @@ def config3(rows=(0, C3_H), seed=C3_SEED, workers=8):
                 lam=LAMBDA, step=STEP, value_range=1.0)
 
 
-def config4(n=64, seed0=100):
+def config4(n=64, seed0=100, workers=8):
     """64 uneven instances: W ~ U{320..1920}, H ~ U{240..1080}, Cg in {1,3,8,16},
-    Ct in {1,2,3}, sigma_s ~ U[4,32], sigma_r ~ U[0.05,0.3], T=10; scenes as config 1."""
-    out = []
-    for i in range(n):
+    Ct in {1,2,3}, sigma_s ~ U[4,32], sigma_r ~ U[0.05,0.3], T=10; scenes as config 1.
+    Instances are independently seeded, so a thread pool builds them in any order."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(i):
         rng = np.random.default_rng(seed0 + i)
         W = int(rng.integers(320, 1921))
         H = int(rng.integers(240, 1081))
@@ -307,26 +309,26 @@ def config4(n=64, seed0=100):
         sigma_s = float(rng.uniform(4.0, 32.0))
         sigma_r = float(rng.uniform(0.05, 0.3))
         guide, target, conf, _ = _c1_style(seed0 + 1000 + i, H, W, Cg, Ct, 12)
-        out.append(dict(name=f"C4[{i}] {W}x{H} Cg={Cg} Ct={Ct}", guide=guide, target=target,
-                        conf=conf, sigma_s=sigma_s, sigma_r=sigma_r,
-                        filter_iters=FILTER_ITERS, solver_iters=10, lam=LAMBDA, step=STEP,
-                        value_range=1.0))
-    return out
+        return dict(name=f"C4[{i}] {W}x{H} Cg={Cg} Ct={Ct}", guide=guide, target=target,
+                    conf=conf, sigma_s=sigma_s, sigma_r=sigma_r, filter_iters=FILTER_ITERS,
+                    solver_iters=10, lam=LAMBDA, step=STEP, value_range=1.0)
+
+    with ThreadPoolExecutor(max(1, workers)) as ex:
+        return list(ex.map(one, range(n)))
 
 
-def config5(n=8, size=1024, seed0=200, ref_seed=299):
+def config5(n=8, size=1024, seed0=200, ref_seed=299, workers=8):
     """Batch of 8 1024x1024 RGB guides with 3-channel targets and confidences (config-1
     scenes), T=15, and the seeded reference r ~ U[0,1] of the loss sum((z^T - r)^2)."""
-    guides, targets, confs = [], [], []
-    for i in range(n):
-        g, t, c, _ = _c1_style(seed0 + i, size, size, 3, 3, 12)
-        guides.append(g)
-        targets.append(t)
-        confs.append(c)
+    from concurrent.futures import ThreadPoolExecutor
+
+    with ThreadPoolExecutor(max(1, workers)) as ex:
+        parts = list(ex.map(lambda i: _c1_style(seed0 + i, size, size, 3, 3, 12), range(n)))
     rng = np.random.default_rng(ref_seed)
     ref = rng.uniform(0.0, 1.0, size=(n, 3, size, size)).astype(np.float32)
-    return dict(name=f"C5 {n}x{size}x{size} RGB->3, T=15", guide=np.stack(guides),
-                target=np.stack(targets), conf=np.stack(confs), ref=ref,
+    return dict(name=f"C5 {n}x{size}x{size} RGB->3, T=15",
+                guide=np.stack([p[0] for p in parts]), target=np.stack([p[1] for p in parts]),
+                conf=np.stack([p[2] for p in parts]), ref=ref,
                 sigma_s=8.0, sigma_r=0.2, filter_iters=FILTER_ITERS, solver_iters=15,
                 lam=LAMBDA, step=STEP, value_range=1.0)
 

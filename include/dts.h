@@ -99,7 +99,8 @@ int dts_solve_backward(const float* guide, int Cg, const float* target, const fl
 /* ---- Many uneven solves in one persistent launch ---- */
 
 /* One independent solve: device pointers, shape and parameters (1 <= T, 1 <= N <= 8,
- * W <= 8192).  Layouts as above with batch 1. */
+ * W <= 8192; at most DTS_BATCH_MAX_PROBLEMS per batch).  Layouts as above with batch 1. */
+#define DTS_BATCH_MAX_PROBLEMS 1024
 typedef struct dts_problem {
     const float* guide;
     const float* target;
@@ -115,13 +116,15 @@ typedef struct dts_batched_plan {
     int n, variant, n_phases, total_tiles, grid;
     float lambda, step;
     size_t workspace_bytes;
-    size_t off_inst, off_base, off_prefix, off_need, off_done;
+    size_t off_inst, off_prefix, off_tickets;
 } dts_batched_plan;
 
-/* Launch shapes of the batched kernel: rows per wave of the column chunks and target
- * channels per column group.  The autotuner of the Python package picks one. */
+/* Launch shapes of the batched kernel: rows per wave of the column chunks, target
+ * channels per column group, and the size of a row tile (pixels x channels it aims
+ * for).  The autotuner of the Python package picks one. */
 int dts_batched_variant_count(void);
-int dts_batched_variant_info(int variant, int* rows_per_wave, int* group_channels);
+int dts_batched_variant_info(int variant, int* rows_per_wave, int* group_channels,
+                             int* row_tile_pixels);
 size_t dts_batched_workspace_bytes(const dts_problem* probs, int n, int variant);
 
 /* Writes the instance table and the tile schedule for `probs` (host array of n problems)
@@ -131,10 +134,14 @@ int dts_batched_prepare(const dts_problem* probs, int n, float lambda, float ste
                         void* workspace, size_t workspace_bytes, dts_batched_plan* plan, void* stream);
 
 /* Runs every planned solve (not in the paper; each instance is exactly what dts_solve
- * computes): one small reset kernel and one persistent kernel whose workgroups take the
- * row and column tiles of all instances in pass order, each tile waiting on its
- * instance's earlier passes through device-side counters.  Allocates and copies nothing,
- * so it can be captured into a HIP graph and replayed. */
+ * computes): one small reset kernel and one persistent kernel with one workgroup per
+ * resident slot of the device.  The workgroups run the passes of all instances in
+ * lockstep (pass p of every instance, a grid barrier, pass p + 1, ...), taking the row
+ * and column tiles of a pass from a device-side ticket counter.  The kernel needs the
+ * whole device: work running concurrently on other streams can delay the barriers,
+ * which give up after a bounded wait and then make dts_workspace_status return
+ * DTS_EDEVICE.  Allocates and copies nothing, so it can be captured into a HIP
+ * graph and replayed; calls sharing one workspace must not overlap. */
 int dts_solve_batched(const dts_batched_plan* plan, void* workspace, void* stream);
 
 /* ---- The individual steps of the filter (each also runs inside the calls above) ---- */

@@ -129,10 +129,8 @@ class _BatchedPlan(ctypes.Structure):
         ("step", ctypes.c_float),
         ("workspace_bytes", ctypes.c_size_t),
         ("off_inst", ctypes.c_size_t),
-        ("off_base", ctypes.c_size_t),
         ("off_prefix", ctypes.c_size_t),
-        ("off_need", ctypes.c_size_t),
-        ("off_done", ctypes.c_size_t),
+        ("off_tickets", ctypes.c_size_t),
     ]
 
 
@@ -213,7 +211,7 @@ def library():
     BP = ctypes.POINTER(_BatchedPlan)
     lib.dts_batched_variant_count.argtypes = []
     lib.dts_batched_variant_count.restype = i
-    lib.dts_batched_variant_info.argtypes = [i, ip, ip]
+    lib.dts_batched_variant_info.argtypes = [i, ip, ip, ip]
     lib.dts_batched_variant_info.restype = i
     lib.dts_batched_workspace_bytes.argtypes = [PP, i, i]
     lib.dts_batched_workspace_bytes.restype = sz
@@ -363,14 +361,15 @@ def tune_row_segment(pixels_per_lane):
 
 
 def batched_variants():
-    """[(index, rows_per_wave, group_channels)] of the batched kernel's shapes."""
+    """[(index, rows_per_wave, group_channels, row_tile_pixels)] of the batched kernel's
+    shapes."""
     lib = library()
     out = []
     for v in range(lib.dts_batched_variant_count()):
-        r, ct = ctypes.c_int(), ctypes.c_int()
-        _check(lib.dts_batched_variant_info(v, ctypes.byref(r), ctypes.byref(ct)),
+        r, ct, px = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib.dts_batched_variant_info(v, ctypes.byref(r), ctypes.byref(ct), ctypes.byref(px)),
                "dts_batched_variant_info")
-        out.append((v, r.value, ct.value))
+        out.append((v, r.value, ct.value, px.value))
     return out
 
 

@@ -1,7 +1,8 @@
 """Autotuner of launch shapes.
 
 For the batched persistent solve it times every variant of the kernel (rows per wave of
-the column chunks x target channels per column group) on the caller's own problem set,
+the column chunks, target channels per column group, row-tile size) on the caller's own
+problem set,
 keeps the fastest, and caches the choice in a JSON file keyed by the device architecture
 and a coarse signature of the problem set (instance count, total pixels, widest row,
 channel counts), so later solvers of the same kind skip the measurement.
@@ -77,12 +78,14 @@ def batched_variant(solver, iters=2, use_cache=True, report=None):
     """Index of the fastest batched-kernel variant for ``solver``'s problems."""
     from . import batched_variants
 
-    key = _arch() + "|" + batched_signature(solver.problems)
+    shapes = batched_variants()
+    key = (_arch() + "|" + batched_signature(solver.problems) + "|variants:" +
+           ",".join("x".join(str(x) for x in v[1:]) for v in shapes))
     db = _load() if use_cache else {}
     if key in db:
         return int(db[key]["variant"])
     timings = {}
-    for v, rows, ctm in batched_variants():
+    for v, *_ in shapes:
         try:
             solver._prepare(v)
         except Exception:

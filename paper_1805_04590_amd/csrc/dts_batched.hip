@@ -2,17 +2,21 @@
 // every instance is the Eq. (3) gradient descent with the recursive domain-transform
 // filter of Sec. 3.2, exactly as dts_solve runs it).
 //
-// Work is a list of tiles in phase-major order: phase p is the p-th pass of every
-// instance (the row and column passes of each filter iteration, solver iteration after
-// solver iteration), and within a phase the tiles of instance 0, then instance 1, ...
-// A row tile is one image row; a column tile is one chunk of one 64-column strip (chunks
-// of a strip are consecutive).  Workgroups of a persistent grid that fits on the device
-// at once take tiles in order from an atomic ticket counter.  A tile of phase p of
-// instance i waits until all tiles of the instance's earlier phases are done (a
-// per-instance counter, released after the tile's stores and acquired before its
-// loads); chunks of one strip exchange carries through epoch-tagged words.  Every wait
-// is on an earlier ticket or on a chunk of the same strip, whose tickets are consecutive
-// and fit in the grid, so the launch always completes.
+// Phase p is the p-th pass of every instance (the row and column passes of each filter
+// iteration, solver iteration after solver iteration).  All workgroups of a grid that
+// fits on the device at once work through the phases in lockstep: inside a phase they
+// take tiles from the phase's atomic ticket counter (instance 0's tiles first, then
+// instance 1's, ...), and between phases they meet at a grid barrier whose release and
+// acquire make the phase's stores visible to every XCD.  A row tile is a band of rows of
+// one instance, processed 8 / row_gw rows at a time by groups of row_gw waves; a column
+// tile is one chunk of one 64-column strip (chunks of a strip are consecutive tickets)
+// and exchanges carries with the strip's other chunks through epoch-tagged words.
+//
+// Progress: a workgroup takes its next ticket only when its current tile can no longer
+// wait (at the start of a row tile, after the carries of a column tile are resolved), so
+// every chunk that a waiting chunk needs is either running or held by a workgroup that
+// will start it; a strip has at most as many chunks as the grid has workgroups.  Every
+// wait is bounded and flags the workspace status when it gives up.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -28,6 +32,8 @@
 
 namespace dts {
 
+constexpr int kBarrierSpinLimit = 1 << 25;
+
 __device__ __forceinline__ int upper_index(const int* v, int n, int x) {
     // largest j in [0, n) with v[j] <= x (v sorted ascending, v[0] <= x)
     int lo = 0, hi = n - 1;
@@ -39,129 +45,163 @@ __device__ __forceinline__ int upper_index(const int* v, int n, int x) {
     return lo;
 }
 
-template <int S>
-__device__ __forceinline__ void row_tile_any(const RowArgs& ra, bool dist, int y) {
-    if (dist) row_tile<S, true>(ra, y, 0);
-    else row_tile<S, false>(ra, y, 0);
+// All workgroups of the grid: every store issued before the call is visible to every
+// workgroup after it.
+__device__ __forceinline__ void grid_barrier(unsigned* count, unsigned target, int* status) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int spins = 0, backoff = 1;
+        while (__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            spins += backoff;
+            if (spins > kBarrierSpinLimit) {
+                flag_error(status, kErrSpinTimeout);
+                break;
+            }
+            for (int q = 0; q < backoff; ++q) __builtin_amdgcn_s_sleep(1);
+            backoff = backoff < 16 ? backoff * 2 : 16;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+}
+
+struct RowLds {
+    float2 fagg[kBatchWaves];
+    float2 bagg[kBatchWaves];
+    float wfirst[2 * kBatchWaves];
+};
+
+// Rows [y0, y1) of one instance, 8 / gw rows side by side.
+template <int S, bool DIST>
+__device__ __forceinline__ void row_band(const RowArgs& ra, int y0, int y1, int gw, RowLds& RL) {
+    const int wave = threadIdx.x >> 6;
+    const int rg = wave / gw;
+    const int gwv = wave - rg * gw;
+    const int groups = kBatchWaves / gw;
+    for (int y = y0; y < y1; y += groups) {
+        const int yy = y + rg;
+        const bool live = yy < y1;
+        row_line<S, DIST>(ra, live ? yy : 0, 0, gwv, gw, live, RL.fagg + rg * gw, RL.bagg + rg * gw,
+                          RL.wfirst + rg * (gw + 1));
+    }
 }
 
 template <int R, int CTM>
 __global__ void __launch_bounds__(kWave * kBatchWaves) batched_kernel(BatchArgs a) {
     __shared__ ChunkLds<CTM, kBatchWaves> L;
-    __shared__ int s_t;
+    __shared__ RowLds RL;
+    __shared__ int s_pre[kBatchMaxProblems + 1];
+    __shared__ unsigned s_t;
     const unsigned launch = __hip_atomic_load(const_cast<unsigned*>(a.launch), __ATOMIC_RELAXED,
                                               __HIP_MEMORY_SCOPE_AGENT);
-    while (true) {
+    const int n = a.n;
+    for (int p = 0; p < a.n_phases; ++p) {
+        unsigned* tickets = a.tickets + p;
+        const int* pre = a.phase_prefix + static_cast<size_t>(p) * (n + 1);
+        for (int j = threadIdx.x; j <= n; j += blockDim.x) s_pre[j] = pre[j];
+        if (threadIdx.x == 0) s_t = atomicAdd(tickets, 1u);
         __syncthreads();
-        if (threadIdx.x == 0) s_t = static_cast<int>(atomicAdd(a.ticket, 1u));
-        __syncthreads();
-        const int t = __builtin_amdgcn_readfirstlane(s_t);
-        if (t >= a.total) break;
-        const int p = upper_index(a.phase_base, a.n_phases + 1, t);
-        const int local = t - a.phase_base[p];
-        const int* pre = a.phase_prefix + static_cast<size_t>(p) * (a.n + 1);
-        const int i = upper_index(pre, a.n + 1, local);
-        const int tile = local - pre[i];
-        const BInst& I = a.inst[i];
-
-        // wait until the instance's earlier phases are complete
-        if (threadIdx.x == 0) {
-            const unsigned need = static_cast<unsigned>(a.need[static_cast<size_t>(p) * a.n + i]);
-            int spins = 0, backoff = 1;
-            while (__hip_atomic_load(&a.done[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
-                spins += backoff;
-                if (spins > kSpinLimit) {
-                    flag_error(a.status, kErrSpinTimeout);
-                    break;
+        const int total = s_pre[n];
+        int t = static_cast<int>(__builtin_amdgcn_readfirstlane(s_t));
+        unsigned nxt = 0u;  // thread 0: the next ticket, taken while the tile runs
+        while (t < total) {
+            const int i = __builtin_amdgcn_readfirstlane(upper_index(s_pre, n + 1, t));
+            const int tile = t - s_pre[i];
+            const BInst& I = a.inst[i];
+            const int per_iter = 2 * I.N;
+            const int k = p / per_iter;
+            const int q = p % per_iter;
+            const int fi = q / 2 + 1;  // filter iteration 1..N
+            const float* zk = (k == 0) ? I.target : I.out;
+            if ((q & 1) == 0) {
+                if (threadIdx.x == 0) nxt = atomicAdd(tickets, 1u);
+                RowArgs ra;
+                ra.src = (fi == 1) ? zk : I.tmp;
+                ra.dst = I.tmp;
+                ra.d = I.dx;
+                ra.guide = I.guide;
+                ra.dx_out = I.dx;
+                ra.dy_out = I.dy;
+                ra.Cg = I.Cg;
+                ra.s2 = I.s2;
+                ra.C = I.Ct;
+                ra.H = I.H;
+                ra.W = I.W;
+                ra.log2a = I.log2a[fi - 1];
+                const int y0 = tile * I.row_rows;
+                const int y1 = min(I.H, y0 + I.row_rows);
+                const bool dist = (k == 0 && fi == 1);
+                if (I.row_S == 8) {
+                    if (dist) row_band<8, true>(ra, y0, y1, I.row_gw, RL);
+                    else row_band<8, false>(ra, y0, y1, I.row_gw, RL);
+                } else {
+                    if (dist) row_band<16, true>(ra, y0, y1, I.row_gw, RL);
+                    else row_band<16, false>(ra, y0, y1, I.row_gw, RL);
                 }
-                for (int q = 0; q < backoff; ++q) __builtin_amdgcn_s_sleep(2);
-                backoff = backoff < 32 ? backoff * 2 : 32;
+            } else {
+                ColArgs ca;
+                const bool epi = (fi == I.N);
+                ca.src = I.tmp;
+                ca.dst = epi ? I.out : I.tmp;
+                ca.d = I.dy;
+                ca.C = I.Ct;
+                ca.H = I.H;
+                ca.W = I.W;
+                ca.log2a = I.log2a[fi - 1];
+                ca.G = I.G;
+                ca.S = I.S;
+                ca.NG = I.NG;
+                ca.batch = 1;
+                ca.groups = 1;
+                ca.carry = I.carry;
+                ca.epoch = launch * static_cast<unsigned>(a.n_phases + 1) + static_cast<unsigned>(p) + 1u;
+                ca.status = a.status;
+                ca.zk = zk;
+                ca.tgt = I.target;
+                ca.conf = I.conf;
+                ca.Cc = I.Cc;
+                ca.dst2 = nullptr;
+                ca.lambda = a.lambda;
+                ca.step = a.step;
+                const CarryCtx cctx{ca.carry, ca.epoch, ca.status, ca.G, ca.S, ca.NG};
+                const int chunk = tile % I.G;
+                const int rest = tile / I.G;
+                const int strip = rest % I.S;
+                const int grp = rest / I.S;
+                auto take_next = [&]() {
+                    if (threadIdx.x == 0) nxt = atomicAdd(tickets, 1u);
+                };
+                if (epi) col_tile<CTM, R, kBatchWaves, true>(ca, cctx, L, chunk, strip, grp, 0, take_next);
+                else col_tile<CTM, R, kBatchWaves, false>(ca, cctx, L, chunk, strip, grp, 0, take_next);
             }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            // every wave has read s_t (at least one barrier of the tile lies between)
+            if (threadIdx.x == 0) s_t = nxt;
+            __syncthreads();
+            t = static_cast<int>(__builtin_amdgcn_readfirstlane(s_t));
         }
-        __syncthreads();
-
-        const int per_iter = 2 * I.N;
-        const int k = p / per_iter;
-        const int q = p % per_iter;
-        const int fi = q / 2 + 1;  // filter iteration 1..N
-        const float* zk = (k == 0) ? I.target : I.out;
-        if ((q & 1) == 0) {
-            RowArgs ra;
-            ra.src = (fi == 1) ? zk : I.tmp;
-            ra.dst = I.tmp;
-            ra.d = I.dx;
-            ra.guide = I.guide;
-            ra.dx_out = I.dx;
-            ra.dy_out = I.dy;
-            ra.Cg = I.Cg;
-            ra.s2 = I.s2;
-            ra.C = I.Ct;
-            ra.H = I.H;
-            ra.W = I.W;
-            ra.log2a = I.log2a[fi - 1];
-            const bool dist = (k == 0 && fi == 1);
-            if (I.row_S == 4) row_tile_any<4>(ra, dist, tile);
-            else if (I.row_S == 8) row_tile_any<8>(ra, dist, tile);
-            else row_tile_any<16>(ra, dist, tile);
-        } else {
-            ColArgs ca;
-            const bool epi = (fi == I.N);
-            ca.src = I.tmp;
-            ca.dst = epi ? I.out : I.tmp;
-            ca.d = I.dy;
-            ca.C = I.Ct;
-            ca.H = I.H;
-            ca.W = I.W;
-            ca.log2a = I.log2a[fi - 1];
-            ca.G = I.G;
-            ca.S = I.S;
-            ca.NG = I.NG;
-            ca.batch = 1;
-            ca.groups = 1;
-            ca.carry = I.carry;
-            ca.epoch = launch * static_cast<unsigned>(a.n_phases + 1) + static_cast<unsigned>(p) + 1u;
-            ca.status = a.status;
-            ca.zk = zk;
-            ca.tgt = I.target;
-            ca.conf = I.conf;
-            ca.Cc = I.Cc;
-            ca.dst2 = nullptr;
-            ca.lambda = a.lambda;
-            ca.step = a.step;
-            const CarryCtx cctx{ca.carry, ca.epoch, ca.status, ca.G, ca.S, ca.NG};
-            const int chunk = tile % I.G;
-            const int rest = tile / I.G;
-            const int strip = rest % I.S;
-            const int grp = rest / I.S;
-            if (epi) col_tile<CTM, R, kBatchWaves, true>(ca, cctx, L, chunk, strip, grp, 0);
-            else col_tile<CTM, R, kBatchWaves, false>(ca, cctx, L, chunk, strip, grp, 0);
-        }
-
-        // publish completion: every wave's stores precede the barrier, the release makes
-        // them visible device-wide before the counter moves
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            __hip_atomic_fetch_add(&a.done[i], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        if (p + 1 < a.n_phases)
+            grid_barrier(a.barrier, static_cast<unsigned>(p + 1) * gridDim.x, a.status);
     }
 }
 
-__global__ void batched_reset_kernel(unsigned* ticket, unsigned* launch, unsigned* done, int n, int* status) {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) done[i] = 0u;
+__global__ void batched_reset_kernel(unsigned* tickets, int n_phases, unsigned* barrier, unsigned* launch,
+                                     int* status) {
+    for (int i = threadIdx.x; i < n_phases; i += blockDim.x) tickets[i] = 0u;
     if (threadIdx.x == 0) {
-        *ticket = 0u;
+        *barrier = 0u;
         *launch = *launch + 1u;
         *status = 0;
     }
 }
 
 // ---------------------------------------------------------------------------------------
-// Variants (chosen by the autotuner): rows per wave R and channels per column group CTM
+// Variants (chosen by the autotuner): rows per wave R of the column chunks, channels per
+// column group CTM, and the target size of a row tile in pixels x channels
 // ---------------------------------------------------------------------------------------
 struct BatchVariant {
-    int R, ctm;
+    int R, ctm, row_px;
     void (*launch)(const BatchArgs&, unsigned, hipStream_t);
     int (*capacity)();
 };
@@ -190,20 +230,21 @@ static int batched_capacity_v() {
     return cached[dev];
 }
 
+#define DTS_BV(R, CT, PX) {R, CT, PX, batched_launch_v<R, CT>, batched_capacity_v<R, CT>}
 static const BatchVariant kBatchVariants[] = {
-    {16, 1, batched_launch_v<16, 1>, batched_capacity_v<16, 1>},
-    {32, 1, batched_launch_v<32, 1>, batched_capacity_v<32, 1>},
-    {16, 3, batched_launch_v<16, 3>, batched_capacity_v<16, 3>},
-    {8, 3, batched_launch_v<8, 3>, batched_capacity_v<8, 3>},
+    DTS_BV(16, 1, 16384), DTS_BV(32, 1, 16384), DTS_BV(16, 3, 16384), DTS_BV(8, 3, 16384),
+    DTS_BV(16, 1, 65536), DTS_BV(32, 1, 65536), DTS_BV(16, 3, 65536),
 };
+#undef DTS_BV
 constexpr int kNumBatchVariants = sizeof(kBatchVariants) / sizeof(kBatchVariants[0]);
 
 int num_batch_variants() { return kNumBatchVariants; }
 
-int batch_variant_info(int v, int* rows_per_wave, int* group_channels) {
+int batch_variant_info(int v, int* rows_per_wave, int* group_channels, int* row_tile_pixels) {
     if (v < 0 || v >= kNumBatchVariants) return DTS_EINVAL;
     *rows_per_wave = kBatchVariants[v].R;
     *group_channels = kBatchVariants[v].ctm;
+    *row_tile_pixels = kBatchVariants[v].row_px;
     return DTS_OK;
 }
 
@@ -215,7 +256,7 @@ constexpr size_t kBAlign = 256;
 size_t bal(size_t v) { return (v + kBAlign - 1) / kBAlign * kBAlign; }
 
 struct Geo {
-    int row_S, G, S, NG, rows_tiles, col_tiles, phases;
+    int row_S, row_gw, row_rows, G, S, NG, rows_tiles, col_tiles, phases;
     size_t dx, dy, tmp, carry, carry_bytes;
 };
 }  // namespace
@@ -229,6 +270,7 @@ static int check_problem(const dts_problem& q) {
         return DTS_EINVAL;
     if (q.filter_iters < 1 || q.solver_iters < 1) return DTS_EINVAL;
     if (q.filter_iters > kBatchMaxN || q.W > kBatchMaxWidth || q.H > DTS_MAX_HEIGHT) return DTS_ENOTSUP;
+    if (static_cast<long long>(q.filter_iters) * q.solver_iters > (1 << 20)) return DTS_ENOTSUP;
     if ((static_cast<size_t>(q.H) + 64) * static_cast<size_t>(q.W) * 4 >= (static_cast<size_t>(1) << 31))
         return DTS_ENOTSUP;
     return DTS_OK;
@@ -236,24 +278,33 @@ static int check_problem(const dts_problem& q) {
 
 static Geo geometry(const dts_problem& q, const BatchVariant& v) {
     Geo g{};
-    g.row_S = q.W > 4096 ? 16 : q.W > 2048 ? 8 : 4;
+    g.row_S = q.W <= 512 ? 8 : 16;
+    const int waves = (q.W + kWave * g.row_S - 1) / (kWave * g.row_S);
+    g.row_gw = 1;
+    while (g.row_gw < waves) g.row_gw *= 2;
+    const int side = kBatchWaves / g.row_gw;  // rows processed side by side
+    const long long per_round = static_cast<long long>(q.W) * q.Ct * side;
+    long long rounds = (v.row_px + per_round - 1) / per_round;
+    rounds = std::max(1LL, std::min(rounds, static_cast<long long>(std::max(1, 64 / side))));
+    g.row_rows = static_cast<int>(rounds) * side;
     const int rows = v.R * kBatchWaves;
     g.G = (q.H + rows - 1) / rows;
     g.S = (q.W + kWave - 1) / kWave;
     g.NG = (q.Ct + v.ctm - 1) / v.ctm;
-    g.rows_tiles = q.H;
+    g.rows_tiles = (q.H + g.row_rows - 1) / g.row_rows;
     g.col_tiles = g.NG * g.S * g.G;
     g.phases = 2 * q.filter_iters * q.solver_iters;
     return g;
 }
 
 struct BatchLayout {
-    size_t hdr = 0, inst = 0, base = 0, prefix = 0, need = 0, done = 0, bufs = 0, total = 0;
+    size_t inst = 0, prefix = 0, tickets = 0, bufs = 0, total = 0;
     int n_phases = 0, total_tiles = 0, max_G = 0;
     std::vector<Geo> geo;
 };
 
 static int make_batch_layout(const dts_problem* probs, int n, const BatchVariant& v, BatchLayout& L) {
+    if (n < 1 || n > kBatchMaxProblems) return DTS_ENOTSUP;
     L.geo.resize(n);
     long long tiles = 0;
     for (int i = 0; i < n; ++i) {
@@ -267,17 +318,13 @@ static int make_batch_layout(const dts_problem* probs, int n, const BatchVariant
     }
     if (tiles > (1LL << 30)) return DTS_ENOTSUP;
     L.total_tiles = static_cast<int>(tiles);
-    size_t off = 256;  // header: status, ticket, launch
+    size_t off = 256;  // header: status, barrier count, launch count
     L.inst = off;
     off = bal(off + sizeof(BInst) * n);
-    L.base = off;
-    off = bal(off + sizeof(int) * (L.n_phases + 1));
     L.prefix = off;
     off = bal(off + sizeof(int) * static_cast<size_t>(L.n_phases) * (n + 1));
-    L.need = off;
-    off = bal(off + sizeof(int) * static_cast<size_t>(L.n_phases) * n);
-    L.done = off;
-    off = bal(off + sizeof(unsigned) * n);
+    L.tickets = off;
+    off = bal(off + sizeof(unsigned) * static_cast<size_t>(L.n_phases));
     L.bufs = off;
     for (int i = 0; i < n; ++i) {
         const dts_problem& q = probs[i];
@@ -298,7 +345,7 @@ static int make_batch_layout(const dts_problem* probs, int n, const BatchVariant
     return DTS_OK;
 }
 
-constexpr size_t kBTicket = 64, kBLaunch = 128;
+constexpr size_t kBBarrier = 64, kBLaunch = 128;
 
 }  // namespace dts
 
@@ -308,9 +355,9 @@ extern "C" {
 
 int dts_batched_variant_count(void) { return num_batch_variants(); }
 
-int dts_batched_variant_info(int variant, int* rows_per_wave, int* group_channels) {
-    if (!rows_per_wave || !group_channels) return DTS_EINVAL;
-    return batch_variant_info(variant, rows_per_wave, group_channels);
+int dts_batched_variant_info(int variant, int* rows_per_wave, int* group_channels, int* row_tile_pixels) {
+    if (!rows_per_wave || !group_channels || !row_tile_pixels) return DTS_EINVAL;
+    return batch_variant_info(variant, rows_per_wave, group_channels, row_tile_pixels);
 }
 
 size_t dts_batched_workspace_bytes(const dts_problem* probs, int n, int variant) {
@@ -360,6 +407,8 @@ int dts_batched_prepare(const dts_problem* probs, int n, float lambda, float ste
         I.N = q.filter_iters;
         I.T = q.solver_iters;
         I.row_S = g.row_S;
+        I.row_gw = g.row_gw;
+        I.row_rows = g.row_rows;
         I.G = g.G;
         I.S = g.S;
         I.NG = g.NG;
@@ -375,27 +424,18 @@ int dts_batched_prepare(const dts_problem* probs, int n, float lambda, float ste
             }
         }
     }
-    int* pbase = reinterpret_cast<int*>(at(L.base));
     int* pre = reinterpret_cast<int*>(at(L.prefix));
-    int* need = reinterpret_cast<int*>(at(L.need));
-    std::vector<long long> done_before(n, 0);
-    long long acc = 0;
     for (int p = 0; p < L.n_phases; ++p) {
-        pbase[p] = static_cast<int>(acc);
         int local = 0;
         for (int i = 0; i < n; ++i) {
             const Geo& g = L.geo[i];
             pre[static_cast<size_t>(p) * (n + 1) + i] = local;
-            need[static_cast<size_t>(p) * n + i] = static_cast<int>(done_before[i]);
             int tiles = 0;
             if (p < g.phases) tiles = (p & 1) ? g.col_tiles : g.rows_tiles;
             local += tiles;
-            done_before[i] += tiles;
         }
         pre[static_cast<size_t>(p) * (n + 1) + n] = local;
-        acc += local;
     }
-    pbase[L.n_phases] = static_cast<int>(acc);
     if ((rc = launch_zero(base, L.inst, s))) return rc;
     if ((rc = hip_fail(hipMemcpyAsync(base + L.inst, img.data(), img.size(), hipMemcpyHostToDevice, s))))
         return rc;
@@ -408,13 +448,11 @@ int dts_batched_prepare(const dts_problem* probs, int n, float lambda, float ste
     plan->variant = variant;
     plan->n_phases = L.n_phases;
     plan->total_tiles = L.total_tiles;
-    plan->grid = std::min(cap, L.total_tiles);
+    plan->grid = cap;  // all co-resident: the phases meet at grid barriers
     plan->workspace_bytes = L.total;
     plan->off_inst = L.inst;
-    plan->off_base = L.base;
     plan->off_prefix = L.prefix;
-    plan->off_need = L.need;
-    plan->off_done = L.done;
+    plan->off_tickets = L.tickets;
     plan->lambda = lambda;
     plan->step = step;
     return DTS_OK;
@@ -425,22 +463,20 @@ int dts_solve_batched(const dts_batched_plan* plan, void* workspace, void* strea
         return DTS_EINVAL;
     char* base = static_cast<char*>(workspace);
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (plan->grid < 1 || plan->grid > kBatchVariants[plan->variant].capacity()) return DTS_EINVAL;
     BatchArgs a;
     a.inst = reinterpret_cast<const BInst*>(base + plan->off_inst);
-    a.phase_base = reinterpret_cast<const int*>(base + plan->off_base);
     a.phase_prefix = reinterpret_cast<const int*>(base + plan->off_prefix);
-    a.need = reinterpret_cast<const int*>(base + plan->off_need);
-    a.done = reinterpret_cast<unsigned*>(base + plan->off_done);
-    a.ticket = reinterpret_cast<unsigned*>(base + kBTicket);
+    a.tickets = reinterpret_cast<unsigned*>(base + plan->off_tickets);
+    a.barrier = reinterpret_cast<unsigned*>(base + kBBarrier);
     a.launch = reinterpret_cast<const unsigned*>(base + kBLaunch);
     a.status = reinterpret_cast<int*>(base);
     a.n = plan->n;
     a.n_phases = plan->n_phases;
-    a.total = plan->total_tiles;
     a.lambda = plan->lambda;
     a.step = plan->step;
-    hipLaunchKernelGGL(batched_reset_kernel, dim3(1), dim3(256), 0, s, a.ticket,
-                       reinterpret_cast<unsigned*>(base + kBLaunch), a.done, a.n, a.status);
+    hipLaunchKernelGGL(batched_reset_kernel, dim3(1), dim3(256), 0, s, a.tickets, a.n_phases, a.barrier,
+                       reinterpret_cast<unsigned*>(base + kBLaunch), a.status);
     int rc = hip_fail(hipGetLastError());
     if (rc) return rc;
     ProfScope prof("batched_solve", 0.0, s);

@@ -3,9 +3,10 @@
 
 namespace dts {
 
-constexpr int kBatchMaxN = 8;        // filter iterations per instance
-constexpr int kBatchWaves = 8;       // waves per workgroup of the batched kernel
+constexpr int kBatchMaxN = 8;          // filter iterations per instance
+constexpr int kBatchWaves = 8;         // waves per workgroup of the batched kernel
 constexpr int kBatchMaxWidth = kBatchWaves * 64 * 16;
+constexpr int kBatchMaxProblems = 1024;
 
 struct BInst {
     const float* guide;
@@ -17,7 +18,9 @@ struct BInst {
     float* tmp;
     unsigned long long* carry;
     int H, W, Cg, Ct, Cc, N, T;
-    int row_S;       // pixels per lane of the row tiles
+    int row_S;       // pixels per lane of a row (8 or 16)
+    int row_gw;      // waves per row (1, 2, 4 or 8); 8 / row_gw rows side by side
+    int row_rows;    // rows per row tile (a multiple of 8 / row_gw)
     int G, S, NG;    // column chunks per strip, strips, channel groups
     float s2;
     float log2a[kBatchMaxN];
@@ -25,14 +28,12 @@ struct BInst {
 
 struct BatchArgs {
     const BInst* inst;
-    const int* phase_base;    // [n_phases + 1] first ticket of each phase
     const int* phase_prefix;  // [n_phases][n + 1] first tile of each instance in a phase
-    const int* need;          // [n_phases][n] tiles of the instance done before the phase
-    unsigned* done;           // [n] completed tiles per instance
-    unsigned* ticket;
+    unsigned* tickets;        // [n_phases] tile counters, zeroed by the reset kernel
+    unsigned* barrier;        // workgroups that finished a phase (cumulative)
     const unsigned* launch;   // launch counter (epoch base of the carry words)
     int* status;
-    int n, n_phases, total;
+    int n, n_phases;
     float lambda, step;
 };
 

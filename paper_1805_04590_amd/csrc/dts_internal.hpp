@@ -110,7 +110,7 @@ int tune_col_variant(int ct, int variant);
 int col_variant_info(int variant, int* ct, int* rows_per_wave, int* waves);
 int num_col_variants();
 int num_batch_variants();
-int batch_variant_info(int v, int* rows_per_wave, int* group_channels);
+int batch_variant_info(int v, int* rows_per_wave, int* group_channels, int* row_tile_pixels);
 int tune_row_segment(int S);
 int launch_zero(void* ptr, size_t bytes, hipStream_t s);
 int launch_copy(float* dst, const float* src, size_t n, hipStream_t s);

@@ -1,7 +1,8 @@
 // Tile bodies of the forward passes, shared by the per-pass kernels (dts_forward.hip)
 // and the persistent batched kernel (dts_batched.hip).
 //
-// row_tile: one image row per workgroup.  Lane l of wave v owns S consecutive pixels.
+// row_line / row_tile: one image row per group of waves (row_tile: the whole workgroup).
+//   Lane l of wave v owns S consecutive pixels.
 //   Each direction of the recurrence is a chain of affine maps: a serial composition over
 //   the lane's S pixels, one 64-lane scan (DPP inside rows of 16 lanes, scalar reads
 //   across rows), one exchange of wave totals through LDS, then a serial sweep from the
@@ -64,20 +65,19 @@ __device__ __forceinline__ void store_seg(float* row, int n0, int W, bool vec, c
     }
 }
 
-// One workgroup per row; lane l of wave v owns the S consecutive pixels starting at
-// (64 v + l) S.  Per direction: a serial composition of the lane's S maps, one 64-lane
-// scan, one exchange of wave totals through LDS, and a serial sweep that produces the
-// final values.
+// One image row processed by a group of `nw` waves of the workgroup; lane l of group wave
+// v owns the S consecutive pixels starting at (64 v + l) S.  Per direction: a serial
+// composition of the lane's S maps, one 64-lane scan, one exchange of wave totals through
+// the group's LDS slots (fagg/bagg: nw entries, wfirst: nw + 1), and a serial sweep that
+// produces the final values.  Every wave of the workgroup must call it the same number of
+// times (it holds workgroup barriers); a group with `live` false reads and writes no
+// pixel.
 template <int S, bool DIST>
-__device__ __forceinline__ void row_tile(const RowArgs& a, int y, int b) {
-    __shared__ float2 fagg[kMaxRowWaves];
-    __shared__ float2 bagg[kMaxRowWaves];
-    __shared__ float wfirst[kMaxRowWaves + 1];
-
+__device__ __forceinline__ void row_line(const RowArgs& a, int y, int b, int wave, int nw, bool live,
+                                         float2* fagg, float2* bagg, float* wfirst) {
     const int lane = lane_id();
-    const int wave = threadIdx.x >> 6;
-    const int nw = blockDim.x >> 6;
     const int H = a.H, W = a.W;
+    const int We = live ? W : 0;  // pixels of the row this group touches
     const size_t plane = static_cast<size_t>(H) * W;
     const int n0 = (wave * kWave + lane) * S;
     const bool vec = (W & 3) == 0;
@@ -92,10 +92,10 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int y, int b) {
                              static_cast<size_t>(y) * W;
             const float* gu = (y > 0) ? g - W : g;
             float v[S], u[S];
-            load_seg<S>(g, n0, W, vec, 0.f, v);
-            load_seg<S>(gu, n0, W, vec, 0.f, u);
+            load_seg<S>(g, n0, We, vec, 0.f, v);
+            load_seg<S>(gu, n0, We, vec, 0.f, u);
             float prev = __shfl_up(v[S - 1], 1);
-            if (lane == 0) prev = (n0 > 0 && n0 <= W) ? g[n0 - 1] : v[0];
+            if (lane == 0) prev = (n0 > 0 && n0 <= We) ? g[n0 - 1] : v[0];
 #pragma unroll
             for (int e = 0; e < S; ++e) {
                 const float ex = v[e] - (e == 0 ? prev : v[e > 0 ? e - 1 : 0]);
@@ -111,26 +111,26 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int y, int b) {
             ax[e] = sqrtf(fmaf(a.s2, ax[e], 1.f));
             ay[e] = sqrtf(fmaf(a.s2, ay[e], 1.f));
         }
-        store_seg<S>(dxr, n0, W, vec, ax);
-        store_seg<S>(dyr, n0, W, vec, ay);
+        store_seg<S>(dxr, n0, We, vec, ax);
+        store_seg<S>(dyr, n0, We, vec, ay);
 #pragma unroll
         for (int e = 0; e < S; ++e) {
             const int n = n0 + e;
-            w[e] = (n > 0 && n < W) ? weight(ax[e], a.log2a) : 0.f;
+            w[e] = (n > 0 && n < We) ? weight(ax[e], a.log2a) : 0.f;
         }
     } else {
         const float* dr = a.d + static_cast<size_t>(b) * plane + static_cast<size_t>(y) * W;
         float dv[S];
-        load_seg<S>(dr, n0, W, vec, 1.f, dv);
+        load_seg<S>(dr, n0, We, vec, 1.f, dv);
 #pragma unroll
         for (int e = 0; e < S; ++e) {
             const int n = n0 + e;
-            w[e] = (n > 0 && n < W) ? weight(dv[e], a.log2a) : 0.f;
+            w[e] = (n > 0 && n < We) ? weight(dv[e], a.log2a) : 0.f;
         }
     }
     // weight linking each lane's last pixel to the next pixel (0 past the end of the row)
     if (lane == 0) wfirst[wave] = w[0];
-    if (threadIdx.x == 0) wfirst[nw] = 0.f;
+    if (wave == 0 && lane == 0) wfirst[nw] = 0.f;
     __syncthreads();
     float wlast = __shfl_down(w[0], 1);
     if (lane == kWave - 1) wlast = wfirst[wave + 1];
@@ -138,7 +138,7 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int y, int b) {
     for (int c = 0; c < a.C; ++c) {
         const size_t roff = (static_cast<size_t>(b) * a.C + c) * plane + static_cast<size_t>(y) * W;
         float f[S];
-        load_seg<S>(a.src + roff, n0, W, vec, 0.f, f);
+        load_seg<S>(a.src + roff, n0, We, vec, 0.f, f);
 
         // causal: J[n] = w[n] J[n-1] + (1 - w[n]) f[n]
         float la = 1.f, lb = 0.f;
@@ -189,8 +189,17 @@ __device__ __forceinline__ void row_tile(const RowArgs& a, int y, int b) {
             k = fmaf(wn, k - f[e], f[e]);
             f[e] = k;
         }
-        store_seg<S>(a.dst + roff, n0, W, vec, f);
+        store_seg<S>(a.dst + roff, n0, We, vec, f);
     }
+}
+
+// One workgroup per row (all of its waves form one group).
+template <int S, bool DIST>
+__device__ __forceinline__ void row_tile(const RowArgs& a, int y, int b) {
+    __shared__ float2 fagg[kMaxRowWaves];
+    __shared__ float2 bagg[kMaxRowWaves];
+    __shared__ float wfirst[kMaxRowWaves + 1];
+    row_line<S, DIST>(a, y, b, threadIdx.x >> 6, blockDim.x >> 6, true, fagg, bagg, wfirst);
 }
 
 
@@ -213,11 +222,17 @@ struct ColArgs {
     float lambda, step;
 };
 
+struct NoHook {
+    __device__ void operator()() const {}
+};
+
 // One workgroup = NWV waves stacked vertically over one 64-column strip: wave v owns rows
-// [r0 + v R, r0 + (v+1) R) of the chunk, one column per lane, all in registers.
-template <int CT, int R, int NWV, bool EPI>
+// [r0 + v R, r0 + (v+1) R) of the chunk, one column per lane, all in registers.  `hook`
+// runs on every thread once the chunk's carries are known, i.e. once the tile no longer
+// waits on any other tile.
+template <int CT, int R, int NWV, bool EPI, typename Hook = NoHook>
 __device__ __forceinline__ void col_tile(const ColArgs& a, const CarryCtx& cctx, ChunkLds<CT, NWV>& L,
-                                         int chunk, int strip, int grp, int b) {
+                                         int chunk, int strip, int grp, int b, Hook hook = Hook{}) {
     const int lane = opaque_v(lane_id());
     const int wave = opaque_s(__builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
     const int H = a.H, W = a.W;
@@ -301,6 +316,7 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, const CarryCtx& cctx,
     __syncthreads();
     if (wave == 0) chunk_carries<CT, NWV>(cctx, L, b, grp, strip, chunk, lane, valid, ncv);
     __syncthreads();
+    hook();
 
     float Jin[CT], Kin[CT];
 #pragma unroll

@@ -111,3 +111,19 @@ def test_binding_refuses_cpu_tensors():
         dts.filter(g, g[:1], 8.0, 0.2)
     with pytest.raises(ValueError, match="GPU"):
         dts.solve(g, g[:1], g[:1], 8.0, 0.2)
+
+
+def test_batched_variant_table(lib):
+    import test_gpu_batched
+
+    n = lib.dts_batched_variant_count()
+    assert n == test_gpu_batched.N_BATCH_VARIANTS
+    seen = set()
+    for v in range(n):
+        r, ct, px = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        assert lib.dts_batched_variant_info(v, ctypes.byref(r), ctypes.byref(ct), ctypes.byref(px)) == 0
+        assert r.value * 8 >= 64 and ct.value in (1, 2, 3, 4) and px.value > 0
+        seen.add((r.value, ct.value, px.value))
+    assert len(seen) == n
+    assert lib.dts_batched_variant_info(n, ctypes.byref(r), ctypes.byref(ct), ctypes.byref(px)) != 0
+

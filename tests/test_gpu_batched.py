@@ -12,6 +12,8 @@ import paper_1805_04590_amd as dts
 
 pytestmark = pytest.mark.gpu
 
+N_BATCH_VARIANTS = 7  # also checked against the library by a CPU test
+
 
 def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
@@ -39,7 +41,7 @@ def problems_of(cases):
                  solver_iters=c["solver_iters"]) for c in cases]
 
 
-@pytest.mark.parametrize("variant", range(4))
+@pytest.mark.parametrize("variant", range(N_BATCH_VARIANTS))
 def test_batched_matches_oracle_and_single(variant):
     cases = small_set()
     print("CASE batched variant", variant, [c["name"] for c in cases], flush=True)
@@ -56,6 +58,25 @@ def test_batched_matches_oracle_and_single(variant):
         got = o.cpu().numpy()
         assert np.abs(got - ref).max() <= 1e-4, c["name"]
         assert np.abs(got - single.cpu().numpy()).max() <= 1e-5, c["name"]
+
+
+@pytest.mark.parametrize("variant", [0, 2])
+def test_batched_wide_rows(variant):
+    """Rows split over 2, 4 and 8 waves, narrow rows side by side, a 1-row and a 1-column
+    image, next to each other in one launch."""
+    shapes = [(9, 1100, 3, 1), (6, 2500, 1, 2), (5, 5000, 8, 1), (4, 8192, 1, 1), (1, 300, 3, 1),
+              (70, 1, 1, 2), (33, 100, 16, 3)]
+    cases = [dts_inputs.random_case(1200 + k, H, W, Cg, Ct, Cc=1, sigma_s=12.0, sigma_r=0.2, T=2)
+             for k, (H, W, Cg, Ct) in enumerate(shapes)]
+    print("CASE batched wide rows", variant, shapes, flush=True)
+    probs = problems_of(cases)
+    bs = dts.BatchedSolver(probs, variant=variant)
+    outs = bs.run()
+    torch.cuda.synchronize()
+    bs.status()
+    for c, o in zip(cases, outs):
+        ref = oracle.solve(c["guide"], c["target"], c["conf"], c["sigma_s"], c["sigma_r"], 3, 2)
+        assert np.abs(o.cpu().numpy() - ref).max() <= 1e-4, c["name"]
 
 
 def test_graph_replays_match_eager():
