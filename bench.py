@@ -34,6 +34,9 @@ def parse():
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel timing run")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched (64 uneven solves) and forward+backward legs")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first fill and copy a MIB-sized float32 buffer with torch: kernels of "
+                         "known traffic that calibrate the hardware byte counters")
     return ap.parse_args()
 
 
@@ -181,6 +184,16 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.calibrate_copy > 0:
+        n = args.calibrate_copy * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)  # writes 4n bytes
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)  # reads 4n, writes 4n bytes
+        torch.cuda.synchronize()
+        log(f"calibration: fill and 3 copies of {4 * n} bytes")
+        del a, b
+        torch.cuda.empty_cache()
     H, W, Cg = dts_inputs.config3_shape()
     t0 = time.time()
     log(f"generating the {W}x{H}x{Cg} workload ...")

@@ -99,7 +99,7 @@ int dts_solve_backward(const float* guide, int Cg, const float* target, const fl
 /* ---- Many uneven solves in one persistent launch ---- */
 
 /* One independent solve: device pointers, shape and parameters (1 <= T, 1 <= N <= 8,
- * W <= 8192; at most DTS_BATCH_MAX_PROBLEMS per batch).  Layouts as above with batch 1. */
+ * W <= 4096; at most DTS_BATCH_MAX_PROBLEMS per batch).  Layouts as above with batch 1. */
 #define DTS_BATCH_MAX_PROBLEMS 1024
 typedef struct dts_problem {
     const float* guide;

@@ -2,21 +2,23 @@
 // every instance is the Eq. (3) gradient descent with the recursive domain-transform
 // filter of Sec. 3.2, exactly as dts_solve runs it).
 //
-// Phase p is the p-th pass of every instance (the row and column passes of each filter
+// Phase 0 computes the transformed distances of every instance (Eq. (8)-(9)); phase
+// p > 0 is the (p-1)-th pass of every instance (the row and column passes of each filter
 // iteration, solver iteration after solver iteration).  All workgroups of a grid that
 // fits on the device at once work through the phases in lockstep: inside a phase they
 // take tiles from the phase's atomic ticket counter (instance 0's tiles first, then
 // instance 1's, ...), and between phases they meet at a grid barrier whose release and
 // acquire make the phase's stores visible to every XCD.  A row tile is a band of rows of
-// one instance, processed 8 / row_gw rows at a time by groups of row_gw waves; a column
-// tile is one chunk of one 64-column strip (chunks of a strip are consecutive tickets)
-// and exchanges carries with the strip's other chunks through epoch-tagged words.
+// one instance: rows up to kBatchSoloWidth pixels are filtered by one wave each with no
+// barrier, wider rows by groups of row_gw waves.  A column tile is one chunk of one
+// 64-column strip (chunks of a strip are consecutive tickets) and exchanges carries with
+// the strip's other chunks through epoch-tagged words.
 //
 // Progress: a workgroup takes its next ticket only when its current tile can no longer
-// wait (at the start of a row tile, after the carries of a column tile are resolved), so
-// every chunk that a waiting chunk needs is either running or held by a workgroup that
-// will start it; a strip has at most as many chunks as the grid has workgroups.  Every
-// wait is bounded and flags the workspace status when it gives up.
+// wait (at the start of a row or distance tile, after the carries of a column tile are
+// resolved), so every chunk that a waiting chunk needs is either running or held by a
+// workgroup that will start it; a strip has at most as many chunks as the grid has
+// workgroups.  Every wait is bounded and flags the workspace status when it gives up.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -73,23 +75,128 @@ struct RowLds {
     float wfirst[2 * kBatchWaves];
 };
 
-// Rows [y0, y1) of one instance, 8 / gw rows side by side.
-template <int S, bool DIST>
+// Rows y0 + v, y0 + v + kBatchWaves, ... of [y0, y1), each filtered by wave v alone.
+// While one channel of a row is filtered, the loads of the next channel (or of the next
+// row's distances and first channel) are already in flight.
+template <int S>
+__device__ __forceinline__ void row_band_solo(const RowArgs& a, int y0, int y1, int wave) {
+    const int lane = lane_id();
+    const int W = a.W, C = a.C;
+    const size_t plane = static_cast<size_t>(a.H) * W;
+    const int n0 = lane * S;
+    const bool vec = (W & 3) == 0;
+    int y = y0 + wave;
+    if (y >= y1) return;
+    float d[S], f[S];
+    load_seg<S>(a.d + static_cast<size_t>(y) * W, n0, W, vec, 1.f, d);
+    load_seg<S>(a.src + static_cast<size_t>(y) * W, n0, W, vec, 0.f, f);
+    while (true) {
+        float w[S];
+#pragma unroll
+        for (int e = 0; e < S; ++e) {
+            const int n = n0 + e;
+            w[e] = (n > 0 && n < W) ? weight(d[e], a.log2a) : 0.f;
+        }
+        float wlast = __shfl_down(w[0], 1);
+        if (lane == kWave - 1) wlast = 0.f;
+        const int yn = y + kBatchWaves;
+        for (int c = 0; c < C; ++c) {
+            float g[S];
+            const bool more = c + 1 < C || yn < y1;
+            if (c + 1 < C) {
+                load_seg<S>(a.src + (c + 1) * plane + static_cast<size_t>(y) * W, n0, W, vec, 0.f, g);
+            } else if (yn < y1) {
+                load_seg<S>(a.d + static_cast<size_t>(yn) * W, n0, W, vec, 1.f, d);
+                load_seg<S>(a.src + static_cast<size_t>(yn) * W, n0, W, vec, 0.f, g);
+            }
+            row_filter_solo<S>(w, wlast, f, lane);
+            store_seg<S>(a.dst + c * plane + static_cast<size_t>(y) * W, n0, W, vec, f);
+            if (more) {
+#pragma unroll
+                for (int e = 0; e < S; ++e) f[e] = g[e];
+            }
+        }
+        if (yn >= y1) break;
+        y = yn;
+    }
+}
+
+// Rows [y0, y1) of one instance.  gw == 1: one wave per row (row_band_solo); otherwise
+// kBatchWaves / gw groups of gw waves filter rows side by side.
+template <int S>
 __device__ __forceinline__ void row_band(const RowArgs& ra, int y0, int y1, int gw, RowLds& RL) {
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (gw == 1) {
+        row_band_solo<S>(ra, y0, y1, wave);
+        return;
+    }
     const int rg = wave / gw;
     const int gwv = wave - rg * gw;
     const int groups = kBatchWaves / gw;
     for (int y = y0; y < y1; y += groups) {
         const int yy = y + rg;
         const bool live = yy < y1;
-        row_line<S, DIST>(ra, live ? yy : 0, 0, gwv, gw, live, RL.fagg + rg * gw, RL.bagg + rg * gw,
-                          RL.wfirst + rg * (gw + 1));
+        row_line<S, false, false>(ra, live ? yy : 0, 0, gwv, gw, live, RL.fagg + rg * gw,
+                                  RL.bagg + rg * gw, RL.wfirst + rg * (gw + 1));
     }
 }
 
-template <int R, int CTM>
-__global__ void __launch_bounds__(kWave * kBatchWaves) batched_kernel(BatchArgs a) {
+// Transformed distances (Eq. (8)-(9)) of rows [y0, y1): one pixel per thread, guide bands
+// four at a time (their loads in flight together, the sums in band order); at x = 0
+// (y = 0) the missing neighbour is the pixel itself, so the distance is 1.  Consecutive
+// rows of a band share the workgroup's L2, where the row above is re-read.
+__device__ __forceinline__ void dist_band(const BInst& I, int y0, int y1) {
+    const int W = I.W, Cg = I.Cg;
+    const size_t plane = static_cast<size_t>(I.H) * W;
+    const float* __restrict__ guide = I.guide;
+    float* __restrict__ dx = I.dx;
+    float* __restrict__ dy = I.dy;
+    const float s2 = I.s2;
+    constexpr int kU = 4;
+    for (int y = y0; y < y1; ++y) {
+        for (int x = threadIdx.x; x < W; x += kWave * kBatchWaves) {
+            const size_t o = static_cast<size_t>(y) * W + x;
+            const ptrdiff_t dl = (x > 0) ? 1 : 0;
+            const ptrdiff_t du = (y > 0) ? W : 0;
+            float ax = 0.f, ay = 0.f;
+            const float* g = guide + o;
+            int k = 0;
+            for (; k + kU <= Cg; k += kU) {
+                float v[kU], l[kU], u[kU];
+#pragma unroll
+                for (int q = 0; q < kU; ++q) {
+                    const float* gq = g + q * plane;
+                    v[q] = gq[0];
+                    l[q] = gq[-dl];
+                    u[q] = gq[-du];
+                }
+#pragma unroll
+                for (int q = 0; q < kU; ++q) {
+                    const float ex = v[q] - l[q];
+                    const float ey = v[q] - u[q];
+                    ax = fmaf(ex, ex, ax);
+                    ay = fmaf(ey, ey, ay);
+                }
+                g += kU * plane;
+            }
+            for (; k < Cg; ++k) {
+                const float v = g[0];
+                const float ex = v - g[-dl];
+                const float ey = v - g[-du];
+                ax = fmaf(ex, ex, ax);
+                ay = fmaf(ey, ey, ay);
+                g += plane;
+            }
+            dx[o] = sqrtf(fmaf(s2, ax, 1.f));
+            dy[o] = sqrtf(fmaf(s2, ay, 1.f));
+        }
+    }
+}
+
+// OCC: waves per SIMD the register allocation must allow (OCC workgroups per CU).
+template <int R, int CTM, int OCC>
+__global__ void __launch_bounds__(kWave * kBatchWaves) __attribute__((amdgpu_waves_per_eu(OCC, 8)))
+batched_kernel(BatchArgs a) {
     __shared__ ChunkLds<CTM, kBatchWaves> L;
     __shared__ RowLds RL;
     __shared__ int s_pre[kBatchMaxProblems + 1];
@@ -110,73 +217,76 @@ __global__ void __launch_bounds__(kWave * kBatchWaves) batched_kernel(BatchArgs 
             const int i = __builtin_amdgcn_readfirstlane(upper_index(s_pre, n + 1, t));
             const int tile = t - s_pre[i];
             const BInst& I = a.inst[i];
-            const int per_iter = 2 * I.N;
-            const int k = p / per_iter;
-            const int q = p % per_iter;
-            const int fi = q / 2 + 1;  // filter iteration 1..N
-            const float* zk = (k == 0) ? I.target : I.out;
-            if ((q & 1) == 0) {
+            if (p == 0) {
                 if (threadIdx.x == 0) nxt = atomicAdd(tickets, 1u);
-                RowArgs ra;
-                ra.src = (fi == 1) ? zk : I.tmp;
-                ra.dst = I.tmp;
-                ra.d = I.dx;
-                ra.guide = I.guide;
-                ra.dx_out = I.dx;
-                ra.dy_out = I.dy;
-                ra.Cg = I.Cg;
-                ra.s2 = I.s2;
-                ra.C = I.Ct;
-                ra.H = I.H;
-                ra.W = I.W;
-                ra.log2a = I.log2a[fi - 1];
-                const int y0 = tile * I.row_rows;
-                const int y1 = min(I.H, y0 + I.row_rows);
-                const bool dist = (k == 0 && fi == 1);
-                if (I.row_S == 8) {
-                    if (dist) row_band<8, true>(ra, y0, y1, I.row_gw, RL);
-                    else row_band<8, false>(ra, y0, y1, I.row_gw, RL);
-                } else {
-                    if (dist) row_band<16, true>(ra, y0, y1, I.row_gw, RL);
-                    else row_band<16, false>(ra, y0, y1, I.row_gw, RL);
-                }
+                const int y0 = tile * I.dist_rows;
+                dist_band(I, y0, min(I.H, y0 + I.dist_rows));
+                __syncthreads();  // every wave has read s_t
             } else {
-                ColArgs ca;
-                const bool epi = (fi == I.N);
-                ca.src = I.tmp;
-                ca.dst = epi ? I.out : I.tmp;
-                ca.d = I.dy;
-                ca.C = I.Ct;
-                ca.H = I.H;
-                ca.W = I.W;
-                ca.log2a = I.log2a[fi - 1];
-                ca.G = I.G;
-                ca.S = I.S;
-                ca.NG = I.NG;
-                ca.batch = 1;
-                ca.groups = 1;
-                ca.carry = I.carry;
-                ca.epoch = launch * static_cast<unsigned>(a.n_phases + 1) + static_cast<unsigned>(p) + 1u;
-                ca.status = a.status;
-                ca.zk = zk;
-                ca.tgt = I.target;
-                ca.conf = I.conf;
-                ca.Cc = I.Cc;
-                ca.dst2 = nullptr;
-                ca.lambda = a.lambda;
-                ca.step = a.step;
-                const CarryCtx cctx{ca.carry, ca.epoch, ca.status, ca.G, ca.S, ca.NG};
-                const int chunk = tile % I.G;
-                const int rest = tile / I.G;
-                const int strip = rest % I.S;
-                const int grp = rest / I.S;
-                auto take_next = [&]() {
+                const int pass = p - 1;
+                const int per_iter = 2 * I.N;
+                const int k = pass / per_iter;
+                const int q = pass % per_iter;
+                const int fi = q / 2 + 1;  // filter iteration 1..N
+                const float* zk = (k == 0) ? I.target : I.out;
+                if ((q & 1) == 0) {
                     if (threadIdx.x == 0) nxt = atomicAdd(tickets, 1u);
-                };
-                if (epi) col_tile<CTM, R, kBatchWaves, true>(ca, cctx, L, chunk, strip, grp, 0, take_next);
-                else col_tile<CTM, R, kBatchWaves, false>(ca, cctx, L, chunk, strip, grp, 0, take_next);
+                    RowArgs ra;
+                    ra.src = (fi == 1) ? zk : I.tmp;
+                    ra.dst = I.tmp;
+                    ra.d = I.dx;
+                    ra.guide = nullptr;
+                    ra.dx_out = nullptr;
+                    ra.dy_out = nullptr;
+                    ra.Cg = I.Cg;
+                    ra.s2 = I.s2;
+                    ra.C = I.Ct;
+                    ra.H = I.H;
+                    ra.W = I.W;
+                    ra.log2a = I.log2a[fi - 1];
+                    const int y0 = tile * I.row_rows;
+                    const int y1 = min(I.H, y0 + I.row_rows);
+                    if (I.row_S == 8) row_band<8>(ra, y0, y1, I.row_gw, RL);
+                    else row_band<16>(ra, y0, y1, I.row_gw, RL);
+                    __syncthreads();  // every wave has read s_t
+                } else {
+                    ColArgs ca;
+                    const bool epi = (fi == I.N);
+                    ca.src = I.tmp;
+                    ca.dst = epi ? I.out : I.tmp;
+                    ca.d = I.dy;
+                    ca.C = I.Ct;
+                    ca.H = I.H;
+                    ca.W = I.W;
+                    ca.log2a = I.log2a[fi - 1];
+                    ca.G = I.G;
+                    ca.S = I.S;
+                    ca.NG = I.NG;
+                    ca.batch = 1;
+                    ca.groups = 1;
+                    ca.carry = I.carry;
+                    ca.epoch = launch * static_cast<unsigned>(a.n_phases + 1) + static_cast<unsigned>(p) + 1u;
+                    ca.status = a.status;
+                    ca.zk = zk;
+                    ca.tgt = I.target;
+                    ca.conf = I.conf;
+                    ca.Cc = I.Cc;
+                    ca.dst2 = nullptr;
+                    ca.lambda = a.lambda;
+                    ca.step = a.step;
+                    const CarryCtx cctx{ca.carry, ca.epoch, ca.status, ca.G, ca.S, ca.NG};
+                    const int chunk = tile % I.G;
+                    const int rest = tile / I.G;
+                    const int strip = rest % I.S;
+                    const int grp = rest / I.S;
+                    auto take_next = [&]() {
+                        if (threadIdx.x == 0) nxt = atomicAdd(tickets, 1u);
+                    };
+                    if (epi) col_tile<CTM, R, kBatchWaves, true>(ca, cctx, L, chunk, strip, grp, 0, take_next);
+                    else col_tile<CTM, R, kBatchWaves, false>(ca, cctx, L, chunk, strip, grp, 0, take_next);
+                }
             }
-            // every wave has read s_t (at least one barrier of the tile lies between)
+            // every wave has read s_t (a barrier of the tile lies in between)
             if (threadIdx.x == 0) s_t = nxt;
             __syncthreads();
             t = static_cast<int>(__builtin_amdgcn_readfirstlane(s_t));
@@ -206,12 +316,12 @@ struct BatchVariant {
     int (*capacity)();
 };
 
-template <int R, int CTM>
+template <int R, int CTM, int OCC>
 static void batched_launch_v(const BatchArgs& a, unsigned grid, hipStream_t s) {
-    hipLaunchKernelGGL((batched_kernel<R, CTM>), dim3(grid), dim3(kWave * kBatchWaves), 0, s, a);
+    hipLaunchKernelGGL((batched_kernel<R, CTM, OCC>), dim3(grid), dim3(kWave * kBatchWaves), 0, s, a);
 }
 
-template <int R, int CTM>
+template <int R, int CTM, int OCC>
 static int batched_capacity_v() {
     static int cached[64] = {0};
     static std::mutex mu;
@@ -220,7 +330,7 @@ static int batched_capacity_v() {
     std::lock_guard<std::mutex> lock(mu);
     if (cached[dev] == 0) {
         int per_cu = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_kernel<R, CTM>,
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_kernel<R, CTM, OCC>,
                                                          kWave * kBatchWaves, 0) != hipSuccess)
             return 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
@@ -230,10 +340,10 @@ static int batched_capacity_v() {
     return cached[dev];
 }
 
-#define DTS_BV(R, CT, PX) {R, CT, PX, batched_launch_v<R, CT>, batched_capacity_v<R, CT>}
+#define DTS_BV(R, CT, OCC, PX) {R, CT, PX, batched_launch_v<R, CT, OCC>, batched_capacity_v<R, CT, OCC>}
 static const BatchVariant kBatchVariants[] = {
-    DTS_BV(16, 1, 16384), DTS_BV(32, 1, 16384), DTS_BV(16, 3, 16384), DTS_BV(8, 3, 16384),
-    DTS_BV(16, 1, 65536), DTS_BV(32, 1, 65536), DTS_BV(16, 3, 65536),
+    DTS_BV(32, 1, 3, 16384), DTS_BV(16, 1, 3, 16384), DTS_BV(16, 2, 3, 16384), DTS_BV(8, 3, 3, 16384),
+    DTS_BV(16, 3, 2, 16384), DTS_BV(32, 1, 3, 65536), DTS_BV(16, 2, 3, 65536),
 };
 #undef DTS_BV
 constexpr int kNumBatchVariants = sizeof(kBatchVariants) / sizeof(kBatchVariants[0]);
@@ -256,7 +366,7 @@ constexpr size_t kBAlign = 256;
 size_t bal(size_t v) { return (v + kBAlign - 1) / kBAlign * kBAlign; }
 
 struct Geo {
-    int row_S, row_gw, row_rows, G, S, NG, rows_tiles, col_tiles, phases;
+    int row_S, row_gw, row_rows, dist_rows, dist_tiles, G, S, NG, rows_tiles, col_tiles, phases;
     size_t dx, dy, tmp, carry, carry_bytes;
 };
 }  // namespace
@@ -278,22 +388,30 @@ static int check_problem(const dts_problem& q) {
 
 static Geo geometry(const dts_problem& q, const BatchVariant& v) {
     Geo g{};
-    g.row_S = q.W <= 512 ? 8 : 16;
-    const int waves = (q.W + kWave * g.row_S - 1) / (kWave * g.row_S);
-    g.row_gw = 1;
-    while (g.row_gw < waves) g.row_gw *= 2;
+    if (q.W <= kBatchSoloWidth) {
+        g.row_S = q.W <= 512 ? 8 : 16;
+        g.row_gw = 1;
+    } else {
+        g.row_S = 16;
+        const int waves = (q.W + kBatchSoloWidth - 1) / kBatchSoloWidth;
+        g.row_gw = 1;
+        while (g.row_gw < waves) g.row_gw *= 2;
+    }
     const int side = kBatchWaves / g.row_gw;  // rows processed side by side
     const long long per_round = static_cast<long long>(q.W) * q.Ct * side;
     long long rounds = (v.row_px + per_round - 1) / per_round;
     rounds = std::max(1LL, std::min(rounds, static_cast<long long>(std::max(1, 64 / side))));
     g.row_rows = static_cast<int>(rounds) * side;
+    const long long dist_row = static_cast<long long>(q.W) * q.Cg;
+    g.dist_rows = static_cast<int>(std::max(1LL, std::min(256LL, (4LL * v.row_px + dist_row - 1) / dist_row)));
+    g.dist_tiles = (q.H + g.dist_rows - 1) / g.dist_rows;
     const int rows = v.R * kBatchWaves;
     g.G = (q.H + rows - 1) / rows;
     g.S = (q.W + kWave - 1) / kWave;
     g.NG = (q.Ct + v.ctm - 1) / v.ctm;
     g.rows_tiles = (q.H + g.row_rows - 1) / g.row_rows;
     g.col_tiles = g.NG * g.S * g.G;
-    g.phases = 2 * q.filter_iters * q.solver_iters;
+    g.phases = 1 + 2 * q.filter_iters * q.solver_iters;  // distances, then the passes
     return g;
 }
 
@@ -313,8 +431,8 @@ static int make_batch_layout(const dts_problem* probs, int n, const BatchVariant
         L.geo[i] = geometry(probs[i], v);
         L.n_phases = std::max(L.n_phases, L.geo[i].phases);
         L.max_G = std::max(L.max_G, L.geo[i].G);
-        tiles += static_cast<long long>(probs[i].filter_iters) * probs[i].solver_iters *
-                 (L.geo[i].rows_tiles + L.geo[i].col_tiles);
+        tiles += L.geo[i].dist_tiles + static_cast<long long>(probs[i].filter_iters) *
+                                           probs[i].solver_iters * (L.geo[i].rows_tiles + L.geo[i].col_tiles);
     }
     if (tiles > (1LL << 30)) return DTS_ENOTSUP;
     L.total_tiles = static_cast<int>(tiles);
@@ -409,6 +527,7 @@ int dts_batched_prepare(const dts_problem* probs, int n, float lambda, float ste
         I.row_S = g.row_S;
         I.row_gw = g.row_gw;
         I.row_rows = g.row_rows;
+        I.dist_rows = g.dist_rows;
         I.G = g.G;
         I.S = g.S;
         I.NG = g.NG;
@@ -431,7 +550,8 @@ int dts_batched_prepare(const dts_problem* probs, int n, float lambda, float ste
             const Geo& g = L.geo[i];
             pre[static_cast<size_t>(p) * (n + 1) + i] = local;
             int tiles = 0;
-            if (p < g.phases) tiles = (p & 1) ? g.col_tiles : g.rows_tiles;
+            if (p == 0) tiles = g.dist_tiles;
+            else if (p < g.phases) tiles = ((p - 1) & 1) ? g.col_tiles : g.rows_tiles;
             local += tiles;
         }
         pre[static_cast<size_t>(p) * (n + 1) + n] = local;

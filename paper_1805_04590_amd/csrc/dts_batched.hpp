@@ -4,8 +4,9 @@
 namespace dts {
 
 constexpr int kBatchMaxN = 8;          // filter iterations per instance
-constexpr int kBatchWaves = 8;         // waves per workgroup of the batched kernel
-constexpr int kBatchMaxWidth = kBatchWaves * 64 * 16;
+constexpr int kBatchWaves = 4;         // waves per workgroup of the batched kernel
+constexpr int kBatchSoloWidth = 64 * 16;              // widest row one wave filters alone
+constexpr int kBatchMaxWidth = kBatchWaves * kBatchSoloWidth;
 constexpr int kBatchMaxProblems = 1024;
 
 struct BInst {
@@ -19,8 +20,9 @@ struct BInst {
     unsigned long long* carry;
     int H, W, Cg, Ct, Cc, N, T;
     int row_S;       // pixels per lane of a row (8 or 16)
-    int row_gw;      // waves per row (1, 2, 4 or 8); 8 / row_gw rows side by side
-    int row_rows;    // rows per row tile (a multiple of 8 / row_gw)
+    int row_gw;      // waves per row (1, 2 or 4); kBatchWaves / row_gw rows side by side
+    int row_rows;    // rows per row tile (a multiple of kBatchWaves / row_gw)
+    int dist_rows;   // rows per tile of the distance phase
     int G, S, NG;    // column chunks per strip, strips, channel groups
     float s2;
     float log2a[kBatchMaxN];

@@ -30,6 +30,16 @@ __device__ __forceinline__ float weight(float d, float log2a) { return exp2_fast
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 
+// Workgroups of a dispatch go to the 8 XCDs in turn (workgroup b to XCD b % 8), and each
+// XCD has its own L2.  This bijection of [0, n) gives XCD x a contiguous band of indices,
+// visited in order, so neighbouring rows meet in the same L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_band_index(int b, int n) {
+    const int q = n / kXcds, r = n % kXcds;
+    const int x = b % kXcds, j = b / kXcds;
+    return x * q + min(x, r) + j;
+}
+
 // Inclusive scan of affine maps from lane 0 upwards: lane l ends with the composition of
 // the maps of lanes 0..l (lane l's map applied last).
 __device__ __forceinline__ void scan_maps_up(float& a, float& b, int lane) {

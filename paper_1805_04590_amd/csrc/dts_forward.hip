@@ -32,7 +32,10 @@ namespace dts {
 // ---------------------------------------------------------------------------------------
 template <int S, bool DIST>
 __global__ void __launch_bounds__(1024) row_pass_kernel(RowArgs a) {
-    row_tile<S, DIST>(a, blockIdx.x, blockIdx.y);
+    // the fused distance pass reads each guide row twice (as row y and as the row above
+    // row y + 1): XCD bands keep the second read in L2
+    const int y = DIST ? xcd_band_index(blockIdx.x, gridDim.x) : static_cast<int>(blockIdx.x);
+    row_tile<S, DIST>(a, y, blockIdx.y);
 }
 
 template <int S, bool DIST>

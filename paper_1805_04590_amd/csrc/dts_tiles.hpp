@@ -65,6 +65,45 @@ __device__ __forceinline__ void store_seg(float* row, int n0, int W, bool vec, c
     }
 }
 
+// Both directions of the recurrence over one row held by one wave (lane l owns pixels
+// [l S, (l+1) S)), in registers: w[e] links pixel e to the one before it, wlast links
+// the lane's last pixel to the next lane's first (0 for lane 63).  f is replaced by K.
+template <int S>
+__device__ __forceinline__ void row_filter_solo(const float (&w)[S], float wlast, float (&f)[S], int lane) {
+    float la = 1.f, lb = 0.f;
+#pragma unroll
+    for (int e = 0; e < S; ++e) {
+        lb = fmaf(w[e], lb - f[e], f[e]);
+        la *= w[e];
+    }
+    scan_up_dpp(la, lb, lane);
+    const float xa = __shfl_up(la, 1), xb = __shfl_up(lb, 1);
+    float j = (lane == 0) ? 0.f : xb;
+    (void)xa;
+#pragma unroll
+    for (int e = 0; e < S; ++e) {
+        j = fmaf(w[e], j - f[e], f[e]);
+        f[e] = j;
+    }
+    la = 1.f;
+    lb = 0.f;
+#pragma unroll
+    for (int e = S - 1; e >= 0; --e) {
+        const float wn = (e == S - 1) ? wlast : w[e < S - 1 ? e + 1 : e];
+        lb = fmaf(wn, lb - f[e], f[e]);
+        la *= wn;
+    }
+    scan_down_dpp(la, lb, lane);
+    const float yb = __shfl_down(lb, 1);
+    float k = (lane == kWave - 1) ? 0.f : yb;
+#pragma unroll
+    for (int e = S - 1; e >= 0; --e) {
+        const float wn = (e == S - 1) ? wlast : w[e < S - 1 ? e + 1 : e];
+        k = fmaf(wn, k - f[e], f[e]);
+        f[e] = k;
+    }
+}
+
 // One image row processed by a group of `nw` waves of the workgroup; lane l of group wave
 // v owns the S consecutive pixels starting at (64 v + l) S.  Per direction: a serial
 // composition of the lane's S maps, one 64-lane scan, one exchange of wave totals through
@@ -72,7 +111,10 @@ __device__ __forceinline__ void store_seg(float* row, int n0, int W, bool vec, c
 // produces the final values.  Every wave of the workgroup must call it the same number of
 // times (it holds workgroup barriers); a group with `live` false reads and writes no
 // pixel.
-template <int S, bool DIST>
+//
+// SOLO: the row belongs to one wave alone (nw = 1): no LDS, no barrier, and the waves of
+// a workgroup may call it independently.
+template <int S, bool DIST, bool SOLO = false>
 __device__ __forceinline__ void row_line(const RowArgs& a, int y, int b, int wave, int nw, bool live,
                                          float2* fagg, float2* bagg, float* wfirst) {
     const int lane = lane_id();
@@ -129,11 +171,15 @@ __device__ __forceinline__ void row_line(const RowArgs& a, int y, int b, int wav
         }
     }
     // weight linking each lane's last pixel to the next pixel (0 past the end of the row)
-    if (lane == 0) wfirst[wave] = w[0];
-    if (wave == 0 && lane == 0) wfirst[nw] = 0.f;
-    __syncthreads();
     float wlast = __shfl_down(w[0], 1);
-    if (lane == kWave - 1) wlast = wfirst[wave + 1];
+    if constexpr (SOLO) {
+        if (lane == kWave - 1) wlast = 0.f;
+    } else {
+        if (lane == 0) wfirst[wave] = w[0];
+        if (wave == 0 && lane == 0) wfirst[nw] = 0.f;
+        __syncthreads();
+        if (lane == kWave - 1) wlast = wfirst[wave + 1];
+    }
 
     for (int c = 0; c < a.C; ++c) {
         const size_t roff = (static_cast<size_t>(b) * a.C + c) * plane + static_cast<size_t>(y) * W;
@@ -148,13 +194,15 @@ __device__ __forceinline__ void row_line(const RowArgs& a, int y, int b, int wav
             la *= w[e];
         }
         scan_up_dpp(la, lb, lane);
-        if (lane == kWave - 1) fagg[wave] = make_float2(la, lb);
         float xa = __shfl_up(la, 1), xb = __shfl_up(lb, 1);
-        __syncthreads();
         float jin = 0.f;
-        for (int u = 0; u < wave; ++u) {
-            const float2 g = fagg[u];
-            jin = fmaf(g.x, jin, g.y);
+        if constexpr (!SOLO) {
+            if (lane == kWave - 1) fagg[wave] = make_float2(la, lb);
+            __syncthreads();
+            for (int u = 0; u < wave; ++u) {
+                const float2 g = fagg[u];
+                jin = fmaf(g.x, jin, g.y);
+            }
         }
         float j = (lane == 0) ? jin : fmaf(xa, jin, xb);
 #pragma unroll
@@ -173,14 +221,16 @@ __device__ __forceinline__ void row_line(const RowArgs& a, int y, int b, int wav
             la *= wn;
         }
         scan_down_dpp(la, lb, lane);
-        if (lane == 0) bagg[wave] = make_float2(la, lb);
         xa = __shfl_down(la, 1);
         xb = __shfl_down(lb, 1);
-        __syncthreads();
         float kin = 0.f;
-        for (int u = nw - 1; u > wave; --u) {
-            const float2 g = bagg[u];
-            kin = fmaf(g.x, kin, g.y);
+        if constexpr (!SOLO) {
+            if (lane == 0) bagg[wave] = make_float2(la, lb);
+            __syncthreads();
+            for (int u = nw - 1; u > wave; --u) {
+                const float2 g = bagg[u];
+                kin = fmaf(g.x, kin, g.y);
+            }
         }
         float k = (lane == kWave - 1) ? kin : fmaf(xa, kin, xb);
 #pragma unroll

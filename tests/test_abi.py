@@ -127,3 +127,24 @@ def test_batched_variant_table(lib):
     assert len(seen) == n
     assert lib.dts_batched_variant_info(n, ctypes.byref(r), ctypes.byref(ct), ctypes.byref(px)) != 0
 
+
+def test_batched_rejects_unsupported_problems(lib):
+    """Host-side checks of dts_batched_workspace_bytes (nothing is dereferenced)."""
+    P = dts._Problem
+    fake = 0x10000
+
+    def table(**kw):
+        q = dict(H=64, W=64, Cg=3, Ct=1, Cc=1, sigma_s=8.0, sigma_r=0.2, filter_iters=3, solver_iters=2)
+        q.update(kw)
+        arr = (P * 1)()
+        arr[0] = P(fake, fake, fake, fake, q["H"], q["W"], q["Cg"], q["Ct"], q["Cc"], q["sigma_s"],
+                   q["sigma_r"], q["filter_iters"], q["solver_iters"])
+        return arr
+
+    assert lib.dts_batched_workspace_bytes(table(), 1, 0) > 0
+    assert lib.dts_batched_workspace_bytes(table(W=4096), 1, 0) > 0
+    for bad in (dict(W=4097), dict(filter_iters=9), dict(solver_iters=0), dict(Cc=2), dict(Ct=17),
+                dict(sigma_r=0.0), dict(H=0)):
+        assert lib.dts_batched_workspace_bytes(table(**bad), 1, 0) == 0, bad
+    assert lib.dts_batched_workspace_bytes(table(), 1, lib.dts_batched_variant_count()) == 0
+
