@@ -22,6 +22,41 @@ sys.path.insert(0, ROOT)
 
 METRIC = "DTS solve Mpixel/s & % of HBM peak; batched and fwd+bwd vs plain fwd"
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "solve_10240x10240_hbm_traffic.md")
+
+
+def sources_digest():
+    """SHA-256 over the library's sources: hardware-counter traffic recorded for one
+    digest is reported only while the kernels are unchanged."""
+    import hashlib
+
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1805_04590_amd", "csrc")
+    files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc) if f.endswith((".hip", ".hpp")))
+    for path in files + [os.path.join(ROOT, "include", "dts.h")]:
+        h.update(os.path.basename(path).encode())
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` measured with rocprofv3 FETCH_SIZE / WRITE_SIZE
+    (scaled by a plain copy of known size), or None when no record matches these sources."""
+    import re
+
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    m = re.search(r"<!-- traffic: (\{.*?\}) -->", text, flags=re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec.get("sources_sha256") != sources_digest():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("traffic_bytes")
 
 
 def parse():
@@ -34,6 +69,10 @@ def parse():
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel timing run")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched (64 uneven solves) and forward+backward legs")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="time the batched leg with direct launches instead of graph replays")
+    ap.add_argument("--no-solve", action="store_true",
+                    help="skip the single-image solve (for profiling the other legs alone)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first fill and copy a MIB-sized float32 buffer with torch: kernels of "
                          "known traffic that calibrate the hardware byte counters")
@@ -82,9 +121,10 @@ def timed(fn, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
-def batched_leg(steps, warmup):
-    """64 uneven solves: one graph-captured persistent launch against the same solves
-    run one by one through dts_solve (workspaces preallocated)."""
+def batched_leg(steps, warmup, graph=True):
+    """64 uneven solves: one graph-captured persistent launch (graph=False: the launch
+    made directly) against the same solves run one by one through dts_solve (workspaces
+    preallocated)."""
     import ctypes
 
     import torch
@@ -99,8 +139,7 @@ def batched_leg(steps, warmup):
                   filter_iters=3, solver_iters=10) for c in cases]
     px = sum(c["target"].shape[1] * c["target"].shape[2] for c in cases)
     bs = dts.BatchedSolver(probs)  # autotuned variant
-    graph = bs.capture()
-    ms_b = timed(graph.replay, steps, warmup)
+    ms_b = timed(bs.capture().replay if graph else bs.run, steps, warmup)
     bs.status()
     outs = [torch.empty_like(q["target"]) for q in probs]
     wss = []
@@ -118,7 +157,7 @@ def batched_leg(steps, warmup):
     ms_s = timed(seq, steps, warmup)
     err = max((o - b).abs().max().item() for o, b in zip(outs, bs.outputs))
     return dict(workload="64 uneven solves 320-1920 x 240-1080, Cg in {1,3,8,16}, Ct 1-3, T=10",
-                pixels=px, variant=bs.variant, batched_ms=round(ms_b, 3),
+                pixels=px, variant=bs.variant, launch="hip graph replay" if graph else "direct", batched_ms=round(ms_b, 3),
                 batched_mpix_s=round(px / ms_b / 1e3, 1), sequential_ms=round(ms_s, 3),
                 sequential_mpix_s=round(px / ms_s / 1e3, 1), speedup=round(ms_s / ms_b, 3),
                 max_abs_diff=err)
@@ -170,30 +209,16 @@ def fwd_bwd_leg(steps, warmup):
                 fwd_bwd_over_fwd=round(ms_fb / ms_f, 3))
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the solve is not "
-              "sharded across GPUs in this build.", file=sys.stderr)
-        sys.exit(2)
+def solve_leg(args, dev):
+    """The headline workload: Mpixel/s of dts_solve and, unless --no-profile, the per-kernel
+    timing (HIP events around every launch) and the dominant kernel's roofline."""
+    import ctypes
 
     import torch
 
     import dts_inputs
     import paper_1805_04590_amd as dts
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    dev = torch.device("cuda:0")
-    if args.calibrate_copy > 0:
-        n = args.calibrate_copy * (1 << 20) // 4
-        a = torch.ones(n, dtype=torch.float32, device=dev)  # writes 4n bytes
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)  # reads 4n, writes 4n bytes
-        torch.cuda.synchronize()
-        log(f"calibration: fill and 3 copies of {4 * n} bytes")
-        del a, b
-        torch.cuda.empty_cache()
     H, W, Cg = dts_inputs.config3_shape()
     t0 = time.time()
     log(f"generating the {W}x{H}x{Cg} workload ...")
@@ -207,7 +232,6 @@ def main():
     T, N = case["solver_iters"], case["filter_iters"]
     ss, sr = case["sigma_s"], case["sigma_r"]
     lib = dts.library()
-    import ctypes
     p = dts.Params(ss, sr, N, T).c()
     ws = torch.empty(lib.dts_solve_workspace_bytes(1, H, W, Ct, ctypes.byref(p)),
                      dtype=torch.uint8, device=dev)
@@ -259,16 +283,44 @@ def main():
         s = stats[dom]
         achieved = s["bytes_per_launch"] / (s["avg_ms"] / 1e3) / 1e9
         roofline = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=HBM_PEAK_GBPS,
-                        unit="GB/s", frac=round(achieved / HBM_PEAK_GBPS, 4), traffic=None,
+                        unit="GB/s", frac=round(achieved / HBM_PEAK_GBPS, 4),
+                        traffic=recorded_traffic(dom),
                         bytes_per_launch=s["bytes_per_launch"], avg_us=round(s["avg_ms"] * 1e3, 2))
         log("  " + json.dumps(kernels))
 
+    del guide, target, conf, out, ws
+    torch.cuda.empty_cache()
+    return dict(ms=ms, mpix=mpix, solve_bytes=solve_bytes, kernels=kernels, roofline=roofline,
+                H=H, W=W, Cg=Cg, Ct=Ct, T=T, N=N, ss=ss, sr=sr)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the solve is not "
+              "sharded across GPUs in this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    if args.calibrate_copy > 0:
+        n = args.calibrate_copy * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)  # writes 4n bytes
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)  # reads 4n, writes 4n bytes
+        torch.cuda.synchronize()
+        log(f"calibration: fill and 3 copies of {4 * n} bytes")
+        del a, b
+        torch.cuda.empty_cache()
+    sol = None if args.no_solve else solve_leg(args, dev)
+
     extras = {}
     if not args.no_extras:
-        del guide, target, conf, out, ws
-        torch.cuda.empty_cache()
         log("batched leg (64 uneven solves) ...")
-        extras["batched"] = batched_leg(max(3, args.steps // 2), 2)
+        extras["batched"] = batched_leg(max(3, args.steps // 2), 2, graph=not args.no_graph)
         log("  " + json.dumps(extras["batched"]))
         torch.cuda.empty_cache()
         log("forward+backward leg (8 x 1024^2, T=15) ...")
@@ -282,29 +334,35 @@ def main():
         log(f"  {cpu['value']:.3f} Mpixel/s in {cpu['seconds']:.1f} s")
         cpu.pop("seconds")
 
+    if sol is None:
+        sol = dict(ms=None, mpix=None, solve_bytes=None, kernels={}, roofline=None, H=None, W=None,
+                   Cg=None, Ct=None, T=None, N=None, ss=None, sr=None)
+    ms, mpix = sol["ms"], sol["mpix"]
+    gbps = None if ms is None else sol["solve_bytes"] / (ms / 1e3) / 1e9
     res = {
         "metric": METRIC,
-        "value": round(mpix, 2),
+        "value": None if mpix is None else round(mpix, 2),
         "unit": "Mpixel/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms, 4),
+        "ms_per_step": None if ms is None else round(ms, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"multispectral solve {W}x{H}, {Cg}-band guide, {Ct}-channel target, "
-                        f"sigma_s={ss}, sigma_r={sr}, N={N} filter iterations, T={T}",
-            "H": H, "W": W, "Cg": Cg, "Ct": Ct, "T": T, "N": N,
+            "workload": f"multispectral solve {sol['W']}x{sol['H']}, {sol['Cg']}-band guide, "
+                        f"{sol['Ct']}-channel target, sigma_s={sol['ss']}, sigma_r={sol['sr']}, "
+                        f"N={sol['N']} filter iterations, T={sol['T']}",
+            "H": sol["H"], "W": sol["W"], "Cg": sol["Cg"], "Ct": sol["Ct"], "T": sol["T"], "N": sol["N"],
         },
-        "solve_algorithmic_GBps": round(solve_bytes / (ms / 1e3) / 1e9, 1),
-        "solve_hbm_frac": round(solve_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
-        "roofline": roofline,
+        "solve_algorithmic_GBps": None if gbps is None else round(gbps, 1),
+        "solve_hbm_frac": None if gbps is None else round(gbps / HBM_PEAK_GBPS, 4),
+        "roofline": sol["roofline"],
         "cpu_baseline": cpu,
-        "kernels": kernels,
+        "kernels": sol["kernels"],
     }
     res.update(extras)
     print(json.dumps(res), flush=True)
