@@ -51,6 +51,7 @@ __all__ = [
     "energy_e2",
     "residual",
     "dense_filter_matrix",
+    "variance_confidence",
 ]
 
 
@@ -346,3 +347,26 @@ def dense_filter_matrix(dx, dy, sigma_s, filter_iters=3):
         e.flat[j] = 1.0
         A[:, j] = dt_filter(e, dx, dy, sigma_s, filter_iters).ravel()
     return A
+
+
+# ----------------------------------------------------------------------------------------
+# Eq. (7): variance-based confidence (Sec. 3.1), computed from an input before a solve
+# ----------------------------------------------------------------------------------------
+def variance_confidence(guide, z, sigma_s, sigma_r, sigma_c, filter_iters=3, dists=None):
+    """Edge-aware variance of z and the confidence derived from it (Eq. (7)):
+
+        V = DT(z^2) - DT(z)^2,      c = exp(-V / (2 sigma_c^2)),
+
+    where DT is the same domain-transform mean the solver uses (guided by ``guide``),
+    read as a local edge-aware estimate of the mean.  z [C][H][W] gives C confidence
+    channels.  V is not clipped: rounding can make it slightly negative.
+    Returns (c, V)."""
+    zz = np.asarray(z, dtype=np.float64)
+    if dists is None:
+        dists = distances(guide, sigma_s, sigma_r)
+    dx, dy = dists
+    m1 = dt_filter(zz, dx, dy, sigma_s, filter_iters)
+    m2 = dt_filter(zz * zz, dx, dy, sigma_s, filter_iters)
+    V = m2 - m1 * m1
+    return np.exp(-V / (2.0 * float(sigma_c) ** 2)), V
+

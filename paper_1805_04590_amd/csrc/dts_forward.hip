@@ -184,7 +184,7 @@ static int col_variant(int C) {
     if (pin >= 0 && pin < kNumColVariants && kColVariants[pin].ct == ct) return pin;
     switch (ct) {
         case 1: return 0;
-        case 2: return 5;
+        case 2: return 6;
         case 3: return 7;
         default: return 9;
     }
