@@ -288,10 +288,30 @@ def solve_leg(args, dev):
                         bytes_per_launch=s["bytes_per_launch"], avg_us=round(s["avg_ms"] * 1e3, 2))
         log("  " + json.dumps(kernels))
 
-    del guide, target, conf, out, ws
+    # Eq. (7): confidence from the edge-aware variance of the target, same guide
+    sc = 0.05
+    wsv = torch.empty(lib.dts_variance_confidence_workspace_bytes(1, H, W, Ct), dtype=torch.uint8,
+                      device=dev)
+    confv = torch.empty_like(target)
+
+    def vstep():
+        dts.variance_confidence(guide, target, ss, sr, sc, N, out=confv, workspace=wsv)
+
+    ms_v = timed(vstep, args.steps, args.warmup)
+    dts.workspace_status(wsv)
+    # first row pass: z in, (z, z^2) out, guide in, dx and dy out; 2N - 1 further passes over
+    # the pairs; the confidence kernel reads the pairs and writes the confidences
+    v_bytes = px * (4 * (3 * Ct + Cg + 2) + (2 * N - 1) * 4 * (4 * Ct + 1) + 12 * Ct)
+    variance = dict(workload=f"variance confidence (Eq. 7) of the {W}x{H} target, {Cg}-band guide, "
+                             f"sigma_c={sc}, N={N}",
+                    ms=round(ms_v, 3), mpix_s=round(px / ms_v / 1e3, 1),
+                    algorithmic_GBps=round(v_bytes / (ms_v / 1e3) / 1e9, 1),
+                    hbm_frac=round(v_bytes / (ms_v / 1e3) / 1e9 / HBM_PEAK_GBPS, 4))
+    log("  variance confidence: " + json.dumps(variance))
+    del guide, target, conf, out, ws, wsv, confv
     torch.cuda.empty_cache()
     return dict(ms=ms, mpix=mpix, solve_bytes=solve_bytes, kernels=kernels, roofline=roofline,
-                H=H, W=W, Cg=Cg, Ct=Ct, T=T, N=N, ss=ss, sr=sr)
+                H=H, W=W, Cg=Cg, Ct=Ct, T=T, N=N, ss=ss, sr=sr, variance=variance)
 
 
 def main():
@@ -336,7 +356,7 @@ def main():
 
     if sol is None:
         sol = dict(ms=None, mpix=None, solve_bytes=None, kernels={}, roofline=None, H=None, W=None,
-                   Cg=None, Ct=None, T=None, N=None, ss=None, sr=None)
+                   Cg=None, Ct=None, T=None, N=None, ss=None, sr=None, variance=None)
     ms, mpix = sol["ms"], sol["mpix"]
     gbps = None if ms is None else sol["solve_bytes"] / (ms / 1e3) / 1e9
     res = {
@@ -363,6 +383,7 @@ def main():
         "roofline": sol["roofline"],
         "cpu_baseline": cpu,
         "kernels": sol["kernels"],
+        "variance": sol["variance"],
     }
     res.update(extras)
     print(json.dumps(res), flush=True)

@@ -96,6 +96,22 @@ int dts_solve_backward(const float* guide, int Cg, const float* target, const fl
                        float* grad_conf, float* grad_guide, void* workspace,
                        size_t workspace_bytes, void* stream);
 
+/* ---- Variance-based confidence (Eq. (7), Sec. 3.1) ---- */
+
+/* Workspace for dts_variance_confidence (0 if the arguments are invalid). */
+size_t dts_variance_confidence_workspace_bytes(int batch, int H, int W, int C);
+
+/* Confidence from the edge-aware variance of z (Eq. (7)): V = DT(z^2) - DT(z)^2 with DT the
+ * same domain-transform mean dts_filter computes (guide, sigma_s, sigma_r, filter_iters),
+ * and conf = exp(-V / (2 sigma_c^2)), per channel.  z [batch][C][H][W] (1 <= C <= 8),
+ * conf the same shape; conf may alias z.  V is used as computed: rounding can make it
+ * slightly negative and conf slightly above 1.  The pairs (z, z^2) are filtered
+ * together: the squaring happens in the first row pass and the workspace holds the 2C
+ * filtered planes.  Errors as dts_filter; sigma_c must be finite and positive. */
+int dts_variance_confidence(const float* guide, int Cg, const float* z, float* conf, int C, int batch,
+                            int H, int W, float sigma_s, float sigma_r, int filter_iters, float sigma_c,
+                            void* workspace, size_t workspace_bytes, void* stream);
+
 /* ---- Many uneven solves in one persistent launch ---- */
 
 /* One independent solve: device pointers, shape and parameters (1 <= T, 1 <= N <= 8,

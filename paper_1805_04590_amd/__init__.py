@@ -9,6 +9,7 @@ is missing or a tensor is not on the GPU.
 
 Entry points (same names as the C ABI):
   filter(guide, src, sigma_s, sigma_r, filter_iters=3)           edge-aware mean DT(src)
+  variance_confidence(guide, z, sigma_s, sigma_r, sigma_c)        Eq. (7) confidence
   solve(guide, target, conf, sigma_s, sigma_r, ...)               Eq. (3) gradient descent
   solve_backward(guide, target, conf, checkpoints, grad_out, ...) adjoint of solve
   DTSFunction.apply(guide, target, conf, params)                  autograd wrapper
@@ -28,6 +29,7 @@ __all__ = [
     "library",
     "library_path",
     "filter",
+    "variance_confidence",
     "solve",
     "solve_backward",
     "DTSFunction",
@@ -65,6 +67,8 @@ EXPORTED_SYMBOLS = (
     "dts_workspace_status",
     "dts_strerror",
     "dts_last_hip_error",
+    "dts_variance_confidence_workspace_bytes",
+    "dts_variance_confidence",
     "dts_distances",
     "dts_pass_workspace_bytes",
     "dts_row_pass",
@@ -190,6 +194,10 @@ def library():
     lib.dts_solve_backward.argtypes = [fp, i, fp, fp, i, i, i, i, i, P, fp, fp, fp, fp, fp,
                                        vp, sz, vp]
     lib.dts_solve_backward.restype = i
+    lib.dts_variance_confidence_workspace_bytes.argtypes = [i, i, i, i]
+    lib.dts_variance_confidence_workspace_bytes.restype = sz
+    lib.dts_variance_confidence.argtypes = [fp, i, fp, fp, i, i, i, i, f, f, i, f, vp, sz, vp]
+    lib.dts_variance_confidence.restype = i
     lib.dts_distances.argtypes = [fp, i, i, i, i, f, f, fp, fp, vp]
     lib.dts_distances.restype = i
     lib.dts_pass_workspace_bytes.argtypes = [i, i, i, i]
@@ -472,6 +480,30 @@ def filter(guide, src, sigma_s, sigma_r, filter_iters=3, out=None, workspace=Non
                         _stream())
     _check(rc, "dts_filter")
     return out if src.dim() == 4 else out[0]
+
+
+def variance_confidence(guide, z, sigma_s, sigma_r, sigma_c, filter_iters=3, out=None, workspace=None):
+    """Confidence from the edge-aware variance of z (Eq. (7)): exp(-(DT(z^2) - DT(z)^2) /
+    (2 sigma_c^2)) per channel, DT guided by ``guide`` as in ``filter``.  ``out`` may be z."""
+    g = _as4d(guide, "guide")
+    x = _as4d(z, "z")
+    B, C, H, W = x.shape
+    if g.shape[0] != B or g.shape[2:] != x.shape[2:]:
+        raise ValueError("guide and z disagree in batch or image size")
+    lib = library()
+    out = torch.empty_like(x) if out is None else _as4d(out, "out")
+    if out.shape != x.shape:
+        raise ValueError("out must have the shape of z")
+    if workspace is None:
+        nbytes = lib.dts_variance_confidence_workspace_bytes(B, H, W, C)
+        if nbytes == 0:
+            raise DTSError(DTS_EINVAL, "dts_variance_confidence_workspace_bytes")
+        workspace = _workspace(nbytes, x.device)
+    rc = lib.dts_variance_confidence(_ptr(g), g.shape[1], _ptr(x), _ptr(out), C, B, H, W,
+                                     float(sigma_s), float(sigma_r), int(filter_iters),
+                                     float(sigma_c), _ptr(workspace), workspace.numel(), _stream())
+    _check(rc, "dts_variance_confidence")
+    return out if z.dim() == 4 else out[0]
 
 
 def solve(guide, target, conf, sigma_s, sigma_r, filter_iters=3, solver_iters=10, lam=0.99,

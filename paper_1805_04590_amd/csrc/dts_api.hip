@@ -441,6 +441,59 @@ int dts_solve_backward(const float* guide, int Cg, const float* target, const fl
     return DTS_OK;
 }
 
+size_t dts_variance_confidence_workspace_bytes(int batch, int H, int W, int C) {
+    if (batch < 1 || H < 1 || W < 1 || C < 1 || 2 * C > DTS_MAX_CHANNELS) return 0;
+    return make_layout(batch, H, W, 2 * C, true).total;
+}
+
+int dts_variance_confidence(const float* guide, int Cg, const float* z, float* conf, int C, int batch,
+                            int H, int W, float sigma_s, float sigma_r, int filter_iters, float sigma_c,
+                            void* workspace, size_t workspace_bytes, void* stream) {
+    if (!guide || !z || !conf) return DTS_EINVAL;
+    int rc = check_shape(batch, H, W);
+    if (rc) return rc;
+    if (check_channels(Cg) || C < 1 || 2 * C > DTS_MAX_CHANNELS) return DTS_EINVAL;
+    if (!finite_pos(sigma_s) || !finite_pos(sigma_r) || !finite_pos(sigma_c)) return DTS_EINVAL;
+    if (filter_iters < 1 || filter_iters > kMaxFilterIters) return DTS_EINVAL;
+    Setup S;
+    rc = begin_call(S, workspace, workspace_bytes, batch, H, W, 2 * C, true, stream);
+    if (rc) return rc;
+    const float s2 = static_cast<float>((static_cast<double>(sigma_s) / sigma_r) *
+                                        (static_cast<double>(sigma_s) / sigma_r));
+    float* m = S.tmp;  // [batch][2C][H][W]: DT(z_c), DT(z_c^2) interleaved
+    for (int i = 1; i <= filter_iters; ++i) {
+        const float l2a = log2_feedback(sigma_s, i, filter_iters);
+        RowPass rp{};
+        rp.src = (i == 1) ? z : m;
+        rp.dst = m;
+        rp.d = S.dx;
+        rp.guide = (i == 1) ? guide : nullptr;
+        rp.dx_out = S.dx;
+        rp.dy_out = S.dy;
+        rp.Cg = Cg;
+        rp.s2 = s2;
+        rp.C = 2 * C;
+        rp.H = H;
+        rp.W = W;
+        rp.batch = batch;
+        rp.log2a = l2a;
+        rp.sq = (i == 1) ? 1 : 0;
+        if ((rc = launch_row_pass(rp, S.ctx))) return rc;
+        ColPass cp{};
+        cp.src = m;
+        cp.dst = m;
+        cp.d = S.dy;
+        cp.C = 2 * C;
+        cp.H = H;
+        cp.W = W;
+        cp.batch = batch;
+        cp.log2a = l2a;
+        cp.epilogue = false;
+        if ((rc = launch_col_pass(cp, S.ctx))) return rc;
+    }
+    return launch_variance_confidence(m, conf, C, batch, static_cast<size_t>(H) * W, sigma_c, S.ctx.stream);
+}
+
 int dts_distances(const float* guide, int Cg, int batch, int H, int W, float sigma_s,
                   float sigma_r, float* dx, float* dy, void* stream) {
     if (!guide || !dx || !dy) return DTS_EINVAL;

@@ -17,6 +17,7 @@
 // look-back resolves the causal carry from earlier chunks, then a look-ahead resolves the
 // anticausal carry from later chunks, so every element is read and written exactly once.
 #include <algorithm>
+#include <cmath>
 #include <mutex>
 
 #include "../../include/dts.h"
@@ -30,22 +31,25 @@ namespace dts {
 // ---------------------------------------------------------------------------------------
 // Row pass
 // ---------------------------------------------------------------------------------------
-template <int S, bool DIST>
+// SQ: the first pass of a variance (Eq. (7)): a.C output channels, the pairs z, z^2 of
+// a.C / 2 input channels.
+template <int S, bool DIST, bool SQ>
 __global__ void __launch_bounds__(1024) row_pass_kernel(RowArgs a) {
     // the fused distance pass reads each guide row twice (as row y and as the row above
     // row y + 1): XCD bands keep the second read in L2
     const int y = DIST ? xcd_band_index(blockIdx.x, gridDim.x) : static_cast<int>(blockIdx.x);
-    row_tile<S, DIST>(a, y, blockIdx.y);
+    row_tile<S, DIST, SQ>(a, y, blockIdx.y);
 }
 
-template <int S, bool DIST>
+template <int S, bool DIST, bool SQ = false>
 static void launch_row_t(const RowArgs& a, int nw, int batch, int H, hipStream_t s) {
     // algorithmic bytes: signal in and out (C planes), distances in -- or, on the fused
     // first pass, the guide in (Cg planes) and both distance planes out instead
     const double px = static_cast<double>(batch) * H * a.W;
-    const double bytes = DIST ? px * 4.0 * (2.0 * a.C + a.Cg + 2.0) : px * 4.0 * (2.0 * a.C + 1.0);
-    ProfScope prof(DIST ? "row_pass_dist" : "row_pass", bytes, s);
-    hipLaunchKernelGGL((row_pass_kernel<S, DIST>), dim3(H, batch), dim3(nw * kWave), 0, s, a);
+    const double cin = SQ ? 0.5 * a.C : a.C;  // planes read for a.C planes written
+    const double bytes = DIST ? px * 4.0 * (cin + a.C + a.Cg + 2.0) : px * 4.0 * (cin + a.C + 1.0);
+    ProfScope prof(SQ ? "row_pass_dist_square" : DIST ? "row_pass_dist" : "row_pass", bytes, s);
+    hipLaunchKernelGGL((row_pass_kernel<S, DIST, SQ>), dim3(H, batch), dim3(nw * kWave), 0, s, a);
 }
 
 // Pixels per lane for a row of width W: long rows use longer lane segments so one wave
@@ -82,6 +86,15 @@ int launch_row_pass(const RowPass& p, Ctx& ctx) {
     const int S = row_segment(p.W);
     const int nw = (p.W + kWave * S - 1) / (kWave * S);
     if (nw > kMaxRowWaves) return DTS_ENOTSUP;
+    if (p.sq) {  // first pass of a variance: always with the distances
+        if (!dist || (p.C & 1)) return DTS_EINVAL;
+        switch (S) {
+            case 4: launch_row_t<4, true, true>(a, nw, p.batch, p.H, s); break;
+            case 8: launch_row_t<8, true, true>(a, nw, p.batch, p.H, s); break;
+            default: launch_row_t<16, true, true>(a, nw, p.batch, p.H, s); break;
+        }
+        return hip_fail(hipGetLastError());
+    }
     switch (S) {
         case 4: dist ? launch_row_t<4, true>(a, nw, p.batch, p.H, s) : launch_row_t<4, false>(a, nw, p.batch, p.H, s); break;
         case 8: dist ? launch_row_t<8, true>(a, nw, p.batch, p.H, s) : launch_row_t<8, false>(a, nw, p.batch, p.H, s); break;
@@ -282,6 +295,34 @@ __global__ void copy_kernel(float* __restrict__ dst, const float* __restrict__ s
 
 // Clears `bytes` bytes at any alignment: 16-byte stores over the aligned middle, byte
 // stores over the unaligned head and tail.
+// Eq. (7): c = exp(-V / (2 sigma_c^2)) with V = DT(z^2) - DT(z)^2, from the filtered
+// pairs: plane 2c of `m` holds DT(z_c), plane 2c + 1 holds DT(z_c^2).  k = -log2(e) /
+// (2 sigma_c^2).  V is used as computed (not clipped at zero).
+__global__ void __launch_bounds__(256) variance_confidence_kernel(const float* __restrict__ m,
+                                                                   float* __restrict__ conf, int C,
+                                                                   size_t plane, size_t total, float k) {
+    const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+    for (size_t e = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += stride) {
+        const size_t pc = e / plane;  // b * C + c
+        const size_t i = e - pc * plane;
+        const float* p = m + 2 * pc * plane + i;
+        const float m1 = p[0];
+        const float m2 = p[plane];
+        conf[e] = exp2_fast(fmaf(-m1, m1, m2) * k);
+    }
+}
+
+int launch_variance_confidence(const float* moments, float* conf, int C, int batch, size_t plane,
+                               float sigma_c, hipStream_t s) {
+    const size_t total = static_cast<size_t>(batch) * C * plane;
+    const double k = -1.0 / (2.0 * static_cast<double>(sigma_c) * sigma_c * std::log(2.0));
+    const size_t blocks = std::min<size_t>((total + 255) / 256, 65536);
+    ProfScope prof("variance_confidence", static_cast<double>(total) * 12.0, s);
+    hipLaunchKernelGGL(variance_confidence_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
+                       moments, conf, C, plane, total, static_cast<float>(k));
+    return hip_fail(hipGetLastError());
+}
+
 int launch_zero(void* ptr, size_t bytes, hipStream_t s) {
     if (bytes == 0) return 0;
     unsigned char* p = static_cast<unsigned char*>(ptr);

@@ -31,8 +31,9 @@ struct RowPass {
     float* dy_out;
     int Cg;
     float s2;         // (sigma_s / sigma_r)^2
-    int C, H, W, batch;
+    int C, H, W, batch;  // C: output channels
     float log2a;
+    int sq;               // 1: the first pass of a variance: src holds C / 2 channels, see RowArgs
 };
 
 // One pass along columns (optional update epilogue of the solver).
@@ -113,6 +114,8 @@ int num_batch_variants();
 int batch_variant_info(int v, int* rows_per_wave, int* group_channels, int* row_tile_pixels);
 int tune_row_segment(int S);
 int launch_zero(void* ptr, size_t bytes, hipStream_t s);
+int launch_variance_confidence(const float* moments, float* conf, int C, int batch, size_t plane,
+                               float sigma_c, hipStream_t s);
 int launch_copy(float* dst, const float* src, size_t n, hipStream_t s);
 
 // RAII launch timer: records a start event on construction and a stop event on

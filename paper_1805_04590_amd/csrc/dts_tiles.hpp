@@ -28,7 +28,7 @@ struct RowArgs {
     float* dy_out;
     int Cg;
     float s2;
-    int C, H, W;
+    int C, H, W;  // C: output channels
     float log2a;
 };
 
@@ -113,8 +113,9 @@ __device__ __forceinline__ void row_filter_solo(const float (&w)[S], float wlast
 // pixel.
 //
 // SOLO: the row belongs to one wave alone (nw = 1): no LDS, no barrier, and the waves of
-// a workgroup may call it independently.
-template <int S, bool DIST, bool SOLO = false>
+// a workgroup may call it independently.  SQ: src holds C / 2 channels and output channel
+// c filters src channel c / 2, squared when c is odd (the pairs z, z^2 of Eq. (7)).
+template <int S, bool DIST, bool SOLO = false, bool SQ = false>
 __device__ __forceinline__ void row_line(const RowArgs& a, int y, int b, int wave, int nw, bool live,
                                          float2* fagg, float2* bagg, float* wfirst) {
     const int lane = lane_id();
@@ -181,10 +182,17 @@ __device__ __forceinline__ void row_line(const RowArgs& a, int y, int b, int wav
         if (lane == kWave - 1) wlast = wfirst[wave + 1];
     }
 
+    const int cin = SQ ? a.C >> 1 : a.C;
     for (int c = 0; c < a.C; ++c) {
         const size_t roff = (static_cast<size_t>(b) * a.C + c) * plane + static_cast<size_t>(y) * W;
+        const size_t soff =
+            (static_cast<size_t>(b) * cin + (SQ ? c >> 1 : c)) * plane + static_cast<size_t>(y) * W;
         float f[S];
-        load_seg<S>(a.src + roff, n0, We, vec, 0.f, f);
+        load_seg<S>(a.src + soff, n0, We, vec, 0.f, f);
+        if (SQ && (c & 1)) {
+#pragma unroll
+            for (int e = 0; e < S; ++e) f[e] *= f[e];
+        }
 
         // causal: J[n] = w[n] J[n-1] + (1 - w[n]) f[n]
         float la = 1.f, lb = 0.f;
@@ -244,12 +252,12 @@ __device__ __forceinline__ void row_line(const RowArgs& a, int y, int b, int wav
 }
 
 // One workgroup per row (all of its waves form one group).
-template <int S, bool DIST>
+template <int S, bool DIST, bool SQ = false>
 __device__ __forceinline__ void row_tile(const RowArgs& a, int y, int b) {
     __shared__ float2 fagg[kMaxRowWaves];
     __shared__ float2 bagg[kMaxRowWaves];
     __shared__ float wfirst[kMaxRowWaves + 1];
-    row_line<S, DIST>(a, y, b, threadIdx.x >> 6, blockDim.x >> 6, true, fagg, bagg, wfirst);
+    row_line<S, DIST, false, SQ>(a, y, b, threadIdx.x >> 6, blockDim.x >> 6, true, fagg, bagg, wfirst);
 }
 
 

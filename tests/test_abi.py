@@ -148,3 +148,16 @@ def test_batched_rejects_unsupported_problems(lib):
         assert lib.dts_batched_workspace_bytes(table(**bad), 1, 0) == 0, bad
     assert lib.dts_batched_workspace_bytes(table(), 1, lib.dts_batched_variant_count()) == 0
 
+
+def test_variance_confidence_rejects_bad_arguments_without_launching(lib):
+    assert lib.dts_variance_confidence_workspace_bytes(1, 8, 8, 8) > 0
+    assert lib.dts_variance_confidence_workspace_bytes(1, 8, 8, 9) == 0
+    assert lib.dts_variance_confidence_workspace_bytes(0, 8, 8, 1) == 0
+    fake = ctypes.c_void_p(0x10000)
+    ws = ctypes.c_void_p(0x10000)
+    # sigma_c <= 0, too many channels, null output: refused before any launch
+    assert lib.dts_variance_confidence(fake, 3, fake, fake, 1, 1, 8, 8, 8.0, 0.2, 3, 0.0, ws, 1 << 20, None) == dts.DTS_EINVAL
+    assert lib.dts_variance_confidence(fake, 3, fake, fake, 9, 1, 8, 8, 8.0, 0.2, 3, 0.1, ws, 1 << 20, None) == dts.DTS_EINVAL
+    assert lib.dts_variance_confidence(fake, 3, fake, None, 1, 1, 8, 8, 8.0, 0.2, 3, 0.1, ws, 1 << 20, None) == dts.DTS_EINVAL
+    assert lib.dts_variance_confidence(fake, 3, fake, fake, 1, 1, 8, 8, 8.0, 0.2, 3, 0.1, ws, 16, None) == dts.DTS_EWORKSPACE
+
