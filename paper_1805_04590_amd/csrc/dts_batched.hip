@@ -76,49 +76,10 @@ struct RowLds {
 };
 
 // Rows y0 + v, y0 + v + kBatchWaves, ... of [y0, y1), each filtered by wave v alone.
-// While one channel of a row is filtered, the loads of the next channel (or of the next
-// row's distances and first channel) are already in flight.
 template <int S>
 __device__ __forceinline__ void row_band_solo(const RowArgs& a, int y0, int y1, int wave) {
-    const int lane = lane_id();
-    const int W = a.W, C = a.C;
-    const size_t plane = static_cast<size_t>(a.H) * W;
-    const int n0 = lane * S;
-    const bool vec = (W & 3) == 0;
-    int y = y0 + wave;
-    if (y >= y1) return;
-    float d[S], f[S];
-    load_seg<S>(a.d + static_cast<size_t>(y) * W, n0, W, vec, 1.f, d);
-    load_seg<S>(a.src + static_cast<size_t>(y) * W, n0, W, vec, 0.f, f);
-    while (true) {
-        float w[S];
-#pragma unroll
-        for (int e = 0; e < S; ++e) {
-            const int n = n0 + e;
-            w[e] = (n > 0 && n < W) ? weight(d[e], a.log2a) : 0.f;
-        }
-        float wlast = __shfl_down(w[0], 1);
-        if (lane == kWave - 1) wlast = 0.f;
-        const int yn = y + kBatchWaves;
-        for (int c = 0; c < C; ++c) {
-            float g[S];
-            const bool more = c + 1 < C || yn < y1;
-            if (c + 1 < C) {
-                load_seg<S>(a.src + (c + 1) * plane + static_cast<size_t>(y) * W, n0, W, vec, 0.f, g);
-            } else if (yn < y1) {
-                load_seg<S>(a.d + static_cast<size_t>(yn) * W, n0, W, vec, 1.f, d);
-                load_seg<S>(a.src + static_cast<size_t>(yn) * W, n0, W, vec, 0.f, g);
-            }
-            row_filter_solo<S>(w, wlast, f, lane);
-            store_seg<S>(a.dst + c * plane + static_cast<size_t>(y) * W, n0, W, vec, f);
-            if (more) {
-#pragma unroll
-                for (int e = 0; e < S; ++e) f[e] = g[e];
-            }
-        }
-        if (yn >= y1) break;
-        y = yn;
-    }
+    for (int y = y0 + wave; y < y1; y += kBatchWaves)
+        row_line<S, false, true>(a, y, 0, 0, 1, true, nullptr, nullptr, nullptr);
 }
 
 // Rows [y0, y1) of one instance.  gw == 1: one wave per row (row_band_solo); otherwise
@@ -342,8 +303,8 @@ static int batched_capacity_v() {
 
 #define DTS_BV(R, CT, OCC, PX) {R, CT, PX, batched_launch_v<R, CT, OCC>, batched_capacity_v<R, CT, OCC>}
 static const BatchVariant kBatchVariants[] = {
-    DTS_BV(32, 1, 3, 16384), DTS_BV(16, 1, 3, 16384), DTS_BV(16, 2, 3, 16384), DTS_BV(8, 3, 3, 16384),
-    DTS_BV(16, 3, 2, 16384), DTS_BV(32, 1, 3, 65536), DTS_BV(16, 2, 3, 65536),
+    DTS_BV(32, 1, 3, 16384), DTS_BV(16, 1, 4, 16384), DTS_BV(16, 2, 3, 16384), DTS_BV(8, 3, 3, 16384),
+    DTS_BV(16, 3, 2, 16384),
 };
 #undef DTS_BV
 constexpr int kNumBatchVariants = sizeof(kBatchVariants) / sizeof(kBatchVariants[0]);
