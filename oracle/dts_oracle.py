@@ -52,6 +52,10 @@ __all__ = [
     "residual",
     "dense_filter_matrix",
     "variance_confidence",
+    "sample_row_linear",
+    "stereo_data_gradient",
+    "energy_stereo",
+    "solve_stereo",
 ]
 
 
@@ -369,4 +373,80 @@ def variance_confidence(guide, z, sigma_s, sigma_r, sigma_c, filter_iters=3, dis
     m2 = dt_filter(zz * zz, dx, dy, sigma_s, filter_iters)
     V = m2 - m1 * m1
     return np.exp(-V / (2.0 * float(sigma_c) ** 2)), V
+
+
+# ----------------------------------------------------------------------------------------
+# Stereo (Sec. 3.3, Eq. (11)): edge-aware smoothness, Charbonnier target term, and the
+# photometric term of a rectified pair.  Readings (listed in the design notes):
+#   S1  disparities are in pixels: the left pixel (x, y) matches the right image at
+#       (x - z, y) on the same row;
+#   S2  the right image is sampled linearly along x, the sample position clamped to
+#       [0, W - 1]; the derivative is the slope of the segment the sample falls in
+#       (segment [x0, x0 + 1] with x0 = min(floor(x_s), W - 2)), and 0 where the position
+#       was clamped (the sample does not move there); a one-pixel-wide image has slope 0;
+#   S3  colour images: the photometric term sums the squared differences over channels;
+#   S4  the update is gradient descent on Eq. (11) with the edge-aware mean held fixed,
+#       as Eq. (3) is for Eq. (2):  z <- z - step * (lam (z - DT(z)) + D(z)),
+#       D = c rho'(z - t) + gamma sum_k (I_L,k - I_R,k(x - z)) dI_R,k/dx(x - z),
+#       rho(r) = sqrt(r^2 + eps^2) (so rho'(r) = r / sqrt(r^2 + eps^2));
+#   S5  the left image is the guide of the edge-aware mean.
+# ----------------------------------------------------------------------------------------
+def sample_row_linear(img, xs):
+    """Linear interpolation of img [C][H][W] along x at positions xs [H][W] (same row),
+    clamped to [0, W - 1] (reading S2).  Returns (values, slopes), both [C][H][W]; the
+    slope is 0 where the position was clamped."""
+    I = np.asarray(img, dtype=np.float64)
+    C, H, W = I.shape
+    xr = np.asarray(xs, dtype=np.float64)
+    x = np.clip(xr, 0.0, W - 1.0)
+    if W == 1:
+        return np.broadcast_to(I, (C, H, W)).copy(), np.zeros((C, H, W))
+    x0 = np.minimum(np.floor(x), W - 2).astype(np.int64)
+    fr = x - x0
+    rows = np.arange(H)[:, None]
+    left = I[:, rows, x0]
+    right = I[:, rows, x0 + 1]
+    inside = (xr >= 0.0) & (xr <= W - 1.0)
+    return left + fr * (right - left), np.where(inside, right - left, 0.0)
+
+
+def stereo_data_gradient(left, right, z, target, conf, gamma, eps):
+    """D(z) of reading S4: the Charbonnier target term's derivative plus the photometric
+    term's derivative with respect to the disparity, per pixel ([1][H][W])."""
+    zz = np.asarray(z, dtype=np.float64)[0]
+    t = np.asarray(target, dtype=np.float64)[0]
+    c = np.asarray(conf, dtype=np.float64)[0]
+    IL = np.asarray(left, dtype=np.float64)
+    H, W = zz.shape
+    xs = np.arange(W)[None, :] - zz
+    val, slope = sample_row_linear(right, xs)
+    r = zz - t
+    photo = gamma * np.sum((IL - val) * slope, axis=0)
+    return (c * r / np.sqrt(r * r + eps * eps) + photo)[None]
+
+
+def energy_stereo(z, zbar, left, right, target, conf, lam, gamma, eps):
+    """Eq. (11) with the Charbonnier target term (reading S4), for a given mean zbar."""
+    zz = np.asarray(z, dtype=np.float64)[0]
+    t = np.asarray(target, dtype=np.float64)[0]
+    c = np.asarray(conf, dtype=np.float64)[0]
+    W = zz.shape[1]
+    val, _ = sample_row_linear(right, np.arange(W)[None, :] - zz)
+    photo = 0.5 * gamma * np.sum((np.asarray(left, dtype=np.float64) - val) ** 2)
+    return (0.5 * lam * float(np.sum((zz - np.asarray(zbar, dtype=np.float64)[0]) ** 2))
+            + float(np.sum(c * np.sqrt((zz - t) ** 2 + eps * eps))) + photo)
+
+
+def solve_stereo(left, right, target, conf, sigma_s, sigma_r, filter_iters=3, solver_iters=10,
+                 lam=0.99, step=0.99, gamma=0.001, eps=0.001):
+    """Stereo refinement (Sec. 3.3, Eq. (11), readings S1-S5): z^0 = t, then
+        z^{k+1} = z^k - step * (lam * (z^k - DT(z^k)) + D(z^k)),
+    DT guided by the left image.  target and conf are [1][H][W]; returns z^T."""
+    t = np.asarray(target, dtype=np.float64)
+    dx, dy = distances(left, sigma_s, sigma_r)
+    z = t.copy()
+    for _ in range(int(solver_iters)):
+        zbar = dt_filter(z, dx, dy, sigma_s, filter_iters)
+        z = z - step * (lam * (z - zbar) + stereo_data_gradient(left, right, z, target, conf, gamma, eps))
+    return z
 
