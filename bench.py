@@ -314,6 +314,49 @@ def solve_leg(args, dev):
                 H=H, W=W, Cg=Cg, Ct=Ct, T=T, N=N, ss=ss, sr=sr, variance=variance)
 
 
+def stereo_leg(steps, warmup):
+    """Eq. (11) disparity refinement on the 1920x1080 stereo pair (T = 20) against the
+    plain solve of the same target and confidence with the left image as guide."""
+    import torch
+
+    import dts_inputs
+    import paper_1805_04590_amd as dts
+
+    c = dts_inputs.config2_stereo()
+    dev = torch.device("cuda:0")
+    L = torch.from_numpy(c["left"]).to(dev)
+    R = torch.from_numpy(c["right"]).to(dev)
+    t = torch.from_numpy(c["target"]).to(dev)
+    cf = torch.from_numpy(c["conf"]).to(dev)
+    _, H, W = t.shape
+    T, ss, sr = c["solver_iters"], c["sigma_s"], c["sigma_r"]
+    lib = dts.library()
+    wss = torch.empty(lib.dts_solve_stereo_workspace_bytes(1, H, W), dtype=torch.uint8, device=dev)
+    import ctypes
+    p = dts.Params(ss, sr, 3, T).c()
+    wsp = torch.empty(lib.dts_solve_workspace_bytes(1, H, W, 1, ctypes.byref(p)), dtype=torch.uint8, device=dev)
+    out = torch.empty_like(t)
+
+    def stereo():
+        dts.solve_stereo(L, R, t, cf, ss, sr, 3, T, gamma=c["gamma"], eps=c["eps"], out=out, workspace=wss)
+
+    def plain():
+        dts.solve(L, t, cf, ss, sr, 3, T, out=out[None], workspace=wsp)
+
+    ms_s = timed(stereo, steps, warmup)
+    dts.workspace_status(wss)
+    ms_p = timed(plain, steps, warmup)
+    px = H * W
+    Cg = L.shape[0]
+    # per iteration: data-term gradient (z, t, c, D and both images) + 6 passes + the
+    # update's reads of z and D; the distances once
+    s_bytes = px * (T * (4 * (4 + 2 * Cg) + 6 * 12 + 8) + 4 * Cg + 8)
+    return dict(workload=f"stereo refinement (Eq. 11) {W}x{H} RGB pair, T={T}, gamma={c['gamma']}, "
+                         f"eps={c['eps']}", stereo_ms=round(ms_s, 3), stereo_mpix_s=round(px / ms_s / 1e3, 1),
+                plain_ms=round(ms_p, 3), stereo_over_plain=round(ms_s / ms_p, 3),
+                algorithmic_GBps=round(s_bytes / (ms_s / 1e3) / 1e9, 1))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -346,6 +389,10 @@ def main():
         log("forward+backward leg (8 x 1024^2, T=15) ...")
         extras["fwd_bwd"] = fwd_bwd_leg(max(3, args.steps // 2), 2)
         log("  " + json.dumps(extras["fwd_bwd"]))
+        torch.cuda.empty_cache()
+        log("stereo leg (1920x1080 pair, T=20) ...")
+        extras["stereo"] = stereo_leg(max(3, args.steps // 2), 2)
+        log("  " + json.dumps(extras["stereo"]))
 
     cpu = None
     if args.cpu_rows > 0:

@@ -132,13 +132,7 @@ def config1(seed=0):
                 lam=LAMBDA, step=STEP, value_range=1.0)
 
 
-def config2(seed=1):
-    """1920x1080 RGB guide (32 polygons) with a disparity-like target in [0, 256).
-
-    The stereo-refinement stand-in: per-label planar disparity a + b*x/W + c*y/H with
-    a ~ U[16,224], b, c ~ U[-16,16], clipped to [0,256); 10% of pixels replaced by
-    U[0,256) outliers; confidence 0.05 on outliers and U[0.5,1] elsewhere;
-    sigma_s=16, sigma_r=0.1, T=20."""
+def _config2_parts(seed):
     H, W, Cg, n_poly = 1080, 1920, 3, 32
     rng = np.random.default_rng(seed)
     clean, labels = polygon_scene(rng, H, W, Cg, n_poly)
@@ -151,14 +145,77 @@ def config2(seed=1):
     disp = a[labels] + b[labels] * xs + c[labels] * ys
     top = np.nextafter(np.float32(256.0), np.float32(0.0))
     disp = np.clip(disp, 0.0, float(top))
+    clean_disp = disp
     outlier = rng.uniform(0.0, 1.0, size=(H, W)) < 0.10
     disp = np.where(outlier, rng.uniform(0.0, 256.0, size=(H, W)), disp)
     disp = np.minimum(disp, float(top))
     conf = np.where(outlier, 0.05, rng.uniform(0.5, 1.0, size=(H, W)))
+    return guide, clean_disp, disp, conf
+
+
+def config2(seed=1):
+    """1920x1080 RGB guide (32 polygons) with a disparity-like target in [0, 256).
+
+    The stereo-refinement stand-in: per-label planar disparity a + b*x/W + c*y/H with
+    a ~ U[16,224], b, c ~ U[-16,16], clipped to [0,256); 10% of pixels replaced by
+    U[0,256) outliers; confidence 0.05 on outliers and U[0.5,1] elsewhere;
+    sigma_s=16, sigma_r=0.1, T=20."""
+    guide, _, disp, conf = _config2_parts(seed)
     return dict(name="C2 1920x1080 RGB->1 disparity, T=20", guide=guide,
                 target=disp.astype(np.float32)[None], conf=conf.astype(np.float32)[None],
                 sigma_s=16.0, sigma_r=0.1, filter_iters=FILTER_ITERS, solver_iters=20,
                 lam=LAMBDA, step=STEP, value_range=256.0)
+
+
+def warp_right(left, disp):
+    """Right image of a synthetic rectified pair: I_R(u, y) = I_L(u + d(u, y), y), read
+    linearly along the row and clamped at the borders, so that I_L(x) is close to
+    I_R(x - d) wherever d varies slowly.  left [C][H][W], disp [H][W] in pixels."""
+    C, H, W = left.shape
+    u = np.arange(W, dtype=np.float64)
+    out = np.empty_like(left)
+    for y in range(H):
+        pos = np.clip(u + disp[y], 0.0, W - 1.0)
+        for k in range(C):
+            out[k, y] = np.interp(pos, u, left[k, y])
+    return out.astype(np.float32)
+
+
+STEREO_GAMMA = 0.001  # Sec. 4, stereo optimisation
+STEREO_EPS = 0.001    # Charbonnier epsilon of Sec. 3.3
+
+
+def config2_stereo(seed=1):
+    """The config-2 scene as a stereo pair: the guide is the left image, the right image
+    is warped by the clean planar disparity, the target is the disparity with its 10%
+    outliers.  gamma and epsilon of the stereo refinement, sigma_s=16, sigma_r=0.1, T=20."""
+    guide, clean_disp, disp, conf = _config2_parts(seed)
+    right = warp_right(guide, clean_disp)
+    return dict(name="C2 stereo 1920x1080 RGB pair, disparity target, T=20", left=guide, right=right,
+                target=disp.astype(np.float32)[None], conf=conf.astype(np.float32)[None],
+                sigma_s=16.0, sigma_r=0.1, filter_iters=FILTER_ITERS, solver_iters=20,
+                lam=LAMBDA, step=STEP, gamma=STEREO_GAMMA, eps=STEREO_EPS, value_range=256.0)
+
+
+def stereo_case(seed, H, W, Cg=3, d_max=16.0, sigma_s=8.0, sigma_r=0.2, T=5, gamma=STEREO_GAMMA,
+                eps=STEREO_EPS):
+    """A small synthetic stereo pair: config-1 style left image, per-label planar
+    disparity in [0, d_max) with 10% outliers, right image warped by the clean disparity."""
+    rng = np.random.default_rng(seed)
+    n_poly = 8
+    clean, labels = polygon_scene(rng, H, W, Cg, n_poly)
+    left = _noisy_guide(rng, clean, 0.02)
+    a = rng.uniform(0.0, 0.8 * d_max, size=n_poly + 1)
+    b = rng.uniform(-0.1 * d_max, 0.1 * d_max, size=n_poly + 1)
+    xs = np.arange(W, dtype=np.float64)[None, :] / max(W, 1)
+    disp = np.clip(a[labels] + b[labels] * xs, 0.0, d_max)
+    outlier = rng.uniform(0.0, 1.0, size=(H, W)) < 0.10
+    target = np.where(outlier, rng.uniform(0.0, d_max, size=(H, W)), disp)
+    conf = np.where(outlier, 0.05, rng.uniform(0.5, 1.0, size=(H, W)))
+    return dict(name=f"stereo {H}x{W} Cg={Cg} seed={seed}", left=left, right=warp_right(left, disp),
+                target=target.astype(np.float32)[None], conf=conf.astype(np.float32)[None],
+                sigma_s=sigma_s, sigma_r=sigma_r, filter_iters=FILTER_ITERS, solver_iters=T,
+                lam=LAMBDA, step=STEP, gamma=gamma, eps=eps, value_range=d_max)
 
 
 # ---------------------------------------------------------------------------------------

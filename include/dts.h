@@ -96,6 +96,27 @@ int dts_solve_backward(const float* guide, int Cg, const float* target, const fl
                        float* grad_conf, float* grad_guide, void* workspace,
                        size_t workspace_bytes, void* stream);
 
+/* ---- Stereo refinement (Eq. (11), Sec. 3.3) ---- */
+
+/* Workspace for dts_solve_stereo (0 if the shape is invalid). */
+size_t dts_solve_stereo_workspace_bytes(int batch, int H, int W);
+
+/* Disparity refinement of Eq. (11): the edge-aware smoothness of Eq. (2) guided by the left
+ * image, a Charbonnier target term c rho(z - t) with rho(r) = sqrt(r^2 + epsilon^2), and
+ * the photometric term gamma/2 sum_k (I_L,k(x) - I_R,k(x - z))^2 of a rectified pair.
+ * Gradient descent with the edge-aware mean held fixed, as for dts_solve:
+ *   z^0 = t,  z^{k+1} = z^k - step (lambda (z^k - DT(z^k)) + D(z^k)),
+ *   D = c rho'(z - t) + gamma sum_k (I_L,k - I_R,k(x - z)) dI_R,k/dx (x - z).
+ * Disparities are in pixels: left pixel (x, y) matches the right image at (x - z, y),
+ * read linearly along the row, the position clamped to [0, W - 1] (slope 0 where
+ * clamped).  left, right [batch][Cg][H][W]; target, conf, out [batch][1][H][W]; p gives
+ * sigma_s, sigma_r, filter_iters, solver_iters (T = 0 copies the target), lambda, step.
+ * gamma >= 0, epsilon > 0 (Sec. 4 uses 0.001 for both).  out must not alias target,
+ * conf or the images.  Errors as dts_solve. */
+int dts_solve_stereo(const float* left, const float* right, int Cg, const float* target, const float* conf,
+                     int batch, int H, int W, const dts_params* p, float gamma, float epsilon, float* out,
+                     void* workspace, size_t workspace_bytes, void* stream);
+
 /* ---- Variance-based confidence (Eq. (7), Sec. 3.1) ---- */
 
 /* Workspace for dts_variance_confidence (0 if the arguments are invalid). */

@@ -10,6 +10,7 @@ is missing or a tensor is not on the GPU.
 Entry points (same names as the C ABI):
   filter(guide, src, sigma_s, sigma_r, filter_iters=3)           edge-aware mean DT(src)
   variance_confidence(guide, z, sigma_s, sigma_r, sigma_c)        Eq. (7) confidence
+  solve_stereo(left, right, target, conf, sigma_s, sigma_r, ...)  Eq. (11) disparity refinement
   solve(guide, target, conf, sigma_s, sigma_r, ...)               Eq. (3) gradient descent
   solve_backward(guide, target, conf, checkpoints, grad_out, ...) adjoint of solve
   DTSFunction.apply(guide, target, conf, params)                  autograd wrapper
@@ -30,6 +31,7 @@ __all__ = [
     "library_path",
     "filter",
     "variance_confidence",
+    "solve_stereo",
     "solve",
     "solve_backward",
     "DTSFunction",
@@ -67,6 +69,8 @@ EXPORTED_SYMBOLS = (
     "dts_workspace_status",
     "dts_strerror",
     "dts_last_hip_error",
+    "dts_solve_stereo_workspace_bytes",
+    "dts_solve_stereo",
     "dts_variance_confidence_workspace_bytes",
     "dts_variance_confidence",
     "dts_distances",
@@ -194,6 +198,10 @@ def library():
     lib.dts_solve_backward.argtypes = [fp, i, fp, fp, i, i, i, i, i, P, fp, fp, fp, fp, fp,
                                        vp, sz, vp]
     lib.dts_solve_backward.restype = i
+    lib.dts_solve_stereo_workspace_bytes.argtypes = [i, i, i]
+    lib.dts_solve_stereo_workspace_bytes.restype = sz
+    lib.dts_solve_stereo.argtypes = [fp, fp, i, fp, fp, i, i, i, P, f, f, fp, vp, sz, vp]
+    lib.dts_solve_stereo.restype = i
     lib.dts_variance_confidence_workspace_bytes.argtypes = [i, i, i, i]
     lib.dts_variance_confidence_workspace_bytes.restype = sz
     lib.dts_variance_confidence.argtypes = [fp, i, fp, fp, i, i, i, i, f, f, i, f, vp, sz, vp]
@@ -480,6 +488,37 @@ def filter(guide, src, sigma_s, sigma_r, filter_iters=3, out=None, workspace=Non
                         _stream())
     _check(rc, "dts_filter")
     return out if src.dim() == 4 else out[0]
+
+
+def solve_stereo(left, right, target, conf, sigma_s, sigma_r, filter_iters=3, solver_iters=10,
+                 lam=0.99, step=0.99, gamma=0.001, eps=0.001, out=None, workspace=None):
+    """Disparity refinement of Eq. (11) (Sec. 3.3): smoothness guided by ``left``, a
+    Charbonnier target term and the photometric term against ``right``.  left/right
+    [B][Cg][H][W] (or [Cg][H][W]); target/conf [B][1][H][W] (or [1][H][W])."""
+    L = _as4d(left, "left")
+    R = _as4d(right, "right")
+    t = _as4d(target, "target")
+    c = _as4d(conf, "conf")
+    B, Cg, H, W = L.shape
+    if R.shape != L.shape:
+        raise ValueError("left and right images differ in shape")
+    if t.shape != (B, 1, H, W) or c.shape != (B, 1, H, W):
+        raise ValueError("target and conf must be [B][1][H][W] like the images")
+    lib = library()
+    out = torch.empty_like(t) if out is None else _as4d(out, "out")
+    if out.shape != t.shape:
+        raise ValueError("out must have the shape of target")
+    if workspace is None:
+        nbytes = lib.dts_solve_stereo_workspace_bytes(B, H, W)
+        if nbytes == 0:
+            raise DTSError(DTS_EINVAL, "dts_solve_stereo_workspace_bytes")
+        workspace = _workspace(nbytes, t.device)
+    p = Params(sigma_s, sigma_r, filter_iters, solver_iters, lam, step).c()
+    rc = lib.dts_solve_stereo(_ptr(L), _ptr(R), Cg, _ptr(t), _ptr(c), B, H, W, ctypes.byref(p),
+                              float(gamma), float(eps), _ptr(out), _ptr(workspace), workspace.numel(),
+                              _stream())
+    _check(rc, "dts_solve_stereo")
+    return out if target.dim() == 4 else out[0]
 
 
 def variance_confidence(guide, z, sigma_s, sigma_r, sigma_c, filter_iters=3, out=None, workspace=None):

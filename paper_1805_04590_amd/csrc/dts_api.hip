@@ -441,6 +441,82 @@ int dts_solve_backward(const float* guide, int Cg, const float* target, const fl
     return DTS_OK;
 }
 
+static size_t stereo_workspace_bytes(int batch, int H, int W) {
+    return make_layout(batch, H, W, 1, true).total + align_up(static_cast<size_t>(batch) * H * W * sizeof(float));
+}
+
+size_t dts_solve_stereo_workspace_bytes(int batch, int H, int W) {
+    if (check_shape(batch, H, W)) return 0;
+    return stereo_workspace_bytes(batch, H, W);
+}
+
+int dts_solve_stereo(const float* left, const float* right, int Cg, const float* target, const float* conf,
+                     int batch, int H, int W, const dts_params* p, float gamma, float epsilon, float* out,
+                     void* workspace, size_t workspace_bytes, void* stream) {
+    if (!left || !right || !target || !conf || !out || !p) return DTS_EINVAL;
+    int rc = check_shape(batch, H, W);
+    if (rc) return rc;
+    if (check_channels(Cg)) return DTS_EINVAL;
+    if (!finite_pos(p->sigma_s) || !finite_pos(p->sigma_r) || !finite_pos(epsilon)) return DTS_EINVAL;
+    if (!isfinite(gamma) || gamma < 0.f) return DTS_EINVAL;
+    if (p->filter_iters < 1 || p->filter_iters > kMaxFilterIters) return DTS_EINVAL;
+    if (p->solver_iters < 0 || p->solver_iters > kMaxSolverIters) return DTS_EINVAL;
+    if (!isfinite(p->lambda) || !isfinite(p->step)) return DTS_EINVAL;
+    if (workspace_bytes < stereo_workspace_bytes(batch, H, W)) return DTS_EWORKSPACE;
+    const int T = p->solver_iters, N = p->filter_iters;
+    Setup S;
+    rc = begin_call(S, workspace, workspace_bytes, batch, H, W, 1, true, stream);
+    if (rc) return rc;
+    float* D = reinterpret_cast<float*>(static_cast<char*>(workspace) + S.L.total);
+    const size_t sig = static_cast<size_t>(batch) * H * W;
+    if (T == 0) return launch_copy(out, target, sig, S.ctx.stream);
+    const float s2 = static_cast<float>((static_cast<double>(p->sigma_s) / p->sigma_r) *
+                                        (static_cast<double>(p->sigma_s) / p->sigma_r));
+    for (int k = 0; k < T; ++k) {
+        const float* zk = (k == 0) ? target : out;
+        if ((rc = launch_stereo_data_grad(zk, target, conf, left, right, D, Cg, batch, H, W, gamma, epsilon,
+                                          S.ctx.stream)))
+            return rc;
+        for (int i = 1; i <= N; ++i) {
+            const float l2a = log2_feedback(p->sigma_s, i, N);
+            RowPass rp{};
+            rp.src = (i == 1) ? zk : S.tmp;
+            rp.dst = S.tmp;
+            rp.d = S.dx;
+            rp.guide = (k == 0 && i == 1) ? left : nullptr;
+            rp.dx_out = S.dx;
+            rp.dy_out = S.dy;
+            rp.Cg = Cg;
+            rp.s2 = s2;
+            rp.C = 1;
+            rp.H = H;
+            rp.W = W;
+            rp.batch = batch;
+            rp.log2a = l2a;
+            if ((rc = launch_row_pass(rp, S.ctx))) return rc;
+            ColPass cp{};
+            cp.src = S.tmp;
+            cp.dst = (i == N) ? out : S.tmp;
+            cp.d = S.dy;
+            cp.C = 1;
+            cp.H = H;
+            cp.W = W;
+            cp.batch = batch;
+            cp.log2a = l2a;
+            cp.epilogue = (i == N);
+            cp.data_grad = true;
+            cp.zk = zk;
+            cp.tgt = D;
+            cp.Cc = 1;
+            cp.dst2 = nullptr;
+            cp.lambda = p->lambda;
+            cp.step = p->step;
+            if ((rc = launch_col_pass(cp, S.ctx))) return rc;
+        }
+    }
+    return DTS_OK;
+}
+
 size_t dts_variance_confidence_workspace_bytes(int batch, int H, int W, int C) {
     if (batch < 1 || H < 1 || W < 1 || C < 1 || 2 * C > DTS_MAX_CHANNELS) return 0;
     return make_layout(batch, H, W, 2 * C, true).total;

@@ -243,8 +243,8 @@ batched_kernel(BatchArgs a) {
                     auto take_next = [&]() {
                         if (threadIdx.x == 0) nxt = atomicAdd(tickets, 1u);
                     };
-                    if (epi) col_tile<CTM, R, kBatchWaves, true>(ca, cctx, L, chunk, strip, grp, 0, take_next);
-                    else col_tile<CTM, R, kBatchWaves, false>(ca, cctx, L, chunk, strip, grp, 0, take_next);
+                    if (epi) col_tile<CTM, R, kBatchWaves, 1>(ca, cctx, L, chunk, strip, grp, 0, take_next);
+                    else col_tile<CTM, R, kBatchWaves, 0>(ca, cctx, L, chunk, strip, grp, 0, take_next);
                 }
             }
             // every wave has read s_t (a barrier of the tile lies in between)

@@ -106,7 +106,7 @@ int launch_row_pass(const RowPass& p, Ctx& ctx) {
 // ---------------------------------------------------------------------------------------
 // Column pass
 // ---------------------------------------------------------------------------------------
-template <int CT, int R, int NWV, bool EPI>
+template <int CT, int R, int NWV, int EPI>
 __global__ void __launch_bounds__(kWave * NWV) col_pass_kernel(ColArgs a) {
     __shared__ ChunkLds<CT, NWV> L;
     const CarryCtx cctx{a.carry, a.epoch, a.status, a.G, a.S, a.NG};
@@ -132,11 +132,11 @@ __global__ void __launch_bounds__(kWave * NWV) col_pass_kernel(ColArgs a) {
 // ---------------------------------------------------------------------------------------
 struct ColVariant {
     int ct, R, nwv;
-    int (*launch)(const ColArgs&, unsigned, hipStream_t, bool);
-    int (*capacity)(bool);
+    int (*launch)(const ColArgs&, unsigned, hipStream_t, int);  // mode: col_tile's EPI
+    int (*capacity)(int);
 };
 
-template <int CT, int R, int NWV, bool EPI>
+template <int CT, int R, int NWV, int EPI>
 static int col_capacity_t() {
     static int cached[64] = {0};
     static std::mutex mu;
@@ -156,16 +156,23 @@ static int col_capacity_t() {
 }
 
 template <int CT, int R, int NWV>
-static int col_capacity_v(bool epi) {
-    return epi ? col_capacity_t<CT, R, NWV, true>() : col_capacity_t<CT, R, NWV, false>();
+static int col_capacity_v(int mode) {
+    return mode == 2 ? col_capacity_t<CT, R, NWV, 2>()
+                     : mode == 1 ? col_capacity_t<CT, R, NWV, 1>() : col_capacity_t<CT, R, NWV, 0>();
 }
 
 template <int CT, int R, int NWV>
-static int col_launch_v(const ColArgs& a, unsigned n, hipStream_t s, bool epi) {
-    if (epi)
-        hipLaunchKernelGGL((col_pass_kernel<CT, R, NWV, true>), dim3(n), dim3(kWave * NWV), 0, s, a);
-    else
-        hipLaunchKernelGGL((col_pass_kernel<CT, R, NWV, false>), dim3(n), dim3(kWave * NWV), 0, s, a);
+static int col_launch_v(const ColArgs& a, unsigned n, hipStream_t s, int mode) {
+    if (mode == 2) {
+        if constexpr (CT == 1)  // the data-gradient update serves single-channel solves
+            hipLaunchKernelGGL((col_pass_kernel<CT, R, NWV, 2>), dim3(n), dim3(kWave * NWV), 0, s, a);
+        else
+            return DTS_ENOTSUP;
+    } else if (mode == 1) {
+        hipLaunchKernelGGL((col_pass_kernel<CT, R, NWV, 1>), dim3(n), dim3(kWave * NWV), 0, s, a);
+    } else {
+        hipLaunchKernelGGL((col_pass_kernel<CT, R, NWV, 0>), dim3(n), dim3(kWave * NWV), 0, s, a);
+    }
     return hip_fail(hipGetLastError());
 }
 
@@ -257,19 +264,23 @@ int launch_col_pass(const ColPass& p, Ctx& ctx) {
     a.step = p.step;
     // every workgroup of the grid must be resident at once: size the grid to the
     // device's capacity for this kernel, in whole strips of G chunks
-    const int cap = v.capacity(p.epilogue);
+    const int mode = !p.epilogue ? 0 : p.data_grad ? 2 : 1;
+    if (mode == 2 && v.ct != 1) return DTS_ENOTSUP;
+    const int cap = v.capacity(mode);
     if (cap <= 0) return hip_fail(hipErrorNoDevice);
     if (a.G > cap) return DTS_ENOTSUP;
     const long long n_strips = static_cast<long long>(p.batch) * a.NG * a.S;
     a.groups = static_cast<int>(std::min<long long>(cap / a.G, n_strips));
     const unsigned n = static_cast<unsigned>(a.groups) * a.G;
     // algorithmic bytes: signal in and out, distances in; the update epilogue also reads
-    // z^k, the target and the confidence
+    // z^k, the target and the confidence (or z^k and the data-term gradient)
     const double px = static_cast<double>(p.batch) * a.H * a.W;
-    const double bytes = p.epilogue ? px * 4.0 * (4.0 * a.C + 1.0 + (a.Cc == 1 ? 1.0 : a.C))
-                                    : px * 4.0 * (2.0 * a.C + 1.0);
-    ProfScope prof(p.epilogue ? "col_pass_update" : "col_pass", bytes, ctx.stream);
-    return v.launch(a, n, ctx.stream, p.epilogue);
+    const double bytes = mode == 1   ? px * 4.0 * (4.0 * a.C + 1.0 + (a.Cc == 1 ? 1.0 : a.C))
+                         : mode == 2 ? px * 4.0 * (4.0 * a.C + 1.0)
+                                     : px * 4.0 * (2.0 * a.C + 1.0);
+    ProfScope prof(mode == 1 ? "col_pass_update" : mode == 2 ? "col_pass_update_grad" : "col_pass", bytes,
+                   ctx.stream);
+    return v.launch(a, n, ctx.stream, mode);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -320,6 +331,58 @@ int launch_variance_confidence(const float* moments, float* conf, int C, int bat
     ProfScope prof("variance_confidence", static_cast<double>(total) * 12.0, s);
     hipLaunchKernelGGL(variance_confidence_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
                        moments, conf, C, plane, total, static_cast<float>(k));
+    return hip_fail(hipGetLastError());
+}
+
+// Data-term gradient of the stereo objective (Eq. (11)) at the disparity z, one pixel per
+// thread:  D = c rho'(z - t) + gamma sum_k (I_L,k - I_R,k(x - z)) dI_R,k/dx (x - z), with
+// rho(r) = sqrt(r^2 + eps^2).  I_R is read linearly along the pixel's row at x - z; the
+// position is clamped to [0, W - 1] and the slope is 0 where it was clamped.
+__global__ void __launch_bounds__(256) stereo_data_grad_kernel(const float* __restrict__ z,
+                                                                const float* __restrict__ t,
+                                                                const float* __restrict__ c,
+                                                                const float* __restrict__ left,
+                                                                const float* __restrict__ right,
+                                                                float* __restrict__ D, int Cg, int H, int W,
+                                                                size_t total, float gamma, float eps2) {
+    const size_t plane = static_cast<size_t>(H) * W;
+    const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+    for (size_t e = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += stride) {
+        const size_t b = e / plane;
+        const size_t i = e - b * plane;
+        const int y = static_cast<int>(i / W);
+        const int x = static_cast<int>(i - static_cast<size_t>(y) * W);
+        const float zz = z[e];
+        const float r = zz - t[e];
+        const float g = c[e] * r / sqrtf(fmaf(r, r, eps2));
+        const float xs = static_cast<float>(x) - zz;
+        const float xc = fminf(fmaxf(xs, 0.f), static_cast<float>(W - 1));
+        const bool inside = xs >= 0.f && xs <= static_cast<float>(W - 1);
+        const int x0 = W > 1 ? min(static_cast<int>(floorf(xc)), W - 2) : 0;
+        const int x1 = W > 1 ? x0 + 1 : 0;
+        const float fr = xc - static_cast<float>(x0);
+        float photo = 0.f;
+        for (int k = 0; k < Cg; ++k) {
+            const size_t row = ((b * Cg + k) * H + y) * static_cast<size_t>(W);
+            const float r0 = right[row + x0];
+            const float r1 = right[row + x1];
+            const float val = fmaf(fr, r1 - r0, r0);
+            const float slope = inside ? r1 - r0 : 0.f;
+            photo = fmaf(left[row + x] - val, slope, photo);
+        }
+        D[e] = fmaf(gamma, photo, g);
+    }
+}
+
+int launch_stereo_data_grad(const float* z, const float* t, const float* c, const float* left, const float* right,
+                            float* D, int Cg, int batch, int H, int W, float gamma, float eps, hipStream_t s) {
+    const size_t total = static_cast<size_t>(batch) * H * W;
+    const size_t blocks = std::min<size_t>((total + 255) / 256, 65536);
+    // z, t, c in, D out, the left image and two right-image samples per band (read once
+    // from HBM when the disparity varies slowly along the row)
+    ProfScope prof("stereo_data_grad", static_cast<double>(total) * 4.0 * (4.0 + 2.0 * Cg), s);
+    hipLaunchKernelGGL(stereo_data_grad_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, z, t, c,
+                       left, right, D, Cg, H, W, total, gamma, eps * eps);
     return hip_fail(hipGetLastError());
 }
 

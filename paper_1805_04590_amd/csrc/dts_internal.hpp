@@ -43,8 +43,11 @@ struct ColPass {
     const float* d;   // dy [batch][H][W]
     int C, H, W, batch;
     float log2a;
-    // epilogue: dst = z - step (lambda (z - K) + c (z - t)), also written to dst2 if set
+    // epilogue: dst = z - step (lambda (z - K) + c (z - t)), also written to dst2 if set;
+    // with data_grad (single-channel signals only): dst = z - step (lambda (z - K) + D),
+    // D read from tgt
     bool epilogue;
+    bool data_grad;
     const float* zk;
     const float* tgt;
     const float* conf;
@@ -114,6 +117,8 @@ int num_batch_variants();
 int batch_variant_info(int v, int* rows_per_wave, int* group_channels, int* row_tile_pixels);
 int tune_row_segment(int S);
 int launch_zero(void* ptr, size_t bytes, hipStream_t s);
+int launch_stereo_data_grad(const float* z, const float* t, const float* c, const float* left, const float* right,
+                            float* D, int Cg, int batch, int H, int W, float gamma, float eps, hipStream_t s);
 int launch_variance_confidence(const float* moments, float* conf, int C, int batch, size_t plane,
                                float sigma_c, hipStream_t s);
 int launch_copy(float* dst, const float* src, size_t n, hipStream_t s);

@@ -288,7 +288,9 @@ struct NoHook {
 // [r0 + v R, r0 + (v+1) R) of the chunk, one column per lane, all in registers.  `hook`
 // runs on every thread once the chunk's carries are known, i.e. once the tile no longer
 // waits on any other tile.
-template <int CT, int R, int NWV, bool EPI, typename Hook = NoHook>
+// EPI: 0 plain pass; 1 the solver update of Eq. (3) (reads z^k, t, c); 2 the update with
+// a precomputed data-term gradient D in place of c (z - t) (reads z^k and D from `tgt`).
+template <int CT, int R, int NWV, int EPI, typename Hook = NoHook>
 __device__ __forceinline__ void col_tile(const ColArgs& a, const CarryCtx& cctx, ChunkLds<CT, NWV>& L,
                                          int chunk, int strip, int grp, int b, Hook hook = Hook{}) {
     const int lane = opaque_v(lane_id());
@@ -400,11 +402,12 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, const CarryCtx& cctx,
             const size_t pidx = static_cast<size_t>(b) * a.C + c0 + c;
             const auto ors = plane_rsrc(a.dst + pidx * plane, pbytes);
             unsigned vo = voff + static_cast<unsigned>(R - 1) * rowb;
-            if constexpr (EPI) {
-                const int cc = (a.Cc == 1) ? 0 : c0 + c;
+            if constexpr (EPI != 0) {
                 const auto zrs = plane_rsrc(a.zk + pidx * plane, pbytes);
                 const auto trs = plane_rsrc(a.tgt + pidx * plane, pbytes);
-                const auto crs = plane_rsrc(a.conf + (static_cast<size_t>(b) * a.Cc + cc) * plane, pbytes);
+                [[maybe_unused]] const auto crs = plane_rsrc(
+                    EPI == 1 ? a.conf + (static_cast<size_t>(b) * a.Cc + ((a.Cc == 1) ? 0 : c0 + c)) * plane : a.tgt,
+                    pbytes);
                 const auto o2rs = plane_rsrc(a.dst2 ? a.dst2 + pidx * plane : a.dst, a.dst2 ? pbytes : 0);
                 // rows in blocks of kEpiBlock, bottom block first: all loads of a block are
                 // issued before any of its stores, so a block costs one memory round trip
@@ -418,7 +421,7 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, const CarryCtx& cctx,
                     for (int q = 0; q < kEpiBlock; ++q) {
                         z[q] = bload(zrs, vl, 0);
                         tt[q] = bload(trs, vl, 0);
-                        cf[q] = bload(crs, vl, 0);
+                        if constexpr (EPI == 1) cf[q] = bload(crs, vl, 0);
                         vl = opaque_vadd(vl, rowb);
                     }
 #pragma unroll
@@ -426,7 +429,8 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, const CarryCtx& cctx,
                         const int r = blk * kEpiBlock + q;
                         const float wn = (r + 1 < R) ? w[(r + 1 < R) ? r + 1 : r] : wnext;
                         K = fmaf(wn, K - f[c][r], f[c][r]);
-                        const float upd = fmaf(a.lambda, z[q] - K, cf[q] * (z[q] - tt[q]));
+                        const float upd = (EPI == 1) ? fmaf(a.lambda, z[q] - K, cf[q] * (z[q] - tt[q]))
+                                                     : fmaf(a.lambda, z[q] - K, tt[q]);
                         const float zn = fmaf(-a.step, upd, z[q]);
                         bstore(ors, vo, 0, zn);
                         bstore(o2rs, vo, 0, zn);

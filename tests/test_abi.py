@@ -161,3 +161,16 @@ def test_variance_confidence_rejects_bad_arguments_without_launching(lib):
     assert lib.dts_variance_confidence(fake, 3, fake, None, 1, 1, 8, 8, 8.0, 0.2, 3, 0.1, ws, 1 << 20, None) == dts.DTS_EINVAL
     assert lib.dts_variance_confidence(fake, 3, fake, fake, 1, 1, 8, 8, 8.0, 0.2, 3, 0.1, ws, 16, None) == dts.DTS_EWORKSPACE
 
+
+def test_solve_stereo_rejects_bad_arguments_without_launching(lib):
+    assert lib.dts_solve_stereo_workspace_bytes(1, 8, 8) > lib.dts_solve_workspace_bytes(1, 8, 8, 1, None)
+    assert lib.dts_solve_stereo_workspace_bytes(0, 8, 8) == 0
+    fake = ctypes.c_void_p(0x10000)
+    p = dts.Params(8.0, 0.2, 3, 5).c()
+    ok = lib.dts_solve_stereo_workspace_bytes(1, 8, 8)
+    # epsilon <= 0, negative gamma, null output, too-small workspace: refused before any launch
+    assert lib.dts_solve_stereo(fake, fake, 3, fake, fake, 1, 8, 8, ctypes.byref(p), 0.001, 0.0, fake, fake, ok, None) == dts.DTS_EINVAL
+    assert lib.dts_solve_stereo(fake, fake, 3, fake, fake, 1, 8, 8, ctypes.byref(p), -1.0, 0.001, fake, fake, ok, None) == dts.DTS_EINVAL
+    assert lib.dts_solve_stereo(fake, fake, 3, fake, fake, 1, 8, 8, ctypes.byref(p), 0.001, 0.001, None, fake, ok, None) == dts.DTS_EINVAL
+    assert lib.dts_solve_stereo(fake, fake, 3, fake, fake, 1, 8, 8, ctypes.byref(p), 0.001, 0.001, fake, fake, ok - 256, None) == dts.DTS_EWORKSPACE
+
