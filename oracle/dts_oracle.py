@@ -52,6 +52,9 @@ __all__ = [
     "residual",
     "dense_filter_matrix",
     "variance_confidence",
+    "support_lines",
+    "support",
+    "support_confidence",
     "sample_row_linear",
     "stereo_data_gradient",
     "energy_stereo",
@@ -373,6 +376,64 @@ def variance_confidence(guide, z, sigma_s, sigma_r, sigma_c, filter_iters=3, dis
     m2 = dt_filter(zz * zz, dx, dy, sigma_s, filter_iters)
     V = m2 - m1 * m1
     return np.exp(-V / (2.0 * float(sigma_c) ** 2)), V
+
+
+# ----------------------------------------------------------------------------------------
+# Support-weighted confidence (Sec. 3.1, the comparison with the bilateral solver after
+# Eq. (6)): the confidence of the gradient-descent update is divided by the support
+# sum_j W_ij of the edge-aware kernel, as in the bilateral solver's per-pixel solution.
+# Reading R10 (listed in the design notes):
+#   - W is the unnormalised form of the 2-D domain-transform kernel: each 1-D pass sums
+#     products of the weights a^d along the line on both sides of a pixel, the pixel itself
+#     once; the passes alternate rows and columns over the N filter iterations as in O4;
+#   - the support is reported relative to that of a pixel deep inside a flat region
+#     (every d = 1), whose 1-D pass sum is (1 + a_i) / (1 - a_i): each pass is scaled by
+#     (1 - a_i) / (1 + a_i), so the relative support s lies in (0, 1] and is 1 far from
+#     edges and borders;
+#   - the weighted confidence is c / s: a pixel with less support (near an edge or a
+#     border) leans more on its target, one with full support keeps c.
+# ----------------------------------------------------------------------------------------
+def support_lines(x, w):
+    """Two-sided unnormalised recursive sum along axis 0 of ``x``:
+
+        S[n] = sum_j (prod of w[k] over the links k between n and j) x[j],
+
+    evaluated as causal y[n] = x[n] + w[n] y[n-1] (y[0] = x[0]), anticausal
+    v[n] = x[n] + w[n+1] v[n+1] (v[L-1] = x[L-1]), S = y + v - x (x[n] counted once).
+    ``w`` broadcasts against ``x``; w[0] is never read."""
+    x = np.asarray(x, dtype=np.float64)
+    w = np.broadcast_to(np.asarray(w, dtype=np.float64), x.shape)
+    L = x.shape[0]
+    y = np.empty_like(x)
+    y[0] = x[0]
+    for n in range(1, L):
+        y[n] = x[n] + w[n] * y[n - 1]
+    v = np.empty_like(x)
+    v[L - 1] = x[L - 1]
+    for n in range(L - 2, -1, -1):
+        v[n] = x[n] + w[n + 1] * v[n + 1]
+    return y + v - x
+
+
+def support(guide, sigma_s, sigma_r, filter_iters=3, dists=None):
+    """Relative support s [H][W] of the edge-aware kernel (reading R10): the unnormalised
+    2-D kernel applied to ones, each 1-D pass scaled by (1 - a_i) / (1 + a_i)."""
+    if dists is None:
+        dists = distances(guide, sigma_s, sigma_r)
+    dx, dy = dists
+    s = np.ones(dx.shape, dtype=np.float64)
+    for a, wx, wy in _pass_weights(dx, dy, sigma_s, filter_iters):
+        m = (1.0 - a) / (1.0 + a)
+        s = m * support_lines(s.T, wx.T).T      # rows: lines along x
+        s = m * support_lines(s, wy)            # columns: lines along y
+    return s
+
+
+def support_confidence(guide, conf, sigma_s, sigma_r, filter_iters=3, dists=None):
+    """Confidence weighted by the inverse relative support, c / s (reading R10);
+    conf [Cc][H][W].  Returns (c / s, s)."""
+    s = support(guide, sigma_s, sigma_r, filter_iters, dists)
+    return np.asarray(conf, dtype=np.float64) / s[None], s
 
 
 # ----------------------------------------------------------------------------------------
