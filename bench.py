@@ -308,10 +308,32 @@ def solve_leg(args, dev):
                     algorithmic_GBps=round(v_bytes / (ms_v / 1e3) / 1e9, 1),
                     hbm_frac=round(v_bytes / (ms_v / 1e3) / 1e9 / HBM_PEAK_GBPS, 4))
     log("  variance confidence: " + json.dumps(variance))
-    del guide, target, conf, out, ws, wsv, confv
+    del wsv, confv
+
+    # support of the edge-aware kernel and the support-weighted confidence, same guide
+    wss = torch.empty(lib.dts_support_workspace_bytes(1, H, W), dtype=torch.uint8, device=dev)
+    sup = torch.empty((1, H, W), dtype=torch.float32, device=dev)
+    confs = torch.empty_like(conf)
+    Cc = conf.shape[0]
+
+    def sstep():
+        dts.support(guide, ss, sr, N, conf=conf, out=sup, conf_out=confs, workspace=wss)
+
+    ms_s = timed(sstep, args.steps, args.warmup)
+    # distances (guide in, dx and dy out); pass 1: rows of ones (dx in, plane out), columns
+    # (plane and dy in, plane out); N - 1 more row and column passes over the support
+    # plane; the last column pass also reads and writes the Cc confidence planes
+    s_bytes = px * (4 * (Cg + 2) + 8 + 12 + 24 * (N - 1) + 8 * Cc)
+    support = dict(workload=f"support and support-weighted confidence of the {W}x{H} "
+                            f"{Cg}-band guide, N={N}",
+                   ms=round(ms_s, 3), mpix_s=round(px / ms_s / 1e3, 1),
+                   algorithmic_GBps=round(s_bytes / (ms_s / 1e3) / 1e9, 1),
+                   hbm_frac=round(s_bytes / (ms_s / 1e3) / 1e9 / HBM_PEAK_GBPS, 4))
+    log("  support: " + json.dumps(support))
+    del guide, target, conf, out, ws, wss, sup, confs
     torch.cuda.empty_cache()
     return dict(ms=ms, mpix=mpix, solve_bytes=solve_bytes, kernels=kernels, roofline=roofline,
-                H=H, W=W, Cg=Cg, Ct=Ct, T=T, N=N, ss=ss, sr=sr, variance=variance)
+                H=H, W=W, Cg=Cg, Ct=Ct, T=T, N=N, ss=ss, sr=sr, variance=variance, support=support)
 
 
 def stereo_leg(steps, warmup):
@@ -403,7 +425,7 @@ def main():
 
     if sol is None:
         sol = dict(ms=None, mpix=None, solve_bytes=None, kernels={}, roofline=None, H=None, W=None,
-                   Cg=None, Ct=None, T=None, N=None, ss=None, sr=None, variance=None)
+                   Cg=None, Ct=None, T=None, N=None, ss=None, sr=None, variance=None, support=None)
     ms, mpix = sol["ms"], sol["mpix"]
     gbps = None if ms is None else sol["solve_bytes"] / (ms / 1e3) / 1e9
     res = {
@@ -431,6 +453,7 @@ def main():
         "cpu_baseline": cpu,
         "kernels": sol["kernels"],
         "variance": sol["variance"],
+        "support": sol["support"],
     }
     res.update(extras)
     print(json.dumps(res), flush=True)

@@ -133,6 +133,26 @@ int dts_variance_confidence(const float* guide, int Cg, const float* z, float* c
                             int H, int W, float sigma_s, float sigma_r, int filter_iters, float sigma_c,
                             void* workspace, size_t workspace_bytes, void* stream);
 
+/* ---- Support-weighted confidence (Sec. 3.1, after Eq. (6)) ---- */
+
+/* Workspace for dts_support (0 if the shape is invalid). */
+size_t dts_support_workspace_bytes(int batch, int H, int W);
+
+/* Support of the edge-aware kernel, s_i = sum_j W_ij relative to a flat region, and
+ * optionally the confidence weighted by it, conf_out = conf / s.  Sec. 3.1 divides the
+ * confidence of the descent update by this support, as in the bilateral solver's
+ * per-pixel solution (Eq. (6)).  W is read as the unnormalised domain-transform kernel:
+ * each 1-D pass sums products of the weights a_i^d over both sides of a pixel, the pixel
+ * counted once, and passes alternate rows and columns over filter_iters iterations
+ * (guide, sigma_s, sigma_r as for dts_filter).  Each pass is scaled by
+ * (1 - a_i) / (1 + a_i), so s is 1 deep inside a flat region and lies in (0, 1].
+ * support [batch][H][W].  conf [batch][Cc][H][W] (1 <= Cc <= 16) and conf_out (same shape)
+ * may be NULL together; conf_out may alias conf but neither may alias support.  The
+ * support depends on the guide only: compute it once per guide.  Errors as dts_filter. */
+int dts_support(const float* guide, int Cg, int batch, int H, int W, float sigma_s, float sigma_r,
+                int filter_iters, float* support, const float* conf, int Cc, float* conf_out, void* workspace,
+                size_t workspace_bytes, void* stream);
+
 /* ---- Many uneven solves in one persistent launch ---- */
 
 /* One independent solve: device pointers, shape and parameters (1 <= T, 1 <= N <= 8,

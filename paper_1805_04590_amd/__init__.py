@@ -73,6 +73,8 @@ EXPORTED_SYMBOLS = (
     "dts_solve_stereo",
     "dts_variance_confidence_workspace_bytes",
     "dts_variance_confidence",
+    "dts_support_workspace_bytes",
+    "dts_support",
     "dts_distances",
     "dts_pass_workspace_bytes",
     "dts_row_pass",
@@ -206,6 +208,10 @@ def library():
     lib.dts_variance_confidence_workspace_bytes.restype = sz
     lib.dts_variance_confidence.argtypes = [fp, i, fp, fp, i, i, i, i, f, f, i, f, vp, sz, vp]
     lib.dts_variance_confidence.restype = i
+    lib.dts_support_workspace_bytes.argtypes = [i, i, i]
+    lib.dts_support_workspace_bytes.restype = sz
+    lib.dts_support.argtypes = [fp, i, i, i, i, f, f, i, fp, fp, i, fp, vp, sz, vp]
+    lib.dts_support.restype = i
     lib.dts_distances.argtypes = [fp, i, i, i, i, f, f, fp, fp, vp]
     lib.dts_distances.restype = i
     lib.dts_pass_workspace_bytes.argtypes = [i, i, i, i]
@@ -543,6 +549,46 @@ def variance_confidence(guide, z, sigma_s, sigma_r, sigma_c, filter_iters=3, out
                                      float(sigma_c), _ptr(workspace), workspace.numel(), _stream())
     _check(rc, "dts_variance_confidence")
     return out if z.dim() == 4 else out[0]
+
+
+def support(guide, sigma_s, sigma_r, filter_iters=3, conf=None, out=None, conf_out=None,
+            workspace=None):
+    """Support of the edge-aware kernel relative to a flat region, s in (0, 1] per pixel
+    ([B][H][W], or [H][W] for a 3-D guide).  With ``conf`` ([B][Cc][H][W]) also returns the
+    support-weighted confidence conf / s (Sec. 3.1, after Eq. (6)) as (s, conf / s);
+    ``conf_out`` may be ``conf``."""
+    g = _as4d(guide, "guide")
+    B, Cg, H, W = g.shape
+    lib = library()
+    if out is None:
+        s_out = torch.empty((B, H, W), dtype=torch.float32, device=g.device)
+    else:
+        if out.numel() != B * H * W:
+            raise ValueError("out must hold [B][H][W] values")
+        s_out = _as4d(out.reshape(B, 1, H, W), "out")
+    c = co = None
+    Cc = 0
+    if conf is not None:
+        c = _as4d(conf, "conf")
+        if c.shape[0] != B or c.shape[2:] != g.shape[2:]:
+            raise ValueError("conf and guide disagree in batch or image size")
+        Cc = c.shape[1]
+        co = torch.empty_like(c) if conf_out is None else _as4d(conf_out, "conf_out")
+        if co.shape != c.shape:
+            raise ValueError("conf_out must have the shape of conf")
+    if workspace is None:
+        nbytes = lib.dts_support_workspace_bytes(B, H, W)
+        if nbytes == 0:
+            raise DTSError(DTS_EINVAL, "dts_support_workspace_bytes")
+        workspace = _workspace(nbytes, g.device)
+    rc = lib.dts_support(_ptr(g), Cg, B, H, W, float(sigma_s), float(sigma_r), int(filter_iters),
+                         _ptr(s_out), _ptr(c), Cc, _ptr(co), _ptr(workspace), workspace.numel(),
+                         _stream())
+    _check(rc, "dts_support")
+    sv = s_out.reshape(B, H, W) if guide.dim() == 4 else s_out.reshape(H, W)
+    if c is None:
+        return sv
+    return sv, (co if conf.dim() == 4 else co[0])
 
 
 def solve(guide, target, conf, sigma_s, sigma_r, filter_iters=3, solver_iters=10, lam=0.99,

@@ -119,6 +119,36 @@ static float log2_feedback(double sigma_s, int i, int N) {
     return static_cast<float>(-sqrt(2.0) / sigma_h / log(2.0));
 }
 
+// a_i itself, in double
+static double feedback(double sigma_s, int i, int N) {
+    const double sigma_h = sigma_s * sqrt(3.0) * ldexp(1.0, N - i) / sqrt(ldexp(1.0, 2 * N) - 1.0);
+    return exp(-sqrt(2.0) / sigma_h);
+}
+
+// Support workspace: [header | dx | dy | tmp | chunk aggregates (float4) | carries (float2)]
+struct SupportLayout {
+    size_t dx, dy, tmp, agg, carry, total;
+};
+
+static SupportLayout make_support_layout(int batch, int H, int W) {
+    SupportLayout L;
+    const size_t plane = static_cast<size_t>(batch) * H * W * sizeof(float);
+    const size_t chunks = static_cast<size_t>(batch) * support_chunks(H) * W;
+    size_t off = kHeaderBytes;
+    L.dx = off;
+    off = align_up(off + plane);
+    L.dy = off;
+    off = align_up(off + plane);
+    L.tmp = off;
+    off = align_up(off + plane);
+    L.agg = off;
+    off = align_up(off + chunks * 16);
+    L.carry = off;
+    off = align_up(off + chunks * 8);
+    L.total = off;
+    return L;
+}
+
 struct Setup {
     Ctx ctx;
     Layout L;
@@ -568,6 +598,57 @@ int dts_variance_confidence(const float* guide, int Cg, const float* z, float* c
         if ((rc = launch_col_pass(cp, S.ctx))) return rc;
     }
     return launch_variance_confidence(m, conf, C, batch, static_cast<size_t>(H) * W, sigma_c, S.ctx.stream);
+}
+
+size_t dts_support_workspace_bytes(int batch, int H, int W) {
+    if (check_shape(batch, H, W)) return 0;
+    return make_support_layout(batch, H, W).total;
+}
+
+int dts_support(const float* guide, int Cg, int batch, int H, int W, float sigma_s, float sigma_r,
+                int filter_iters, float* support, const float* conf, int Cc, float* conf_out, void* workspace,
+                size_t workspace_bytes, void* stream) {
+    if (!guide || !support) return DTS_EINVAL;
+    int rc = check_shape(batch, H, W);
+    if (rc) return rc;
+    if (check_channels(Cg)) return DTS_EINVAL;
+    if (!finite_pos(sigma_s) || !finite_pos(sigma_r)) return DTS_EINVAL;
+    if (filter_iters < 1 || filter_iters > kMaxFilterIters) return DTS_EINVAL;
+    if (conf && (!conf_out || check_channels(Cc))) return DTS_EINVAL;
+    if (conf && (conf == support || conf_out == support)) return DTS_EINVAL;
+    const SupportLayout L = make_support_layout(batch, H, W);
+    if (workspace == nullptr || workspace_bytes < L.total) return DTS_EWORKSPACE;
+    if ((reinterpret_cast<uintptr_t>(workspace) & 15u) != 0) return DTS_EWORKSPACE;
+    char* base = static_cast<char*>(workspace);
+    float* dx = reinterpret_cast<float*>(base + L.dx);
+    float* dy = reinterpret_cast<float*>(base + L.dy);
+    float* tmp = reinterpret_cast<float*>(base + L.tmp);
+    Ctx ctx;
+    ctx.stream = static_cast<hipStream_t>(stream);
+    RowPass rp{};
+    rp.guide = guide;
+    rp.dx_out = dx;
+    rp.dy_out = dy;
+    rp.Cg = Cg;
+    rp.s2 = static_cast<float>((static_cast<double>(sigma_s) / sigma_r) *
+                               (static_cast<double>(sigma_s) / sigma_r));
+    rp.C = 0;  // distances only
+    rp.H = H;
+    rp.W = W;
+    rp.batch = batch;
+    if ((rc = launch_row_pass(rp, ctx))) return rc;
+    for (int i = 1; i <= filter_iters; ++i) {
+        const float l2a = log2_feedback(sigma_s, i, filter_iters);
+        const double a = feedback(sigma_s, i, filter_iters);
+        const float m = static_cast<float>((1.0 - a) / (1.0 + a));
+        if ((rc = launch_support_row(i == 1 ? nullptr : support, dx, tmp, batch, H, W, l2a, m, ctx.stream)))
+            return rc;
+        const bool last = i == filter_iters;
+        if ((rc = launch_support_col(tmp, dy, support, base + L.agg, base + L.carry, last ? conf : nullptr, Cc,
+                                     last ? conf_out : nullptr, batch, H, W, l2a, m, ctx.stream)))
+            return rc;
+    }
+    return DTS_OK;
 }
 
 int dts_distances(const float* guide, int Cg, int batch, int H, int W, float sigma_s,

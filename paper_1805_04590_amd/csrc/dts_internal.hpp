@@ -122,6 +122,11 @@ int launch_stereo_data_grad(const float* z, const float* t, const float* c, cons
 int launch_variance_confidence(const float* moments, float* conf, int C, int batch, size_t plane,
                                float sigma_c, hipStream_t s);
 int launch_copy(float* dst, const float* src, size_t n, hipStream_t s);
+size_t support_chunks(int H);
+int launch_support_row(const float* src, const float* dx, float* dst, int batch, int H, int W, float log2a,
+                       float m, hipStream_t s);
+int launch_support_col(const float* src, const float* dy, float* dst, void* agg, void* carry, const float* conf,
+                       int Cc, float* conf_out, int batch, int H, int W, float log2a, float m, hipStream_t s);
 
 // RAII launch timer: records a start event on construction and a stop event on
 // destruction (both on `s`) when timing is enabled; a no-op otherwise.

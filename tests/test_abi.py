@@ -174,3 +174,23 @@ def test_solve_stereo_rejects_bad_arguments_without_launching(lib):
     assert lib.dts_solve_stereo(fake, fake, 3, fake, fake, 1, 8, 8, ctypes.byref(p), 0.001, 0.001, None, fake, ok, None) == dts.DTS_EINVAL
     assert lib.dts_solve_stereo(fake, fake, 3, fake, fake, 1, 8, 8, ctypes.byref(p), 0.001, 0.001, fake, fake, ok - 256, None) == dts.DTS_EWORKSPACE
 
+
+
+def test_support_rejects_bad_arguments_without_launching(lib):
+    assert lib.dts_support_workspace_bytes(1, 8, 8) > 0
+    assert lib.dts_support_workspace_bytes(0, 8, 8) == 0
+    fake = ctypes.c_void_p(0x10000)
+    other = ctypes.c_void_p(0x20000)
+    ok = lib.dts_support_workspace_bytes(1, 8, 8)
+    # null guide or output, bad channels or sigma, N = 0, confidence without an output or
+    # aliasing the support, too-small workspace: refused before any launch
+    assert lib.dts_support(None, 3, 1, 8, 8, 8.0, 0.2, 3, fake, None, 0, None, fake, ok, None) == dts.DTS_EINVAL
+    assert lib.dts_support(fake, 3, 1, 8, 8, 8.0, 0.2, 3, None, None, 0, None, fake, ok, None) == dts.DTS_EINVAL
+    assert lib.dts_support(fake, 17, 1, 8, 8, 8.0, 0.2, 3, fake, None, 0, None, fake, ok, None) == dts.DTS_EINVAL
+    assert lib.dts_support(fake, 3, 1, 8, 8, 0.0, 0.2, 3, fake, None, 0, None, fake, ok, None) == dts.DTS_EINVAL
+    assert lib.dts_support(fake, 3, 1, 8, 8, 8.0, 0.2, 0, fake, None, 0, None, fake, ok, None) == dts.DTS_EINVAL
+    assert lib.dts_support(fake, 3, 1, 8, 8, 8.0, 0.2, 3, fake, other, 1, None, fake, ok, None) == dts.DTS_EINVAL
+    assert lib.dts_support(fake, 3, 1, 8, 8, 8.0, 0.2, 3, fake, other, 0, other, fake, ok, None) == dts.DTS_EINVAL
+    assert lib.dts_support(fake, 3, 1, 8, 8, 8.0, 0.2, 3, fake, other, 1, fake, fake, ok, None) == dts.DTS_EINVAL
+    assert lib.dts_support(fake, 3, 1, 8, 8, 8.0, 0.2, 3, fake, None, 0, None, fake, ok - 256, None) == dts.DTS_EWORKSPACE
+    assert lib.dts_support(fake, 3, 1, 0, 8, 8.0, 0.2, 3, fake, None, 0, None, fake, ok, None) == dts.DTS_EINVAL

@@ -1,0 +1,93 @@
+"""Support-weighted confidence (Sec. 3.1, after Eq. (6); reading R10) on the GPU against
+the FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import dts_inputs
+import oracle
+import paper_1805_04590_amd as dts
+
+pytestmark = pytest.mark.gpu
+
+# s lies in (0, 1] and c / s can be large where s is small: both are compared relative to
+# the reference.  fp32 error of one pass is a few ulp times the pass sum over its
+# normalisation, at most ~1 / (1 - a) ~ 40 ulp for sigma_s = 32; six passes stay below 1e-5.
+RTOL = 1e-4
+
+CASES = [
+    # H, W, Cg, N, batch, sigma_s, sigma_r
+    (1, 1, 1, 3, 1, 8.0, 0.2),
+    (1, 300, 3, 3, 1, 8.0, 0.2),
+    (300, 1, 3, 3, 1, 8.0, 0.2),
+    (67, 129, 3, 3, 2, 6.0, 0.25),
+    (33, 31, 16, 1, 1, 4.0, 0.2),
+    (200, 300, 8, 2, 1, 12.0, 0.15),
+    (37, 1500, 1, 3, 1, 20.0, 0.3),
+    (1500, 37, 3, 3, 1, 32.0, 0.1),
+    (65, 4500, 3, 3, 1, 32.0, 0.2),
+]
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _rel_err(got, ref):
+    return float(np.max(np.abs(got - ref) / np.abs(ref)))
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}x{c[1]}_Cg{c[2]}_N{c[3]}_B{c[4]}" for c in CASES])
+def test_support_matches_oracle(case):
+    H, W, Cg, N, B, ss, sr = case
+    print("CASE support", case, flush=True)
+    rng = np.random.default_rng(H * 7919 + W * 31 + Cg + N)
+    guides = [dts_inputs.random_case(int(rng.integers(1 << 30)), H, W, Cg, 1, Cc=1, sigma_s=ss,
+                                     sigma_r=sr, T=1)["guide"] for _ in range(B)]
+    g = np.stack(guides)
+    s = dts.support(dev(g), ss, sr, filter_iters=N).cpu().numpy()
+    torch.cuda.synchronize()
+    for b in range(B):
+        ref = oracle.support(g[b], ss, sr, N)
+        assert _rel_err(s[b], ref) <= RTOL, (case, b)
+
+
+@pytest.mark.parametrize("alias", [False, True])
+def test_weighted_confidence_matches_oracle(alias):
+    H, W, Cg, Cc, ss, sr = 90, 140, 3, 2, 10.0, 0.2
+    print("CASE support confidence alias", alias, flush=True)
+    c = dts_inputs.random_case(5, H, W, Cg, 2, Cc=Cc, sigma_s=ss, sigma_r=sr, T=1)
+    conf = dev(c["conf"])
+    out = conf if alias else None
+    s, cw = dts.support(dev(c["guide"]), ss, sr, conf=conf, conf_out=out)
+    ref_c, ref_s = oracle.support_confidence(c["guide"], c["conf"], ss, sr)
+    assert _rel_err(s.cpu().numpy(), ref_s) <= RTOL
+    assert _rel_err(cw.cpu().numpy(), ref_c) <= RTOL
+    if alias:
+        assert cw.data_ptr() == conf.data_ptr()
+
+
+def test_uniform_guide_is_the_toeplitz_cascade():
+    # independent of the oracle: per-axis cascades of explicit a^|i-j| matrices
+    H, W, ss = 45, 77, 8.0
+    alist = oracle.feedback_coefficients(ss, 3)
+
+    def axis(L):
+        idx = np.arange(L)
+        v = np.ones(L)
+        for a in alist:
+            v = (1 - a) / (1 + a) * (np.power(a, np.abs(idx[:, None] - idx[None, :]).astype(float)) @ v)
+        return v
+
+    s = dts.support(dev(np.full((3, H, W), 0.4)), ss, 0.1).cpu().numpy()
+    assert _rel_err(s, np.outer(axis(H), axis(W))) <= RTOL
+
+
+def test_full_size_stereo_shape():
+    # the 1920 x 1080 RGB guide of the stereo-shaped workload, sigma_s = 16, sigma_r = 0.1
+    c = dts_inputs.config2(seed=1)
+    print("CASE support 1920x1080", flush=True)
+    s, cw = dts.support(dev(c["guide"]), c["sigma_s"], c["sigma_r"], conf=dev(c["conf"]))
+    ref_c, ref_s = oracle.support_confidence(c["guide"], c["conf"], c["sigma_s"], c["sigma_r"])
+    assert _rel_err(s.cpu().numpy(), ref_s) <= RTOL
+    assert _rel_err(cw.cpu().numpy(), ref_c) <= RTOL
