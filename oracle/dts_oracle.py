@@ -55,6 +55,11 @@ __all__ = [
     "support_lines",
     "support",
     "support_confidence",
+    "box_codes",
+    "box_radii",
+    "box_lines",
+    "box_filter",
+    "solve_box",
     "sample_row_linear",
     "stereo_data_gradient",
     "energy_stereo",
@@ -434,6 +439,98 @@ def support_confidence(guide, conf, sigma_s, sigma_r, filter_iters=3, dists=None
     conf [Cc][H][W].  Returns (c / s, s)."""
     s = support(guide, sigma_s, sigma_r, filter_iters, dists)
     return np.asarray(conf, dtype=np.float64) / s[None], s
+
+
+# ----------------------------------------------------------------------------------------
+# Box form of the edge-aware mean (Sec. 3.2, Eq. (10) read literally): the kernel H is the
+# indicator of |DT_i - DT_j| <= r, i.e. the mean over the pixels of the same line whose
+# transformed coordinates lie within r of pixel i's (a normalised convolution).
+# Readings (listed in the design notes):
+#   B1  the transformed coordinate of a line is the running sum of the arc-length
+#       increments d of Eq. (9) (reading R1), ct[0] = 0, ct[n] = ct[n-1] + d[n];
+#   B2  the radius, never given, is that of the box with the variance of the recursive
+#       form's iteration: r_i = sqrt(3) sigma_Hi, with the same sigma_Hi schedule (R3);
+#   B3  iterations alternate rows then columns as in O4;
+#   B4  membership is an integer decision: each d is computed in float32 as
+#       sqrt(1 + s2 * sum_k (I_k[n] - I_k[n-1])^2) (each operation rounded to nearest,
+#       bands summed in order, s2 = (sigma_s/sigma_r)^2 rounded to float32) and coded as
+#       q = rint(256 d), the coordinate is the integer sum of the codes, the radius is
+#       R_i = floor(256 r_i), and j belongs to i's box iff |ct_i - ct_j| <= R_i.
+# ----------------------------------------------------------------------------------------
+def box_codes(guide, sigma_s, sigma_r):
+    """Integer codes (qx, qy) [H][W] of the arc-length increments in units of 1/256
+    pixel (reading B4); qx[:, 0] and qy[0, :] are unused and set to 0."""
+    s2 = np.float32((float(np.float32(sigma_s)) / float(np.float32(sigma_r))) ** 2)
+    acc_x = acc_y = None
+    for band in guide:
+        b = np.asarray(band, dtype=np.float32)
+        if acc_x is None:
+            acc_x = np.zeros_like(b)
+            acc_y = np.zeros_like(b)
+        ex = b[:, 1:] - b[:, :-1]
+        ey = b[1:, :] - b[:-1, :]
+        acc_x[:, 1:] = acc_x[:, 1:] + ex * ex
+        acc_y[1:, :] = acc_y[1:, :] + ey * ey
+    one, scale = np.float32(1.0), np.float32(256.0)
+    qx = np.rint(np.sqrt(one + s2 * acc_x) * scale).astype(np.int64)
+    qy = np.rint(np.sqrt(one + s2 * acc_y) * scale).astype(np.int64)
+    qx[:, 0] = 0
+    qy[0, :] = 0
+    return qx, qy
+
+
+def box_radii(sigma_s, filter_iters):
+    """R_i = floor(256 sqrt(3) sigma_Hi), i = 1..N (readings B2, B4)."""
+    N = int(filter_iters)
+    out = []
+    for i in range(1, N + 1):
+        sigma_h = float(np.float32(sigma_s)) * math.sqrt(3.0) * 2.0 ** (N - i) / math.sqrt(4.0 ** N - 1.0)
+        out.append(int(math.floor(sigma_h * math.sqrt(3.0) * 256.0)))
+    return out
+
+
+def box_lines(f, q, R):
+    """Box mean along axis 0 of ``f`` [L][M] (columns are independent lines) with codes
+    q [L][M]: out[n] = mean of f[j] over the j with |ct[n] - ct[j]| <= R."""
+    f = np.asarray(f, dtype=np.float64)
+    q = np.asarray(q, dtype=np.int64).copy()
+    q[0] = 0
+    ct = np.cumsum(q, axis=0)
+    out = np.empty_like(f)
+    for m in range(f.shape[1]):
+        c = ct[:, m]
+        lo = np.searchsorted(c, c - R, side="left")          # first j with ct[j] >= ct[n] - R
+        hi = np.searchsorted(c, c + R, side="right") - 1     # last j with ct[j] <= ct[n] + R
+        P = np.concatenate([[0.0], np.cumsum(f[:, m])])
+        out[:, m] = (P[hi + 1] - P[lo]) / (hi - lo + 1)
+    return out
+
+
+def box_filter(src, qx, qy, sigma_s, filter_iters):
+    """N box iterations, each along rows then along columns, on every channel of
+    src [C][H][W] with the same codes (readings B1-B4)."""
+    z = np.asarray(src, dtype=np.float64)
+    out = np.empty_like(z)
+    for R in box_radii(sigma_s, filter_iters):
+        for c in range(z.shape[0]):
+            out[c] = box_lines(z[c].T, qx.T, R).T
+            out[c] = box_lines(out[c], qy, R)
+        z = out.copy()
+    return z
+
+
+def solve_box(guide, target, conf, sigma_s, sigma_r, filter_iters=3, solver_iters=10,
+              lam=0.99, step=0.99):
+    """The solver of O5 with the box form of the edge-aware mean:
+    z^0 = t, z^{k+1} = z^k - step (lam (z^k - BOX(z^k)) + c (z^k - t))."""
+    qx, qy = box_codes(guide, sigma_s, sigma_r)
+    t = np.asarray(target, dtype=np.float64)
+    c = np.asarray(conf, dtype=np.float64)
+    z = t.copy()
+    for _ in range(int(solver_iters)):
+        zbar = box_filter(z, qx, qy, sigma_s, filter_iters)
+        z = z - step * (lam * (z - zbar) + c * (z - t))
+    return z
 
 
 # ----------------------------------------------------------------------------------------
