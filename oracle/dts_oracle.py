@@ -453,14 +453,16 @@ def support_confidence(guide, conf, sigma_s, sigma_r, filter_iters=3, dists=None
 #   B3  iterations alternate rows then columns as in O4;
 #   B4  membership is an integer decision: each d is computed in float32 as
 #       sqrt(1 + s2 * sum_k (I_k[n] - I_k[n-1])^2) (each operation rounded to nearest,
-#       bands summed in order, s2 = (sigma_s/sigma_r)^2 rounded to float32) and coded as
+#       bands summed in order, s2 = the double product (sigma_s/sigma_r)(sigma_s/sigma_r)
+#       rounded to float32, sigma_s and sigma_r taken as float32) and coded as
 #       q = rint(256 d), the coordinate is the integer sum of the codes, the radius is
 #       R_i = floor(256 r_i), and j belongs to i's box iff |ct_i - ct_j| <= R_i.
 # ----------------------------------------------------------------------------------------
 def box_codes(guide, sigma_s, sigma_r):
     """Integer codes (qx, qy) [H][W] of the arc-length increments in units of 1/256
     pixel (reading B4); qx[:, 0] and qy[0, :] are unused and set to 0."""
-    s2 = np.float32((float(np.float32(sigma_s)) / float(np.float32(sigma_r))) ** 2)
+    ratio = float(np.float32(sigma_s)) / float(np.float32(sigma_r))
+    s2 = np.float32(ratio * ratio)
     acc_x = acc_y = None
     for band in guide:
         b = np.asarray(band, dtype=np.float32)
