@@ -209,6 +209,28 @@ def fwd_bwd_leg(steps, warmup):
                 fwd_bwd_over_fwd=round(ms_fb / ms_f, 3))
 
 
+def kernel_table(step, steps):
+    """Per-kernel launches, average duration and algorithmic GB/s over `steps` calls of
+    `step`, from the HIP events the library records around each of its launches."""
+    import torch
+
+    import paper_1805_04590_amd as dts
+
+    dts.profile_enable(True)
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    stats = dts.profile_read()
+    dts.profile_enable(False)
+    total = sum(v["total_ms"] for v in stats.values())
+    kernels = {}
+    for name, s in stats.items():
+        kernels[name] = dict(launches_per_step=s["launches"] / steps, avg_us=s["avg_ms"] * 1e3,
+                             share=s["total_ms"] / total,
+                             algorithmic_GBps=s["bytes_per_launch"] / (s["avg_ms"] / 1e3) / 1e9)
+    return kernels, stats
+
+
 def solve_leg(args, dev):
     """The headline workload: Mpixel/s of dts_solve and, unless --no-profile, the per-kernel
     timing (HIP events around every launch) and the dominant kernel's roofline."""
@@ -267,18 +289,7 @@ def solve_leg(args, dev):
     roofline = None
     if not args.no_profile:
         log("per-kernel timing run (HIP events around each launch)")
-        dts.profile_enable(True)
-        for _ in range(args.steps):
-            step()
-        torch.cuda.synchronize()
-        stats = dts.profile_read()
-        dts.profile_enable(False)
-        for name, s in stats.items():
-            gbps = s["bytes_per_launch"] / (s["avg_ms"] / 1e3) / 1e9
-            kernels[name] = dict(launches_per_step=s["launches"] / args.steps,
-                                 avg_us=s["avg_ms"] * 1e3,
-                                 share=s["total_ms"] / sum(v["total_ms"] for v in stats.values()),
-                                 algorithmic_GBps=gbps)
+        kernels, stats = kernel_table(step, args.steps)
         dom = max(stats, key=lambda k: stats[k]["total_ms"])
         s = stats[dom]
         achieved = s["bytes_per_launch"] / (s["avg_ms"] / 1e3) / 1e9
@@ -329,11 +340,39 @@ def solve_leg(args, dev):
                    ms=round(ms_s, 3), mpix_s=round(px / ms_s / 1e3, 1),
                    algorithmic_GBps=round(s_bytes / (ms_s / 1e3) / 1e9, 1),
                    hbm_frac=round(s_bytes / (ms_s / 1e3) / 1e9 / HBM_PEAK_GBPS, 4))
+    if not args.no_profile:
+        support["kernels"] = {k: {kk: round(vv, 3) for kk, vv in v.items()}
+                              for k, v in kernel_table(sstep, 2)[0].items()}
     log("  support: " + json.dumps(support))
-    del guide, target, conf, out, ws, wss, sup, confs
+    del wss, sup, confs
+
+    # the box form of the edge-aware mean (Eq. (10) as written) in the same solve
+    wsb = torch.empty(lib.dts_box_workspace_bytes(1, H, W, Ct, N), dtype=torch.uint8, device=dev)
+    outb = torch.empty_like(target)
+
+    def bstep():
+        dts.solve_box(guide, target, conf, ss, sr, N, T, out=outb[None], workspace=wsb)
+
+    ms_b = timed(bstep, args.steps, args.warmup)
+    # codes (guide in, two code planes out); row and column bounds (codes in, N bound planes
+    # out each); per iteration N row passes (signal and bounds in, signal out), N - 1 column
+    # passes (the same) and one column pass with the update (z^k, t and c in as well)
+    b_bytes = px * (4 * (Cg + 2) + 2 * (4 + 2 * N)
+                    + T * (N * (8 * Ct + 2) + (N - 1) * 10 * Ct + 18 * Ct + 4 * Cc))
+    box = dict(workload=f"solve with the box kernel (Eq. 10 as written) on the same {W}x{H} workload, "
+                        f"N={N}, T={T}",
+               ms=round(ms_b, 3), mpix_s=round(px / ms_b / 1e3, 1),
+               algorithmic_GBps=round(b_bytes / (ms_b / 1e3) / 1e9, 1),
+               hbm_frac=round(b_bytes / (ms_b / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
+               over_recursive=round(ms_b / ms, 3))
+    if not args.no_profile:
+        box["kernels"] = {k: {kk: round(vv, 3) for kk, vv in v.items()}
+                          for k, v in kernel_table(bstep, 2)[0].items()}
+    log("  box: " + json.dumps(box))
+    del guide, target, conf, out, ws, wsb, outb
     torch.cuda.empty_cache()
     return dict(ms=ms, mpix=mpix, solve_bytes=solve_bytes, kernels=kernels, roofline=roofline,
-                H=H, W=W, Cg=Cg, Ct=Ct, T=T, N=N, ss=ss, sr=sr, variance=variance, support=support)
+                H=H, W=W, Cg=Cg, Ct=Ct, T=T, N=N, ss=ss, sr=sr, variance=variance, support=support, box=box)
 
 
 def stereo_leg(steps, warmup):
@@ -425,7 +464,7 @@ def main():
 
     if sol is None:
         sol = dict(ms=None, mpix=None, solve_bytes=None, kernels={}, roofline=None, H=None, W=None,
-                   Cg=None, Ct=None, T=None, N=None, ss=None, sr=None, variance=None, support=None)
+                   Cg=None, Ct=None, T=None, N=None, ss=None, sr=None, variance=None, support=None, box=None)
     ms, mpix = sol["ms"], sol["mpix"]
     gbps = None if ms is None else sol["solve_bytes"] / (ms / 1e3) / 1e9
     res = {
@@ -454,6 +493,7 @@ def main():
         "kernels": sol["kernels"],
         "variance": sol["variance"],
         "support": sol["support"],
+        "box": sol["box"],
     }
     res.update(extras)
     print(json.dumps(res), flush=True)

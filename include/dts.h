@@ -133,6 +133,38 @@ int dts_variance_confidence(const float* guide, int Cg, const float* z, float* c
                             int H, int W, float sigma_s, float sigma_r, int filter_iters, float sigma_c,
                             void* workspace, size_t workspace_bytes, void* stream);
 
+/* ---- Box form of the edge-aware mean (Sec. 3.2, Eq. (10) as written) ---- */
+
+/* Workspace for dts_filter_box / dts_solve_box with C signal channels and filter_iters
+ * iterations (0 if the arguments are invalid). */
+size_t dts_box_workspace_bytes(int batch, int H, int W, int C, int filter_iters);
+
+/* Integer codes of the arc-length increments that decide box membership:
+ * q = rint(256 d) with d = sqrt(1 + s2 sum_k (I_k[n] - I_k[n-1])^2) evaluated in float32,
+ * every operation rounded to nearest, bands summed in order, s2 = (sigma_s/sigma_r)^2
+ * rounded to float32; capped at 65536.  qx, qy: device arrays of batch*H*W uint32;
+ * qx[..][0] and qy[..][0][..] are 0 (no pixel before them).  Errors as dts_distances. */
+int dts_box_codes(const float* guide, int Cg, int batch, int H, int W, float sigma_s, float sigma_r,
+                  unsigned int* qx, unsigned int* qy, void* stream);
+
+/* Edge-aware mean with the box kernel that Eq. (10) writes: along a line, the mean of the
+ * samples j with |ct_i - ct_j| <= R_i, where ct is the running sum of the codes of
+ * dts_box_codes and R_i = floor(256 sqrt(3) sigma_Hi) is the box with the variance of
+ * the recursive filter's iteration i (sigma_Hi as for dts_filter).  filter_iters (<= 8)
+ * iterations, each along rows then columns, on every channel of src with the same boxes.
+ * Layouts and aliasing as dts_filter.  Returns DTS_ENOTSUP when R_1 / 256 exceeds 255 pixels
+ * (sigma_s above about 169 for N = 3) or its column ring exceeds the device's LDS. */
+int dts_filter_box(const float* guide, int Cg, const float* src, float* dst, int C, int batch, int H, int W,
+                   float sigma_s, float sigma_r, int filter_iters, void* workspace, size_t workspace_bytes,
+                   void* stream);
+
+/* dts_solve with the box form of the edge-aware mean: z^0 = t,
+ * z^{k+1} = z^k - step (lambda (z^k - BOX(z^k)) + c (z^k - t)).  Arguments as dts_solve
+ * without checkpoints; filter_iters <= 8; limits as dts_filter_box. */
+int dts_solve_box(const float* guide, int Cg, const float* target, const float* conf, int Cc, int Ct, int batch,
+                  int H, int W, const dts_params* p, float* out, void* workspace, size_t workspace_bytes,
+                  void* stream);
+
 /* ---- Support-weighted confidence (Sec. 3.1, after Eq. (6)) ---- */
 
 /* Workspace for dts_support (0 if the shape is invalid). */

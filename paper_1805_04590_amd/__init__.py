@@ -74,6 +74,10 @@ EXPORTED_SYMBOLS = (
     "dts_variance_confidence_workspace_bytes",
     "dts_variance_confidence",
     "dts_support_workspace_bytes",
+    "dts_box_workspace_bytes",
+    "dts_box_codes",
+    "dts_filter_box",
+    "dts_solve_box",
     "dts_support",
     "dts_distances",
     "dts_pass_workspace_bytes",
@@ -212,6 +216,14 @@ def library():
     lib.dts_support_workspace_bytes.restype = sz
     lib.dts_support.argtypes = [fp, i, i, i, i, f, f, i, fp, fp, i, fp, vp, sz, vp]
     lib.dts_support.restype = i
+    lib.dts_box_workspace_bytes.argtypes = [i, i, i, i, i]
+    lib.dts_box_workspace_bytes.restype = sz
+    lib.dts_box_codes.argtypes = [fp, i, i, i, i, f, f, vp, vp, vp]
+    lib.dts_box_codes.restype = i
+    lib.dts_filter_box.argtypes = [fp, i, fp, fp, i, i, i, i, f, f, i, vp, sz, vp]
+    lib.dts_filter_box.restype = i
+    lib.dts_solve_box.argtypes = [fp, i, fp, fp, i, i, i, i, i, P, fp, vp, sz, vp]
+    lib.dts_solve_box.restype = i
     lib.dts_distances.argtypes = [fp, i, i, i, i, f, f, fp, fp, vp]
     lib.dts_distances.restype = i
     lib.dts_pass_workspace_bytes.argtypes = [i, i, i, i]
@@ -549,6 +561,56 @@ def variance_confidence(guide, z, sigma_s, sigma_r, sigma_c, filter_iters=3, out
                                      float(sigma_c), _ptr(workspace), workspace.numel(), _stream())
     _check(rc, "dts_variance_confidence")
     return out if z.dim() == 4 else out[0]
+
+
+def box_codes(guide, sigma_s, sigma_r):
+    """(qx, qy), each [B][H][W] int32 holding the uint32 codes round(256 d) that decide box
+    membership (``dts_box_codes``)."""
+    g = _as4d(guide, "guide")
+    B, Cg, H, W = g.shape
+    qx = torch.empty((B, H, W), dtype=torch.int32, device=g.device)
+    qy = torch.empty_like(qx)
+    _check(library().dts_box_codes(_ptr(g), Cg, B, H, W, float(sigma_s), float(sigma_r), _ptr(qx), _ptr(qy),
+                                   _stream()), "dts_box_codes")
+    return qx, qy
+
+
+def filter_box(guide, src, sigma_s, sigma_r, filter_iters=3, out=None, workspace=None):
+    """Edge-aware mean with the box kernel of Eq. (10) (``dts_filter_box``)."""
+    g = _as4d(guide, "guide")
+    x = _as4d(src, "src")
+    B, C, H, W = x.shape
+    if g.shape[0] != B or g.shape[2:] != x.shape[2:]:
+        raise ValueError("guide and src disagree in batch or image size")
+    lib = library()
+    out = torch.empty_like(x) if out is None else _as4d(out, "out")
+    if out.shape != x.shape:
+        raise ValueError("out must have the shape of src")
+    if workspace is None:
+        workspace = _workspace(lib.dts_box_workspace_bytes(B, H, W, C, int(filter_iters)), x.device)
+    _check(lib.dts_filter_box(_ptr(g), g.shape[1], _ptr(x), _ptr(out), C, B, H, W, float(sigma_s),
+                              float(sigma_r), int(filter_iters), _ptr(workspace), workspace.numel(),
+                              _stream()), "dts_filter_box")
+    return out if src.dim() == 4 else out[0]
+
+
+def solve_box(guide, target, conf, sigma_s, sigma_r, filter_iters=3, solver_iters=10, lam=0.99, step=0.99,
+              out=None, workspace=None):
+    """z^T of the Eq. (3) descent with the box form of the edge-aware mean (``dts_solve_box``)."""
+    g = _as4d(guide, "guide")
+    t = _as4d(target, "target")
+    c = _as4d(conf, "conf")
+    B, Ct, H, W = t.shape
+    if g.shape[0] != B or g.shape[2:] != t.shape[2:] or c.shape[0] != B or c.shape[2:] != t.shape[2:]:
+        raise ValueError("guide/target/conf disagree in batch or image size")
+    p = Params(sigma_s, sigma_r, filter_iters, solver_iters, lam, step).c()
+    lib = library()
+    out = torch.empty_like(t) if out is None else _as4d(out, "out")
+    if workspace is None:
+        workspace = _workspace(lib.dts_box_workspace_bytes(B, H, W, Ct, int(filter_iters)), t.device)
+    _check(lib.dts_solve_box(_ptr(g), g.shape[1], _ptr(t), _ptr(c), c.shape[1], Ct, B, H, W, ctypes.byref(p),
+                             _ptr(out), _ptr(workspace), workspace.numel(), _stream()), "dts_solve_box")
+    return out if target.dim() == 4 else out[0]
 
 
 def support(guide, sigma_s, sigma_r, filter_iters=3, conf=None, out=None, conf_out=None,

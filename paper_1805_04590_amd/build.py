@@ -10,7 +10,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libdts.so")
-SOURCES = ["dts_api.hip", "dts_forward.hip", "dts_adjoint.hip", "dts_batched.hip", "dts_support.hip", "dts_profile.hip"]
+SOURCES = ["dts_api.hip", "dts_forward.hip", "dts_adjoint.hip", "dts_batched.hip", "dts_support.hip", "dts_box.hip", "dts_profile.hip"]
 
 HIPCC_FLAGS = [
     "-O3",

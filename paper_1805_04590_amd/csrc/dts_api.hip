@@ -149,6 +149,97 @@ static SupportLayout make_support_layout(int batch, int H, int W) {
     return L;
 }
 
+// Box workspace: [header | qx | qy (u32 codes) | bx | by (u16 bounds, one plane per
+// iteration) | t1 | t2 (C planes each)]
+struct BoxLayout {
+    size_t qx, qy, bx, by, t1, t2, total;
+};
+
+static BoxLayout make_box_layout(int batch, int H, int W, int C, int N) {
+    BoxLayout L;
+    const size_t px = static_cast<size_t>(batch) * H * W;
+    size_t off = kHeaderBytes;
+    L.qx = off;
+    off = align_up(off + px * 4);
+    L.qy = off;
+    off = align_up(off + px * 4);
+    L.bx = off;
+    off = align_up(off + px * 2 * N);
+    L.by = off;
+    off = align_up(off + px * 2 * N);
+    L.t1 = off;
+    off = align_up(off + px * 4 * C);
+    L.t2 = off;
+    off = align_up(off + px * 4 * C);
+    L.total = off;
+    return L;
+}
+
+// Box radii in units of 1/256 pixel: R_i = floor(256 sqrt(3) sigma_Hi), the box with the
+// variance of the recursive filter's iteration i.
+static int box_radii(double sigma_s, int N, unsigned* R) {
+    for (int i = 1; i <= N; ++i) {
+        const double sigma_h = sigma_s * sqrt(3.0) * ldexp(1.0, N - i) / sqrt(ldexp(1.0, 2 * N) - 1.0);
+        const double r = floor(sigma_h * sqrt(3.0) * 256.0);
+        if (!(r < 65536.0)) return DTS_ENOTSUP;  // the box offsets are stored in one byte
+        R[i - 1] = static_cast<unsigned>(r);
+    }
+    return box_check_radius(static_cast<int>(R[0] >> 8));
+}
+
+static float box_s2(float sigma_s, float sigma_r) {
+    const double q = static_cast<double>(sigma_s) / static_cast<double>(sigma_r);
+    return static_cast<float>(q * q);
+}
+
+// Codes and bounds of one call, then N (row, column) passes from src; the last column
+// pass writes dst, with the solver update when zk is set.
+struct BoxCall {
+    unsigned R[kBoxMaxIters];
+    unsigned* qx;
+    unsigned* qy;
+    unsigned short* bx;
+    unsigned short* by;
+    float* t1;
+    float* t2;
+};
+
+static int box_begin(BoxCall& B, const float* guide, int Cg, int C, int batch, int H, int W, float sigma_s,
+                     float sigma_r, int N, void* ws, size_t ws_bytes, hipStream_t st) {
+    const BoxLayout L = make_box_layout(batch, H, W, C, N);
+    if (ws == nullptr || ws_bytes < L.total) return DTS_EWORKSPACE;
+    if ((reinterpret_cast<uintptr_t>(ws) & 15u) != 0) return DTS_EWORKSPACE;
+    int rc = box_radii(sigma_s, N, B.R);
+    if (rc) return rc;
+    char* base = static_cast<char*>(ws);
+    B.qx = reinterpret_cast<unsigned*>(base + L.qx);
+    B.qy = reinterpret_cast<unsigned*>(base + L.qy);
+    B.bx = reinterpret_cast<unsigned short*>(base + L.bx);
+    B.by = reinterpret_cast<unsigned short*>(base + L.by);
+    B.t1 = reinterpret_cast<float*>(base + L.t1);
+    B.t2 = reinterpret_cast<float*>(base + L.t2);
+    if ((rc = launch_box_codes(guide, Cg, batch, H, W, box_s2(sigma_s, sigma_r), B.qx, B.qy, st))) return rc;
+    return launch_box_bounds(B.qx, B.qy, B.bx, B.by, batch, H, W, B.R, N, st);
+}
+
+static int box_mean(const BoxCall& B, const float* src, float* dst, int C, int batch, int H, int W, int N,
+                    const float* zk, const float* tgt, const float* conf, int Cc, float lambda, float step,
+                    hipStream_t st) {
+    const size_t px = static_cast<size_t>(batch) * H * W;
+    const float* x = src;
+    for (int i = 0; i < N; ++i) {
+        const int h = static_cast<int>(B.R[i] >> 8);
+        int rc = launch_box_row(x, B.t1, B.bx + px * i, C, batch, H, W, h, st);
+        if (rc) return rc;
+        const bool last = i == N - 1;
+        rc = launch_box_col(B.t1, last ? dst : B.t2, B.by + px * i, C, batch, H, W, h, last ? zk : nullptr, tgt,
+                            conf, Cc, lambda, step, st);
+        if (rc) return rc;
+        x = B.t2;
+    }
+    return DTS_OK;
+}
+
 struct Setup {
     Ctx ctx;
     Layout L;
@@ -598,6 +689,70 @@ int dts_variance_confidence(const float* guide, int Cg, const float* z, float* c
         if ((rc = launch_col_pass(cp, S.ctx))) return rc;
     }
     return launch_variance_confidence(m, conf, C, batch, static_cast<size_t>(H) * W, sigma_c, S.ctx.stream);
+}
+
+size_t dts_box_workspace_bytes(int batch, int H, int W, int C, int filter_iters) {
+    if (check_shape(batch, H, W) || check_channels(C)) return 0;
+    if (filter_iters < 1 || filter_iters > kBoxMaxIters) return 0;
+    return make_box_layout(batch, H, W, C, filter_iters).total;
+}
+
+int dts_box_codes(const float* guide, int Cg, int batch, int H, int W, float sigma_s, float sigma_r,
+                  unsigned* qx, unsigned* qy, void* stream) {
+    if (!guide || !qx || !qy) return DTS_EINVAL;
+    int rc = check_shape(batch, H, W);
+    if (rc) return rc;
+    if (check_channels(Cg)) return DTS_EINVAL;
+    if (!finite_pos(sigma_s) || !finite_pos(sigma_r)) return DTS_EINVAL;
+    return launch_box_codes(guide, Cg, batch, H, W, box_s2(sigma_s, sigma_r), qx, qy,
+                            static_cast<hipStream_t>(stream));
+}
+
+int dts_filter_box(const float* guide, int Cg, const float* src, float* dst, int C, int batch, int H, int W,
+                   float sigma_s, float sigma_r, int filter_iters, void* workspace, size_t workspace_bytes,
+                   void* stream) {
+    if (!guide || !src || !dst || src == dst) return DTS_EINVAL;
+    int rc = check_shape(batch, H, W);
+    if (rc) return rc;
+    if (check_channels(Cg) || check_channels(C)) return DTS_EINVAL;
+    if (!finite_pos(sigma_s) || !finite_pos(sigma_r)) return DTS_EINVAL;
+    if (filter_iters < 1 || filter_iters > kBoxMaxIters) return DTS_EINVAL;
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    BoxCall B;
+    if ((rc = box_begin(B, guide, Cg, C, batch, H, W, sigma_s, sigma_r, filter_iters, workspace, workspace_bytes,
+                        st)))
+        return rc;
+    return box_mean(B, src, dst, C, batch, H, W, filter_iters, nullptr, nullptr, nullptr, 0, 0.f, 0.f, st);
+}
+
+int dts_solve_box(const float* guide, int Cg, const float* target, const float* conf, int Cc, int Ct, int batch,
+                  int H, int W, const dts_params* p, float* out, void* workspace, size_t workspace_bytes,
+                  void* stream) {
+    if (!guide || !target || !conf || !out || !p || out == target || out == conf) return DTS_EINVAL;
+    int rc = check_shape(batch, H, W);
+    if (rc) return rc;
+    if (check_channels(Cg) || check_channels(Ct)) return DTS_EINVAL;
+    if (Cc != 1 && Cc != Ct) return DTS_EINVAL;
+    if (!finite_pos(p->sigma_s) || !finite_pos(p->sigma_r)) return DTS_EINVAL;
+    if (p->filter_iters < 1 || p->filter_iters > kBoxMaxIters) return DTS_EINVAL;
+    if (p->solver_iters < 0 || p->solver_iters > kMaxSolverIters) return DTS_EINVAL;
+    if (!isfinite(p->lambda) || !isfinite(p->step)) return DTS_EINVAL;
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t sig = static_cast<size_t>(batch) * Ct * H * W;
+    BoxCall B;
+    if ((rc = box_begin(B, guide, Cg, Ct, batch, H, W, p->sigma_s, p->sigma_r, p->filter_iters, workspace,
+                        workspace_bytes, st)))
+        return rc;
+    if (p->solver_iters == 0) return launch_copy(out, target, sig, st);
+    for (int k = 0; k < p->solver_iters; ++k) {
+        // z^k is the target at k = 0 and `out` afterwards; the update reads z^k and writes
+        // z^{k+1} at the same pixel, so it can run in place
+        const float* zk = (k == 0) ? target : out;
+        if ((rc = box_mean(B, zk, out, Ct, batch, H, W, p->filter_iters, zk, target, conf, Cc, p->lambda, p->step,
+                           st)))
+            return rc;
+    }
+    return DTS_OK;
 }
 
 size_t dts_support_workspace_bytes(int batch, int H, int W) {

@@ -1,0 +1,635 @@
+// Box form of the edge-aware mean (Sec. 3.2, Eq. (10) as written): the kernel H is the
+// indicator of |DT_i - DT_j| <= r on the transformed coordinate of a line, so each 1-D
+// pass is the mean of the samples whose coordinate lies within r of the pixel's (a
+// normalised box convolution).  The radius r_i = sqrt(3) sigma_Hi is the box with the
+// variance of the recursive form's iteration i; passes alternate rows and columns.
+//
+// Membership is decided on integers, so that it cannot depend on summation order:
+//   q = rint(256 d), d = sqrt(1 + s2 sum_k (I_k[n] - I_k[n-1])^2) in float32 with every
+//   operation rounded to nearest (no contraction, bands summed in order), the coordinate
+//   is the integer running sum of q along the line, R_i = floor(256 r_i), and j is in the
+//   box of i iff |ct_i - ct_j| <= R_i.  Codes are capped at 65536, above every accepted
+//   radius, which changes no decision (a step larger than R excludes the pair either way).
+// Since d >= 1, a box never reaches more than h_i = R_i / 256 pixels from its centre.
+//
+// Kernels:
+//   box_codes_kernel        guide -> qx, qy (one pixel per thread)
+//   box_bounds_row_kernel   qx -> per pixel and iteration, the box as two u8 offsets
+//                           (a row segment's prefix of codes in LDS, binary searches)
+//   box_bounds_col_kernel   qy -> the same along columns (one column per lane, a ring
+//                           of the running coordinate in LDS)
+//   box_row_kernel          one row pass: FP64 prefix of the segment and its halo in LDS,
+//                           mean = (P[hi + 1] - P[lo]) / (hi - lo + 1)
+//   box_col_kernel<EPI>     one column pass: one column per lane walking down its rows;
+//                           an LDS ring keeps the float32 prefix within 32-row blocks and
+//                           the FP64 prefix at block starts, so a box sum only carries the
+//                           rounding of its own additions.  EPI: the update of Eq. (3).
+// The bounds depend on the guide only and are computed once per call; every pass then
+// reads its signal and two bytes of bounds per pixel and writes its result.
+#include <algorithm>
+
+#include "../../include/dts.h"
+#include "dts_device.hpp"
+#include "dts_internal.hpp"
+
+namespace dts {
+
+constexpr int kBoxSeg = 1024;          // row-pass outputs per workgroup
+constexpr int kBoxRowThreads = 256;
+constexpr int kBoxRowSpan = 2048;      // segment plus halo: 1024 + 2 * 255 < 2048
+constexpr int kBoxRowChunk = kBoxRowSpan / kBoxRowThreads;
+constexpr int kBoxLoad = 32;           // rows loaded per step of the column kernels
+constexpr int kBoxEmit = 8;            // outputs per block of the column pass
+constexpr unsigned kBoxCodeCap = 65536u;
+
+// ---------------------------------------------------------------------------------------
+// Integer codes of the arc-length increments
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ unsigned box_code(float acc, float s2) {
+#pragma clang fp contract(off)
+    const float d = sqrtf(1.0f + s2 * acc);
+    const float q = rintf(d * 256.0f);
+    return (q < 65536.0f) ? static_cast<unsigned>(q) : kBoxCodeCap;  // NaN takes the cap
+}
+
+__global__ void __launch_bounds__(256) box_codes_kernel(const float* __restrict__ guide, int Cg, int H, int W,
+                                                        float s2, unsigned* __restrict__ qx,
+                                                        unsigned* __restrict__ qy) {
+#pragma clang fp contract(off)
+    const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, b = blockIdx.z;
+    if (x >= W) return;
+    const size_t plane = static_cast<size_t>(H) * W;
+    const size_t i = static_cast<size_t>(y) * W + x;
+    const float* g = guide + static_cast<size_t>(b) * Cg * plane + i;
+    float ax = 0.0f, ay = 0.0f;
+    // bands four at a time: their loads are issued together, the sums stay in band order
+    for (int k0 = 0; k0 < Cg; k0 += 4) {
+        float v[4], l[4], u[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const bool in = k0 + q < Cg;
+            const float* gk = g + static_cast<size_t>(in ? k0 + q : 0) * plane;
+            v[q] = in ? gk[0] : 0.0f;
+            l[q] = (in && x > 0) ? gk[-1] : v[q];
+            u[q] = (in && y > 0) ? gk[-static_cast<ptrdiff_t>(W)] : v[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (k0 + q < Cg) {
+                const float ex = v[q] - l[q];
+                const float ey = v[q] - u[q];
+                ax = ax + ex * ex;
+                ay = ay + ey * ey;
+            }
+        }
+    }
+    const size_t e = static_cast<size_t>(b) * plane + i;
+    qx[e] = (x > 0) ? box_code(ax, s2) : 0u;
+    qy[e] = (y > 0) ? box_code(ay, s2) : 0u;
+}
+
+// ---------------------------------------------------------------------------------------
+// Workgroup scans (256 threads = 4 waves): exclusive prefix of one value per thread
+// ---------------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T* wtot) {
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    T incl = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const T u = __shfl_up(incl, o);
+        if (lane >= o) incl += u;
+    }
+    if (lane == kWave - 1) wtot[wave] = incl;
+    __syncthreads();
+    T off = 0;
+    for (int u = 0; u < wave; ++u) off += wtot[u];
+    __syncthreads();
+    return off + incl - v;
+}
+
+// Ring slot of the row `rel` rows after the row in slot `slot` (|rel| < RB).
+__device__ __forceinline__ int ring_slot(int slot, int rel, int RB) {
+    int v = slot + rel;
+    v += (v < 0) ? RB : 0;
+    v -= (v >= RB) ? RB : 0;
+    return v;
+}
+
+// Offsets of the box of local index li among the prefix coordinates Q[0..n): the first j
+// in [li - h, li] with Q[li] - Q[j] <= R and the last j in [li, li + h] with
+// Q[j] - Q[li] <= R.  Q is strictly increasing (every code >= 1).
+template <typename Get>
+__device__ __forceinline__ unsigned box_offsets(Get Q, int li, int first, int last, unsigned R, int h) {
+    const unsigned qi = Q(li);
+    int a = max(li - h, first), b = li;
+    while (a < b) {
+        const int m = (a + b) >> 1;
+        if (qi - Q(m) <= R) b = m; else a = m + 1;
+    }
+    const int lo = a;
+    a = li;
+    b = min(li + h, last);
+    while (a < b) {
+        const int m = (a + b + 1) >> 1;
+        if (Q(m) - qi <= R) a = m; else b = m - 1;
+    }
+    return static_cast<unsigned>(li - lo) | (static_cast<unsigned>(a - li) << 8);
+}
+
+struct BoxBoundsArgs {
+    const unsigned* q;        // codes [batch][H][W]
+    unsigned short* bounds;   // [iters][batch][H][W]
+    int H, W, iters;
+    unsigned cap;             // R_1 + 1
+    int h1;                   // R_1 / 256
+    int seg;                  // column kernel: output rows per workgroup
+    int ring;                 // column kernel: ring rows
+    unsigned R[kBoxMaxIters];
+};
+
+__global__ void __launch_bounds__(kBoxRowThreads) box_bounds_row_kernel(BoxBoundsArgs a) {
+    __shared__ unsigned Q[kBoxRowSpan];
+    __shared__ unsigned wtot[kBoxRowThreads / kWave];
+    const int x0 = blockIdx.x * kBoxSeg, y = blockIdx.y, b = blockIdx.z;
+    const size_t plane = static_cast<size_t>(a.H) * a.W;
+    const int s0 = max(x0 - a.h1, 0), s1 = min(x0 + kBoxSeg + a.h1, a.W);
+    const int n = s1 - s0;
+    const int E = (n + kBoxRowThreads - 1) / kBoxRowThreads;
+    const unsigned* row = a.q + b * plane + static_cast<size_t>(y) * a.W + s0;
+    unsigned v[kBoxRowChunk], tot = 0;
+#pragma unroll
+    for (int e = 0; e < kBoxRowChunk; ++e) {
+        const int j = threadIdx.x * E + e;
+        v[e] = (e < E && j < n && j > 0) ? min(row[j], a.cap) : 0u;
+        tot += v[e];
+    }
+    unsigned run = block_exclusive_scan(tot, wtot);
+#pragma unroll
+    for (int e = 0; e < kBoxRowChunk; ++e) {
+        const int j = threadIdx.x * E + e;
+        run += v[e];
+        if (e < E && j < n) Q[j] = run;
+    }
+    __syncthreads();
+    auto get = [&](int m) { return Q[m]; };
+    // each thread takes consecutive pixels: a binary search places the first box, and the
+    // ends of the following boxes only move forward
+    constexpr int kPer = kBoxSeg / kBoxRowThreads;
+    int plo[kBoxMaxIters], phi[kBoxMaxIters];
+#pragma unroll
+    for (int it = 0; it < kBoxMaxIters; ++it) plo[it] = phi[it] = 0;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int x = x0 + threadIdx.x * kPer + j;
+        if (x < a.W) {
+            const int li = x - s0;
+            const unsigned qi = Q[li];
+#pragma unroll
+            for (int it = 0; it < kBoxMaxIters; ++it) {
+                if (it < a.iters) {
+                    const unsigned R = a.R[it];
+                    const int h = static_cast<int>(R >> 8);
+                    int lo, hi;
+                    if (j == 0) {
+                        const unsigned bd = box_offsets(get, li, 0, n - 1, R, h);
+                        lo = li - static_cast<int>(bd & 255u);
+                        hi = li + static_cast<int>(bd >> 8);
+                    } else {
+                        const int top = min(li + h, n - 1);
+                        lo = max(plo[it], li - h);
+                        hi = max(phi[it], li);
+                        while (qi - Q[lo] > R) ++lo;
+                        while (hi < top && Q[hi + 1] - qi <= R) ++hi;
+                    }
+                    plo[it] = lo;
+                    phi[it] = hi;
+                    a.bounds[(static_cast<size_t>(it) * gridDim.z + b) * plane + static_cast<size_t>(y) * a.W + x] =
+                        static_cast<unsigned short>(static_cast<unsigned>(li - lo) | (static_cast<unsigned>(hi - li) << 8));
+                }
+            }
+        }
+    }
+}
+
+// One wave per workgroup: lane = column, rows [y0, y0 + seg) of the strip.  The ring
+// holds the running coordinate of the last `ring` rows; each lane reads only its own
+// column, so the ring needs no barrier.
+__global__ void __launch_bounds__(kWave) box_bounds_col_kernel(BoxBoundsArgs a) {
+    extern __shared__ unsigned ring_q[];  // [ring][64]
+    const int lane = threadIdx.x;
+    const int col = blockIdx.x * kWave + lane;
+    const bool valid = col < a.W;
+    const int y0 = blockIdx.y * a.seg, b = blockIdx.z;
+    const size_t plane = static_cast<size_t>(a.H) * a.W;
+    const int RB = a.ring;
+    const int sIn = max(y0 - a.h1, 0);
+    const int rEnd = min(y0 + a.seg + a.h1, a.H) - 1;
+    const int oEnd = min(y0 + a.seg, a.H) - 1;
+    const unsigned* qc = a.q + b * plane + (valid ? col : 0);
+    unsigned Qrun = 0;
+    int wslot = 0;                       // slot of the next row written
+    int next = y0, oslot = y0 - sIn;     // next output row and its slot (y0 - sIn <= h1 < RB)
+    const int last = rEnd - sIn;
+    int plo[kBoxMaxIters], phi[kBoxMaxIters];  // box of the previous output row, per iteration
+#pragma unroll
+    for (int it = 0; it < kBoxMaxIters; ++it) plo[it] = phi[it] = 0;
+    unsigned qv[kBoxLoad];
+#pragma unroll
+    for (int u = 0; u < kBoxLoad; ++u) {
+        const int r = sIn + u;
+        qv[u] = (valid && r <= rEnd && r > sIn) ? min(qc[static_cast<size_t>(r) * a.W], a.cap) : 0u;
+    }
+    for (int r0 = sIn; r0 <= rEnd; r0 += kBoxLoad) {
+        unsigned qn[kBoxLoad];
+#pragma unroll
+        for (int u = 0; u < kBoxLoad; ++u) {
+            const int r = r0 + kBoxLoad + u;
+            qn[u] = (valid && r <= rEnd) ? min(qc[static_cast<size_t>(r) * a.W], a.cap) : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kBoxLoad; ++u) {
+            if (r0 + u <= rEnd) {
+                Qrun += qv[u];
+                ring_q[wslot * kWave + lane] = Qrun;
+                wslot = (wslot + 1 == RB) ? 0 : wslot + 1;
+            }
+        }
+        const int loaded = min(r0 + kBoxLoad - 1, rEnd);
+        while (next <= oEnd && (next + a.h1 <= loaded || loaded == a.H - 1)) {
+            const int li = next - sIn;
+            const int os = oslot;
+            auto get = [&](int m) { return ring_q[ring_slot(os, m - li, RB) * kWave + lane]; };
+            const unsigned qi = get(li);
+#pragma unroll
+            for (int it = 0; it < kBoxMaxIters; ++it) {
+                if (it < a.iters) {
+                    // the box of row li starts at or after the previous row's and ends at or
+                    // after it: both ends only move forward, by one row on average
+                    const unsigned R = a.R[it];
+                    const int h = static_cast<int>(R >> 8);
+                    const int top = min(li + h, last);
+                    int lo = max(plo[it], li - h), hi = max(phi[it], li);
+                    while (qi - get(lo) > R) ++lo;
+                    while (hi < top && get(hi + 1) - qi <= R) ++hi;
+                    plo[it] = lo;
+                    phi[it] = hi;
+                    if (valid)
+                        a.bounds[(static_cast<size_t>(it) * gridDim.z + b) * plane + static_cast<size_t>(next) * a.W + col] =
+                            static_cast<unsigned short>(static_cast<unsigned>(li - lo) | (static_cast<unsigned>(hi - li) << 8));
+                }
+            }
+            ++next;
+            oslot = (oslot + 1 == RB) ? 0 : oslot + 1;
+        }
+#pragma unroll
+        for (int u = 0; u < kBoxLoad; ++u) qv[u] = qn[u];
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Passes
+// ---------------------------------------------------------------------------------------
+struct BoxPassArgs {
+    const float* src;               // [batch][C][H][W]
+    float* dst;
+    const unsigned short* bounds;   // [batch][H][W] of this pass's iteration
+    int C, H, W, h;
+    int seg, ring, nbase;           // column pass: output rows per workgroup, ring rows, base slots
+    // update epilogue (column pass): dst = z - step (lambda (z - mean) + c (z - t))
+    const float* zk;
+    const float* tgt;
+    const float* conf;
+    int Cc;
+    float lambda, step;
+};
+
+__global__ void __launch_bounds__(kBoxRowThreads) box_row_kernel(BoxPassArgs a) {
+    __shared__ double P[kBoxRowSpan + 1];
+    __shared__ double wtot[kBoxRowThreads / kWave];
+    const int x0 = blockIdx.x * kBoxSeg, y = blockIdx.y, b = blockIdx.z;
+    const size_t plane = static_cast<size_t>(a.H) * a.W;
+    const int s0 = max(x0 - a.h, 0), s1 = min(x0 + kBoxSeg + a.h, a.W);
+    const int n = s1 - s0;
+    const int E = (n + kBoxRowThreads - 1) / kBoxRowThreads;
+    constexpr int kOut = kBoxSeg / kBoxRowThreads;
+    unsigned bd[kOut];
+#pragma unroll
+    for (int o = 0; o < kOut; ++o) {
+        const int x = x0 + threadIdx.x + o * kBoxRowThreads;
+        bd[o] = (x < a.W) ? a.bounds[b * plane + static_cast<size_t>(y) * a.W + x] : 0u;
+    }
+    for (int c = 0; c < a.C; ++c) {
+        const size_t roff = (static_cast<size_t>(b) * a.C + c) * plane + static_cast<size_t>(y) * a.W;
+        const float* row = a.src + roff + s0;
+        float v[kBoxRowChunk];
+        double tot = 0.0;
+#pragma unroll
+        for (int e = 0; e < kBoxRowChunk; ++e) {
+            const int j = threadIdx.x * E + e;
+            v[e] = (e < E && j < n) ? row[j] : 0.0f;
+            tot += static_cast<double>(v[e]);
+        }
+        double run = block_exclusive_scan(tot, wtot);
+        if (threadIdx.x == 0) P[0] = 0.0;
+#pragma unroll
+        for (int e = 0; e < kBoxRowChunk; ++e) {
+            const int j = threadIdx.x * E + e;
+            run += static_cast<double>(v[e]);
+            if (e < E && j < n) P[j + 1] = run;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int o = 0; o < kOut; ++o) {
+            const int x = x0 + threadIdx.x + o * kBoxRowThreads;
+            if (x < a.W) {
+                const int li = x - s0;
+                const int lo = li - static_cast<int>(bd[o] & 255u), hi = li + static_cast<int>(bd[o] >> 8);
+                a.dst[roff + x] = static_cast<float>(P[hi + 1] - P[lo]) *
+                                  __builtin_amdgcn_rcpf(static_cast<float>(hi - lo + 1));
+            }
+        }
+        __syncthreads();  // P is rebuilt for the next channel
+    }
+}
+
+template <int EPI>
+__global__ void __launch_bounds__(kWave) box_col_kernel(BoxPassArgs a) {
+    extern __shared__ unsigned char box_smem[];
+    const int RB = a.ring;
+    const int bmask = a.nbase - 1;  // base slots: a power of two
+    float* ring = reinterpret_cast<float*>(box_smem);                                      // [RB][64]
+    double* base = reinterpret_cast<double*>(box_smem + static_cast<size_t>(RB) * kWave * 4);  // [nbase][64]
+    const int lane = threadIdx.x;
+    const int col = blockIdx.x * kWave + lane;
+    const bool valid = col < a.W;
+    const int y0 = blockIdx.y * a.seg;
+    const int bc = blockIdx.z;  // image * C + channel
+    const int b = bc / a.C, c = bc - b * a.C;
+    const size_t plane = static_cast<size_t>(a.H) * a.W;
+    const int h = a.h;
+    const int sIn = max(y0 - h, 0);
+    const int rEnd = min(y0 + a.seg + h, a.H) - 1;
+    const int oEnd = min(y0 + a.seg, a.H) - 1;
+    const int cx = valid ? col : 0;
+    const float* sc = a.src + static_cast<size_t>(bc) * plane + cx;
+    float* dc = a.dst + static_cast<size_t>(bc) * plane + cx;
+    const unsigned short* bdc = a.bounds + static_cast<size_t>(b) * plane + cx;
+    [[maybe_unused]] const float* zc = EPI ? a.zk + static_cast<size_t>(bc) * plane + cx : nullptr;
+    [[maybe_unused]] const float* tc = EPI ? a.tgt + static_cast<size_t>(bc) * plane + cx : nullptr;
+    [[maybe_unused]] const float* cc =
+        EPI ? a.conf + (static_cast<size_t>(b) * a.Cc + (a.Cc == 1 ? 0 : c)) * plane + cx : nullptr;
+
+    float run = 0.0f;
+    double bsum = 0.0;
+    int wslot = 0;                        // slot of the next row written
+    int nextb = y0, oslot = y0 - sIn;     // next output block and the slot of its first row
+
+    // mean of the box of output row o (slot so), from the ring
+    auto box_mean = [&](int o, int so, unsigned bd) -> float {
+        const int lo_off = static_cast<int>(bd & 255u), hi_off = static_cast<int>(bd >> 8);
+        const int ol = o - sIn;
+        const int lh = ol + hi_off, ll = ol - lo_off - 1;
+        const double ph = base[((lh >> 5) & bmask) * kWave + lane] +
+                          static_cast<double>(ring[ring_slot(so, hi_off, RB) * kWave + lane]);
+        const double pl = (ll < 0) ? 0.0
+                                   : base[((ll >> 5) & bmask) * kWave + lane] +
+                                         static_cast<double>(ring[ring_slot(so, -lo_off - 1, RB) * kWave + lane]);
+        return static_cast<float>(ph - pl) * __builtin_amdgcn_rcpf(static_cast<float>(lo_off + hi_off + 1));
+    };
+    auto put = [&](int o, float mean, float z, float t, float cf) {
+        const size_t po = static_cast<size_t>(o) * a.W;
+        if constexpr (EPI) {
+            const float upd = fmaf(a.lambda, z - mean, cf * (z - t));
+            dc[po] = fmaf(-a.step, upd, z);
+        } else {
+            dc[po] = mean;
+        }
+    };
+    auto ready = [&](int loaded) {
+        return nextb <= oEnd && (min(nextb + kBoxEmit - 1, oEnd) + h <= loaded || loaded == a.H - 1);
+    };
+
+    float fv[kBoxLoad];
+#pragma unroll
+    for (int u = 0; u < kBoxLoad; ++u) {
+        const int r = sIn + u;
+        fv[u] = (valid && r <= rEnd) ? sc[static_cast<size_t>(r) * a.W] : 0.0f;
+    }
+    for (int r0 = sIn; r0 <= rEnd; r0 += kBoxLoad) {
+        // Operands of the output rows this group can complete, issued before the prefetch
+        // of the next group: loads return in order, so waiting for them does not wait for
+        // the prefetch.
+        unsigned bdp[kBoxLoad];
+        [[maybe_unused]] float zp[kBoxLoad], tp[kBoxLoad], cp[kBoxLoad];
+#pragma unroll
+        for (int k = 0; k < kBoxLoad; ++k) {
+            const int o = nextb + k;
+            const bool in = valid && o <= oEnd;
+            const size_t po = static_cast<size_t>(in ? o : 0) * a.W;
+            bdp[k] = in ? bdc[po] : 0u;
+            if constexpr (EPI) {
+                zp[k] = in ? zc[po] : 0.0f;
+                tp[k] = in ? tc[po] : 0.0f;
+                cp[k] = in ? cc[po] : 0.0f;
+            }
+        }
+        float fn[kBoxLoad];
+#pragma unroll
+        for (int u = 0; u < kBoxLoad; ++u) {
+            const int r = r0 + kBoxLoad + u;
+            fn[u] = (valid && r <= rEnd) ? sc[static_cast<size_t>(r) * a.W] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < kBoxLoad; ++u) {
+            const int l = r0 + u - sIn;
+            if (r0 + u <= rEnd) {
+                if ((l & 31) == 0) {
+                    bsum += static_cast<double>(run);
+                    run = 0.0f;
+                    base[((l >> 5) & bmask) * kWave + lane] = bsum;
+                }
+                run += fv[u];
+                ring[wslot * kWave + lane] = run;
+                wslot = (wslot + 1 == RB) ? 0 : wslot + 1;
+            }
+        }
+        const int loaded = min(r0 + kBoxLoad - 1, rEnd);
+        // blocks are emitted in order once every box of them is loaded; the first
+        // kBoxLoad / kBoxEmit of them use the operands loaded above
+        bool go = true;
+#pragma unroll
+        for (int j = 0; j < kBoxLoad / kBoxEmit; ++j) {
+            go = go && ready(loaded);
+            if (go) {
+#pragma unroll
+                for (int q = 0; q < kBoxEmit; ++q) {
+                    const int o = nextb + q;
+                    if (o <= oEnd) {
+                        const float m = box_mean(o, ring_slot(oslot, q, RB), bdp[j * kBoxEmit + q]);
+                        if (valid) {
+                            if constexpr (EPI) put(o, m, zp[j * kBoxEmit + q], tp[j * kBoxEmit + q], cp[j * kBoxEmit + q]);
+                            else put(o, m, 0.f, 0.f, 0.f);
+                        }
+                    }
+                }
+                nextb += kBoxEmit;
+                oslot = ring_slot(oslot, kBoxEmit, RB);
+            }
+        }
+        // at the bottom of the image the last group completes every remaining block
+        while (ready(loaded)) {
+#pragma unroll
+            for (int q = 0; q < kBoxEmit; ++q) {
+                const int o = nextb + q;
+                if (o <= oEnd) {
+                    const size_t po = static_cast<size_t>(o) * a.W;
+                    const unsigned bd = valid ? bdc[po] : 0u;
+                    const float m = box_mean(o, ring_slot(oslot, q, RB), bd);
+                    if (valid) {
+                        if constexpr (EPI) put(o, m, zc[po], tc[po], cc[po]);
+                        else put(o, m, 0.f, 0.f, 0.f);
+                    }
+                }
+            }
+            nextb += kBoxEmit;
+            oslot = ring_slot(oslot, kBoxEmit, RB);
+        }
+#pragma unroll
+        for (int u = 0; u < kBoxLoad; ++u) fv[u] = fn[u];
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------------------
+static int max_lds_per_block() {
+    static int cached = -1;
+    if (cached < 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            return 65536;
+        cached = v;
+    }
+    return cached;
+}
+
+// Ring rows of a column kernel with half-width h: the rows a box can reach on both sides
+// of the oldest output still pending, the pending block and one loaded group.
+static int box_ring_rows(int h) { return (2 * h + kBoxLoad + kBoxEmit + 1 + 7) / 8 * 8; }
+// Slots of 32-row block bases: a power of two covering every block the ring spans.
+static int box_base_slots(int h) {
+    int n = 1;
+    while (n < box_ring_rows(h) / 32 + 2) n <<= 1;
+    return n;
+}
+static size_t box_col_lds(int h) {
+    return static_cast<size_t>(box_ring_rows(h)) * kWave * 4 + static_cast<size_t>(box_base_slots(h)) * kWave * 8;
+}
+
+// Output rows per column workgroup: enough workgroups to fill the chip, whole groups.
+static int box_col_seg(int batch_planes, int H, int W) {
+    const long strips = static_cast<long>((W + kWave - 1) / kWave) * batch_planes;
+    int seg = 1024;
+    while (seg > 32 && strips * ((H + seg - 1) / seg) < 2048) seg >>= 1;
+    return seg;
+}
+
+int box_check_radius(int h1) {
+    if (h1 > 255) return DTS_ENOTSUP;  // offsets are stored in one byte
+    if (box_col_lds(h1) > static_cast<size_t>(max_lds_per_block())) return DTS_ENOTSUP;
+    return DTS_OK;
+}
+
+int launch_box_codes(const float* guide, int Cg, int batch, int H, int W, float s2, unsigned* qx, unsigned* qy,
+                     hipStream_t s) {
+    const double total = static_cast<double>(batch) * H * W;
+    ProfScope prof("box_codes", total * 4.0 * (Cg + 2), s);
+    hipLaunchKernelGGL(box_codes_kernel, dim3((W + 255) / 256, H, batch), dim3(256), 0, s, guide, Cg, H, W, s2,
+                       qx, qy);
+    return hip_fail(hipGetLastError());
+}
+
+int launch_box_bounds(const unsigned* qx, const unsigned* qy, unsigned short* bx, unsigned short* by, int batch,
+                      int H, int W, const unsigned* R, int iters, hipStream_t s) {
+    BoxBoundsArgs a{};
+    a.H = H;
+    a.W = W;
+    a.iters = iters;
+    a.cap = R[0] + 1;
+    a.h1 = static_cast<int>(R[0] >> 8);
+    for (int i = 0; i < iters; ++i) a.R[i] = R[i];
+    if (int rc = box_check_radius(a.h1)) return rc;
+    const double px = static_cast<double>(batch) * H * W;
+    {
+        a.q = qx;
+        a.bounds = bx;
+        ProfScope prof("box_bounds_row", px * (4.0 + 2.0 * iters), s);
+        hipLaunchKernelGGL(box_bounds_row_kernel, dim3((W + kBoxSeg - 1) / kBoxSeg, H, batch), dim3(kBoxRowThreads),
+                           0, s, a);
+        if (int rc = hip_fail(hipGetLastError())) return rc;
+    }
+    a.q = qy;
+    a.bounds = by;
+    a.seg = box_col_seg(batch, H, W);
+    a.ring = box_ring_rows(a.h1);
+    const size_t lds = static_cast<size_t>(a.ring) * kWave * 4;
+    ProfScope prof("box_bounds_col", px * (4.0 + 2.0 * iters), s);
+    hipLaunchKernelGGL(box_bounds_col_kernel, dim3((W + kWave - 1) / kWave, (H + a.seg - 1) / a.seg, batch),
+                       dim3(kWave), lds, s, a);
+    return hip_fail(hipGetLastError());
+}
+
+int launch_box_row(const float* src, float* dst, const unsigned short* bounds, int C, int batch, int H, int W, int h,
+                   hipStream_t s) {
+    BoxPassArgs a{};
+    a.src = src;
+    a.dst = dst;
+    a.bounds = bounds;
+    a.C = C;
+    a.H = H;
+    a.W = W;
+    a.h = h;
+    const double px = static_cast<double>(batch) * H * W;
+    ProfScope prof("box_row", px * (8.0 * C + 2.0), s);
+    hipLaunchKernelGGL(box_row_kernel, dim3((W + kBoxSeg - 1) / kBoxSeg, H, batch), dim3(kBoxRowThreads), 0, s, a);
+    return hip_fail(hipGetLastError());
+}
+
+int launch_box_col(const float* src, float* dst, const unsigned short* bounds, int C, int batch, int H, int W, int h,
+                   const float* zk, const float* tgt, const float* conf, int Cc, float lambda, float step,
+                   hipStream_t s) {
+    if (int rc = box_check_radius(h)) return rc;
+    BoxPassArgs a{};
+    a.src = src;
+    a.dst = dst;
+    a.bounds = bounds;
+    a.C = C;
+    a.H = H;
+    a.W = W;
+    a.h = h;
+    a.seg = box_col_seg(batch * C, H, W);
+    a.ring = box_ring_rows(h);
+    a.nbase = box_base_slots(h);
+    a.zk = zk;
+    a.tgt = tgt;
+    a.conf = conf;
+    a.Cc = Cc;
+    a.lambda = lambda;
+    a.step = step;
+    const size_t lds = box_col_lds(h);
+    const dim3 grid((W + kWave - 1) / kWave, (H + a.seg - 1) / a.seg, batch * C);
+    const double px = static_cast<double>(batch) * H * W;
+    if (zk) {
+        // per channel: signal, bounds, z^k and t in, z^{k+1} out; the confidence planes in
+        ProfScope prof("box_col_update", px * (18.0 * C + 4.0 * Cc), s);
+        hipLaunchKernelGGL(box_col_kernel<1>, grid, dim3(kWave), lds, s, a);
+    } else {
+        ProfScope prof("box_col", px * 10.0 * C, s);
+        hipLaunchKernelGGL(box_col_kernel<0>, grid, dim3(kWave), lds, s, a);
+    }
+    return hip_fail(hipGetLastError());
+}
+
+}  // namespace dts

@@ -122,6 +122,17 @@ int launch_stereo_data_grad(const float* z, const float* t, const float* c, cons
 int launch_variance_confidence(const float* moments, float* conf, int C, int batch, size_t plane,
                                float sigma_c, hipStream_t s);
 int launch_copy(float* dst, const float* src, size_t n, hipStream_t s);
+constexpr int kBoxMaxIters = 8;
+int box_check_radius(int h1);
+int launch_box_codes(const float* guide, int Cg, int batch, int H, int W, float s2, unsigned* qx, unsigned* qy,
+                     hipStream_t s);
+int launch_box_bounds(const unsigned* qx, const unsigned* qy, unsigned short* bx, unsigned short* by, int batch,
+                      int H, int W, const unsigned* R, int iters, hipStream_t s);
+int launch_box_row(const float* src, float* dst, const unsigned short* bounds, int C, int batch, int H, int W, int h,
+                   hipStream_t s);
+int launch_box_col(const float* src, float* dst, const unsigned short* bounds, int C, int batch, int H, int W, int h,
+                   const float* zk, const float* tgt, const float* conf, int Cc, float lambda, float step,
+                   hipStream_t s);
 size_t support_chunks(int H);
 int launch_support_row(const float* src, const float* dx, float* dst, int batch, int H, int W, float log2a,
                        float m, hipStream_t s);

@@ -194,3 +194,23 @@ def test_support_rejects_bad_arguments_without_launching(lib):
     assert lib.dts_support(fake, 3, 1, 8, 8, 8.0, 0.2, 3, fake, other, 1, fake, fake, ok, None) == dts.DTS_EINVAL
     assert lib.dts_support(fake, 3, 1, 8, 8, 8.0, 0.2, 3, fake, None, 0, None, fake, ok - 256, None) == dts.DTS_EWORKSPACE
     assert lib.dts_support(fake, 3, 1, 0, 8, 8.0, 0.2, 3, fake, None, 0, None, fake, ok, None) == dts.DTS_EINVAL
+
+
+def test_box_rejects_bad_arguments_without_launching(lib):
+    ok = lib.dts_box_workspace_bytes(1, 8, 8, 1, 3)
+    assert ok > 0
+    assert lib.dts_box_workspace_bytes(1, 8, 8, 1, 9) == 0      # at most 8 iterations
+    assert lib.dts_box_workspace_bytes(1, 8, 8, 17, 3) == 0
+    fake = ctypes.c_void_p(0x10000)
+    other = ctypes.c_void_p(0x20000)
+    # null pointers, aliasing, 9 iterations, a box wider than 255 pixels, too-small workspace
+    assert lib.dts_filter_box(None, 3, fake, other, 1, 1, 8, 8, 8.0, 0.2, 3, fake, ok, None) == dts.DTS_EINVAL
+    assert lib.dts_filter_box(fake, 3, other, other, 1, 1, 8, 8, 8.0, 0.2, 3, fake, ok, None) == dts.DTS_EINVAL
+    assert lib.dts_filter_box(fake, 3, fake, other, 1, 1, 8, 8, 8.0, 0.2, 9, fake, ok, None) == dts.DTS_EINVAL
+    big = lib.dts_box_workspace_bytes(1, 8, 8, 1, 1)
+    assert lib.dts_filter_box(fake, 3, fake, other, 1, 1, 8, 8, 500.0, 0.2, 1, fake, big, None) == dts.DTS_ENOTSUP
+    assert lib.dts_filter_box(fake, 3, fake, other, 1, 1, 8, 8, 8.0, 0.2, 3, fake, ok - 256, None) == dts.DTS_EWORKSPACE
+    p = dts.Params(8.0, 0.2, 3, 5).c()
+    assert lib.dts_solve_box(fake, 3, fake, fake, 1, 1, 1, 8, 8, ctypes.byref(p), fake, fake, ok, None) == dts.DTS_EINVAL
+    assert lib.dts_solve_box(fake, 3, fake, other, 2, 1, 1, 8, 8, ctypes.byref(p), other, fake, ok, None) == dts.DTS_EINVAL
+    assert lib.dts_box_codes(fake, 3, 1, 8, 8, 8.0, 0.0, fake, other, None) == dts.DTS_EINVAL
