@@ -5,8 +5,9 @@
 // distances from the guide's channel differences (Eq. (8)-(9)), weights a^d, and
 // alternating causal+anticausal first-order recursive passes along rows and columns.
 //
-// Row pass: one workgroup per row.  Lane l of wave v owns S consecutive pixels (float4
-// accesses).  Each direction of the recurrence is a chain of affine maps: a serial
+// Row pass: one workgroup per row (one-channel signals: a persistent grid walking the
+// rows, each workgroup loading its next row while it scans the current one).  Lane l of
+// wave v owns S consecutive pixels (float4 accesses).  Each direction of the recurrence is a chain of affine maps: a serial
 // composition over the lane's S pixels, one 64-lane scan (DPP inside rows of 16 lanes,
 // scalar reads across rows), one exchange of wave totals through LDS, then a serial sweep
 // from the lane's exact carry-in.
@@ -41,6 +42,115 @@ __global__ void __launch_bounds__(1024) row_pass_kernel(RowArgs a) {
     row_tile<S, DIST, SQ>(a, y, blockIdx.y);
 }
 
+
+// Persistent row pass for one-channel signals: each workgroup walks rows r, r + grid, ...
+// of the batch and issues the loads of its next row before it scans the current one, so
+// the next row's loads are in flight during the current row's scans, barriers and
+// stores.  Every LDS slot is rewritten only after a barrier that follows all reads of its
+// previous contents, so consecutive rows need no extra barrier.
+template <int S>
+__global__ void __launch_bounds__(1024) row_pass_stream_kernel(RowArgs a, int rows) {
+    __shared__ float2 fagg[kMaxRowWaves];
+    __shared__ float2 bagg[kMaxRowWaves];
+    __shared__ float wfirst[kMaxRowWaves + 1];
+    const int lane = lane_id();
+    const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int W = a.W;
+    const int n0 = (wave * kWave + lane) * S;
+    const bool vec = (W & 3) == 0;
+    float fN[S], dN[S];
+    int r = blockIdx.x;
+    if (r < rows) {
+        load_seg<S>(a.src + static_cast<size_t>(r) * W, n0, W, vec, 0.f, fN);
+        load_seg<S>(a.d + static_cast<size_t>(r) * W, n0, W, vec, 1.f, dN);
+    }
+    for (; r < rows; r += gridDim.x) {
+        float f[S], w[S];
+#pragma unroll
+        for (int e = 0; e < S; ++e) {
+            f[e] = fN[e];
+            const int n = n0 + e;
+            w[e] = (n > 0 && n < W) ? weight(dN[e], a.log2a) : 0.f;
+        }
+        const int rn = r + gridDim.x;
+        if (rn < rows) {
+            load_seg<S>(a.src + static_cast<size_t>(rn) * W, n0, W, vec, 0.f, fN);
+            load_seg<S>(a.d + static_cast<size_t>(rn) * W, n0, W, vec, 1.f, dN);
+        }
+        float wlast = __shfl_down(w[0], 1);
+        if (lane == 0) wfirst[wave] = w[0];
+        if (wave == 0 && lane == 0) wfirst[nw] = 0.f;
+        __syncthreads();
+        if (lane == kWave - 1) wlast = wfirst[wave + 1];
+        float la = 1.f, lb = 0.f;
+#pragma unroll
+        for (int e = 0; e < S; ++e) {
+            lb = fmaf(w[e], lb - f[e], f[e]);
+            la *= w[e];
+        }
+        scan_up_dpp(la, lb, lane);
+        float xa = __shfl_up(la, 1), xb = __shfl_up(lb, 1);
+        if (lane == kWave - 1) fagg[wave] = make_float2(la, lb);
+        __syncthreads();
+        float jin = 0.f;
+        for (int u = 0; u < wave; ++u) {
+            const float2 g = fagg[u];
+            jin = fmaf(g.x, jin, g.y);
+        }
+        float j = (lane == 0) ? jin : fmaf(xa, jin, xb);
+#pragma unroll
+        for (int e = 0; e < S; ++e) {
+            j = fmaf(w[e], j - f[e], f[e]);
+            f[e] = j;
+        }
+        la = 1.f;
+        lb = 0.f;
+#pragma unroll
+        for (int e = S - 1; e >= 0; --e) {
+            const float wn = (e == S - 1) ? wlast : w[e < S - 1 ? e + 1 : e];
+            lb = fmaf(wn, lb - f[e], f[e]);
+            la *= wn;
+        }
+        scan_down_dpp(la, lb, lane);
+        xa = __shfl_down(la, 1);
+        xb = __shfl_down(lb, 1);
+        if (lane == 0) bagg[wave] = make_float2(la, lb);
+        __syncthreads();
+        float kin = 0.f;
+        for (int u = nw - 1; u > wave; --u) {
+            const float2 g = bagg[u];
+            kin = fmaf(g.x, kin, g.y);
+        }
+        float k = (lane == kWave - 1) ? kin : fmaf(xa, kin, xb);
+#pragma unroll
+        for (int e = S - 1; e >= 0; --e) {
+            const float wn = (e == S - 1) ? wlast : w[e < S - 1 ? e + 1 : e];
+            k = fmaf(wn, k - f[e], f[e]);
+            f[e] = k;
+        }
+        store_seg<S>(a.dst + static_cast<size_t>(r) * W, n0, W, vec, f);
+    }
+}
+
+// Resident workgroups of the streaming row pass on the current device (its grid).
+template <int S>
+static int row_stream_grid(int threads) {
+    static int cached[64][kMaxRowWaves + 1] = {};
+    static std::mutex mu;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    const int nw = threads / kWave;
+    std::lock_guard<std::mutex> lock(mu);
+    if (cached[dev][nw] == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, row_pass_stream_kernel<S>, threads, 0) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return 0;
+        cached[dev][nw] = std::max(1, per_cu * cus);
+    }
+    return cached[dev][nw];
+}
+
 template <int S, bool DIST, bool SQ = false>
 static void launch_row_t(const RowArgs& a, int nw, int batch, int H, hipStream_t s) {
     // algorithmic bytes: signal in and out (C planes), distances in -- or, on the fused
@@ -49,6 +159,17 @@ static void launch_row_t(const RowArgs& a, int nw, int batch, int H, hipStream_t
     const double cin = SQ ? 0.5 * a.C : a.C;  // planes read for a.C planes written
     const double bytes = DIST ? px * 4.0 * (cin + a.C + a.Cg + 2.0) : px * 4.0 * (cin + a.C + 1.0);
     ProfScope prof(SQ ? "row_pass_dist_square" : DIST ? "row_pass_dist" : "row_pass", bytes, s);
+    if constexpr (!DIST && !SQ) {
+        // one channel: the streaming kernel; several channels share each row's distances
+        // in the per-row kernel instead
+        const int grid = (a.C == 1) ? row_stream_grid<S>(nw * kWave) : 0;
+        if (grid > 0) {
+            const int rows = batch * H;
+            hipLaunchKernelGGL((row_pass_stream_kernel<S>), dim3(std::min(rows, grid)), dim3(nw * kWave), 0, s, a,
+                               rows);
+            return;
+        }
+    }
     hipLaunchKernelGGL((row_pass_kernel<S, DIST, SQ>), dim3(H, batch), dim3(nw * kWave), 0, s, a);
 }
 
