@@ -1,0 +1,91 @@
+"""The full-size workloads on the GPU, in the launch configurations bench.py times.
+
+The multispectral 10240 x 10240 solve (16-band guide, T = 10) is too large for the FP64
+oracle to run whole within a test, so it is checked two ways:
+- against the oracle on a two-iteration, one-step solve of the same full-size inputs.
+  This covers every kernel of the full solve at its full launch shape: the fused distance
+  pass over 16 bands, the 40-chunk column pass, the streaming row pass and the update
+  epilogue;
+- by a property at the full T = 10 configuration: a constant target with uniform
+  confidence is a fixed point, held exactly.
+The 8 x 1024^2 forward + backward (T = 15) is checked by directional derivatives of its
+loss sum((z - r)^2).  The solve is linear in the target, so along a target direction the
+loss is quadratic and a central difference is exact up to rounding; along a confidence
+direction a small step bounds the truncation error.
+"""
+import numpy as np
+import pytest
+import torch
+
+import dts_inputs
+import oracle
+import paper_1805_04590_amd as dts
+
+pytestmark = pytest.mark.gpu
+
+
+def note(*what):
+    print("STEP", *what, flush=True)
+
+
+@pytest.fixture(scope="module")
+def config3():
+    note("generating the 10240 x 10240 x 16 workload")
+    return dts_inputs.config3()
+
+
+def test_config3_two_passes_match_oracle(config3):
+    c = config3
+    N, T = 2, 1
+    note("GPU solve N=2 T=1")
+    g, t, cf = (torch.from_numpy(c[k]).cuda() for k in ("guide", "target", "conf"))
+    got = dts.solve(g, t, cf, c["sigma_s"], c["sigma_r"], N, T).cpu().numpy()
+    del g, t, cf
+    torch.cuda.empty_cache()
+    note("oracle solve N=2 T=1")
+    ref = oracle.solve(c["guide"], c["target"], c["conf"], c["sigma_s"], c["sigma_r"], N, T)
+    err = float(np.abs(got - ref).max())
+    note("max abs err", err)
+    assert err <= 1e-4
+
+
+def test_config3_constant_target_is_a_fixed_point(config3):
+    c = config3
+    note("GPU solve N=3 T=10, constant target")
+    g = torch.from_numpy(c["guide"]).cuda()
+    t = torch.full((1,) + c["guide"].shape[1:], 0.37, dtype=torch.float32, device="cuda")
+    cf = torch.from_numpy(c["conf"]).cuda()
+    z = dts.solve(g, t, cf, c["sigma_s"], c["sigma_r"], c["filter_iters"], c["solver_iters"])
+    dev = float((z - 0.37).abs().max())
+    note("max deviation", dev)
+    assert dev <= 1e-6
+
+
+def _loss(z, r):
+    return float(((z.double() - r.double()) ** 2).sum())
+
+
+def test_config5_gradients_match_directional_derivatives():
+    c = dts_inputs.config5()
+    note("8 x 1024^2 forward + backward")
+    g, t, cf, r = (torch.from_numpy(c[k]).cuda() for k in ("guide", "target", "conf", "ref"))
+    ss, sr, N, T = c["sigma_s"], c["sigma_r"], c["filter_iters"], c["solver_iters"]
+    z, ck = dts.solve(g, t, cf, ss, sr, N, T, checkpoints=True)
+    gt, gc, _ = dts.solve_backward(g, t, cf, ck, (2.0 * (z - r)).contiguous(), ss, sr, N, T)
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    # target: exact central difference (the loss is quadratic in t)
+    v = torch.randn(t.shape, generator=gen, device="cuda")
+    eps = 1e-2
+    fd = (_loss(dts.solve(g, t + eps * v, cf, ss, sr, N, T), r)
+          - _loss(dts.solve(g, t - eps * v, cf, ss, sr, N, T), r)) / (2 * eps)
+    an = float((gt.double() * v.double()).sum())
+    note("target: adjoint", an, "central difference", fd)
+    assert abs(an - fd) <= 1e-3 * abs(fd)
+    # confidence: a small step keeps c inside [0.1, 1] and the truncation error small
+    v = torch.rand(cf.shape, generator=gen, device="cuda") - 0.5
+    eps = 1e-3
+    fd = (_loss(dts.solve(g, t, cf + eps * v, ss, sr, N, T), r)
+          - _loss(dts.solve(g, t, cf - eps * v, ss, sr, N, T), r)) / (2 * eps)
+    an = float((gc.double() * v.double()).sum())
+    note("confidence: adjoint", an, "central difference", fd)
+    assert abs(an - fd) <= 1e-2 * abs(fd)
