@@ -149,10 +149,10 @@ static SupportLayout make_support_layout(int batch, int H, int W) {
     return L;
 }
 
-// Box workspace: [header | qx | qy (u32 codes) | bx | by (u16 bounds, one plane per
-// iteration) | t1 | t2 (C planes each)]
+// Box workspace: [header | qx | qy (u32 codes) | bx | by | bt (u16 bounds, one plane per
+// iteration; bt holds the transposed column bounds) | t1 | t2 (C planes each)]
 struct BoxLayout {
-    size_t qx, qy, bx, by, t1, t2, total;
+    size_t qx, qy, bx, by, bt, t1, t2, total;
 };
 
 static BoxLayout make_box_layout(int batch, int H, int W, int C, int N) {
@@ -166,6 +166,8 @@ static BoxLayout make_box_layout(int batch, int H, int W, int C, int N) {
     L.bx = off;
     off = align_up(off + px * 2 * N);
     L.by = off;
+    off = align_up(off + px * 2 * N);
+    L.bt = off;
     off = align_up(off + px * 2 * N);
     L.t1 = off;
     off = align_up(off + px * 4 * C);
@@ -200,6 +202,7 @@ struct BoxCall {
     unsigned* qy;
     unsigned short* bx;
     unsigned short* by;
+    unsigned short* bt;
     float* t1;
     float* t2;
 };
@@ -216,10 +219,11 @@ static int box_begin(BoxCall& B, const float* guide, int Cg, int C, int batch, i
     B.qy = reinterpret_cast<unsigned*>(base + L.qy);
     B.bx = reinterpret_cast<unsigned short*>(base + L.bx);
     B.by = reinterpret_cast<unsigned short*>(base + L.by);
+    B.bt = reinterpret_cast<unsigned short*>(base + L.bt);
     B.t1 = reinterpret_cast<float*>(base + L.t1);
     B.t2 = reinterpret_cast<float*>(base + L.t2);
     if ((rc = launch_box_codes(guide, Cg, batch, H, W, box_s2(sigma_s, sigma_r), B.qx, B.qy, st))) return rc;
-    return launch_box_bounds(B.qx, B.qy, B.bx, B.by, batch, H, W, B.R, N, st);
+    return launch_box_bounds(B.qx, B.qy, B.bx, B.by, B.bt, batch, H, W, B.R, N, st);
 }
 
 static int box_mean(const BoxCall& B, const float* src, float* dst, int C, int batch, int H, int W, int N,

@@ -16,8 +16,8 @@
 //   box_codes_kernel        guide -> qx, qy (one pixel per thread)
 //   box_bounds_row_kernel   qx -> per pixel and iteration, the box as two u8 offsets
 //                           (a row segment's prefix of codes in LDS, binary searches)
-//   box_bounds_col_kernel   qy -> the same along columns (one column per lane, a ring
-//                           of the running coordinate in LDS)
+//   box_transpose_kernel    the column bounds are the row bounds of the transposed
+//                           codes, transposed back (64 x 64 LDS tiles)
 //   box_row_kernel          one row pass: FP64 prefix of the segment and its halo in LDS,
 //                           mean = (P[hi + 1] - P[lo]) / (hi - lo + 1)
 //   box_col_kernel<EPI>     one column pass: one column per lane walking down its rows;
@@ -143,8 +143,6 @@ struct BoxBoundsArgs {
     int H, W, iters;
     unsigned cap;             // R_1 + 1
     int h1;                   // R_1 / 256
-    int seg;                  // column kernel: output rows per workgroup
-    int ring;                 // column kernel: ring rows
     unsigned R[kBoxMaxIters];
 };
 
@@ -212,78 +210,26 @@ __global__ void __launch_bounds__(kBoxRowThreads) box_bounds_row_kernel(BoxBound
     }
 }
 
-// One wave per workgroup: lane = column, rows [y0, y0 + seg) of the strip.  The ring
-// holds the running coordinate of the last `ring` rows; each lane reads only its own
-// column, so the ring needs no barrier.
-__global__ void __launch_bounds__(kWave) box_bounds_col_kernel(BoxBoundsArgs a) {
-    extern __shared__ unsigned ring_q[];  // [ring][64]
-    const int lane = threadIdx.x;
-    const int col = blockIdx.x * kWave + lane;
-    const bool valid = col < a.W;
-    const int y0 = blockIdx.y * a.seg, b = blockIdx.z;
-    const size_t plane = static_cast<size_t>(a.H) * a.W;
-    const int RB = a.ring;
-    const int sIn = max(y0 - a.h1, 0);
-    const int rEnd = min(y0 + a.seg + a.h1, a.H) - 1;
-    const int oEnd = min(y0 + a.seg, a.H) - 1;
-    const unsigned* qc = a.q + b * plane + (valid ? col : 0);
-    unsigned Qrun = 0;
-    int wslot = 0;                       // slot of the next row written
-    int next = y0, oslot = y0 - sIn;     // next output row and its slot (y0 - sIn <= h1 < RB)
-    const int last = rEnd - sIn;
-    int plo[kBoxMaxIters], phi[kBoxMaxIters];  // box of the previous output row, per iteration
-#pragma unroll
-    for (int it = 0; it < kBoxMaxIters; ++it) plo[it] = phi[it] = 0;
-    unsigned qv[kBoxLoad];
-#pragma unroll
-    for (int u = 0; u < kBoxLoad; ++u) {
-        const int r = sIn + u;
-        qv[u] = (valid && r <= rEnd && r > sIn) ? min(qc[static_cast<size_t>(r) * a.W], a.cap) : 0u;
+// Tiled transpose of `planes` planes [rows][cols] -> [cols][rows] through LDS (64 x 64
+// tiles, coalesced on both sides): the column bounds are the row bounds of the
+// transposed codes, transposed back.
+template <typename T>
+__global__ void __launch_bounds__(256) box_transpose_kernel(const T* __restrict__ src, T* __restrict__ dst,
+                                                            int rows, int cols) {
+    __shared__ T tile[64][65];
+    const size_t plane = static_cast<size_t>(rows) * cols;
+    const T* sp = src + blockIdx.z * plane;
+    T* dp = dst + blockIdx.z * plane;
+    const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int k = ty; k < 64; k += 4) {
+        const int r = r0 + k, c = c0 + tx;
+        if (r < rows && c < cols) tile[k][tx] = sp[static_cast<size_t>(r) * cols + c];
     }
-    for (int r0 = sIn; r0 <= rEnd; r0 += kBoxLoad) {
-        unsigned qn[kBoxLoad];
-#pragma unroll
-        for (int u = 0; u < kBoxLoad; ++u) {
-            const int r = r0 + kBoxLoad + u;
-            qn[u] = (valid && r <= rEnd) ? min(qc[static_cast<size_t>(r) * a.W], a.cap) : 0u;
-        }
-#pragma unroll
-        for (int u = 0; u < kBoxLoad; ++u) {
-            if (r0 + u <= rEnd) {
-                Qrun += qv[u];
-                ring_q[wslot * kWave + lane] = Qrun;
-                wslot = (wslot + 1 == RB) ? 0 : wslot + 1;
-            }
-        }
-        const int loaded = min(r0 + kBoxLoad - 1, rEnd);
-        while (next <= oEnd && (next + a.h1 <= loaded || loaded == a.H - 1)) {
-            const int li = next - sIn;
-            const int os = oslot;
-            auto get = [&](int m) { return ring_q[ring_slot(os, m - li, RB) * kWave + lane]; };
-            const unsigned qi = get(li);
-#pragma unroll
-            for (int it = 0; it < kBoxMaxIters; ++it) {
-                if (it < a.iters) {
-                    // the box of row li starts at or after the previous row's and ends at or
-                    // after it: both ends only move forward, by one row on average
-                    const unsigned R = a.R[it];
-                    const int h = static_cast<int>(R >> 8);
-                    const int top = min(li + h, last);
-                    int lo = max(plo[it], li - h), hi = max(phi[it], li);
-                    while (qi - get(lo) > R) ++lo;
-                    while (hi < top && get(hi + 1) - qi <= R) ++hi;
-                    plo[it] = lo;
-                    phi[it] = hi;
-                    if (valid)
-                        a.bounds[(static_cast<size_t>(it) * gridDim.z + b) * plane + static_cast<size_t>(next) * a.W + col] =
-                            static_cast<unsigned short>(static_cast<unsigned>(li - lo) | (static_cast<unsigned>(hi - li) << 8));
-                }
-            }
-            ++next;
-            oslot = (oslot + 1 == RB) ? 0 : oslot + 1;
-        }
-#pragma unroll
-        for (int u = 0; u < kBoxLoad; ++u) qv[u] = qn[u];
+    __syncthreads();
+    for (int k = ty; k < 64; k += 4) {
+        const int c = c0 + k, r = r0 + tx;
+        if (c < cols && r < rows) dp[static_cast<size_t>(c) * rows + r] = tile[tx][k];
     }
 }
 
@@ -551,34 +497,42 @@ int launch_box_codes(const float* guide, int Cg, int batch, int H, int W, float 
     return hip_fail(hipGetLastError());
 }
 
-int launch_box_bounds(const unsigned* qx, const unsigned* qy, unsigned short* bx, unsigned short* by, int batch,
-                      int H, int W, const unsigned* R, int iters, hipStream_t s) {
-    BoxBoundsArgs a{};
+template <typename T>
+static int launch_transpose(const T* src, T* dst, int planes, int rows, int cols, const char* name, hipStream_t s) {
+    ProfScope prof(name, 2.0 * sizeof(T) * planes * static_cast<double>(rows) * cols, s);
+    hipLaunchKernelGGL(box_transpose_kernel<T>, dim3((cols + 63) / 64, (rows + 63) / 64, planes), dim3(256), 0, s,
+                       src, dst, rows, cols);
+    return hip_fail(hipGetLastError());
+}
+
+static int launch_bounds_rows(const unsigned* q, unsigned short* bounds, int batch, int H, int W,
+                              const BoxBoundsArgs& base, const char* name, hipStream_t s) {
+    BoxBoundsArgs a = base;
+    a.q = q;
+    a.bounds = bounds;
     a.H = H;
     a.W = W;
+    ProfScope prof(name, static_cast<double>(batch) * H * W * (4.0 + 2.0 * a.iters), s);
+    hipLaunchKernelGGL(box_bounds_row_kernel, dim3((W + kBoxSeg - 1) / kBoxSeg, H, batch), dim3(kBoxRowThreads), 0, s,
+                       a);
+    return hip_fail(hipGetLastError());
+}
+
+// Row bounds from qx; column bounds as the row bounds of the transposed qy (written over
+// qx, no longer needed), transposed back through `bt` (iters planes of the batch).
+int launch_box_bounds(unsigned* qx, const unsigned* qy, unsigned short* bx, unsigned short* by, unsigned short* bt,
+                      int batch, int H, int W, const unsigned* R, int iters, hipStream_t s) {
+    BoxBoundsArgs a{};
     a.iters = iters;
     a.cap = R[0] + 1;
     a.h1 = static_cast<int>(R[0] >> 8);
     for (int i = 0; i < iters; ++i) a.R[i] = R[i];
     if (int rc = box_check_radius(a.h1)) return rc;
-    const double px = static_cast<double>(batch) * H * W;
-    {
-        a.q = qx;
-        a.bounds = bx;
-        ProfScope prof("box_bounds_row", px * (4.0 + 2.0 * iters), s);
-        hipLaunchKernelGGL(box_bounds_row_kernel, dim3((W + kBoxSeg - 1) / kBoxSeg, H, batch), dim3(kBoxRowThreads),
-                           0, s, a);
-        if (int rc = hip_fail(hipGetLastError())) return rc;
-    }
-    a.q = qy;
-    a.bounds = by;
-    a.seg = box_col_seg(batch, H, W);
-    a.ring = box_ring_rows(a.h1);
-    const size_t lds = static_cast<size_t>(a.ring) * kWave * 4;
-    ProfScope prof("box_bounds_col", px * (4.0 + 2.0 * iters), s);
-    hipLaunchKernelGGL(box_bounds_col_kernel, dim3((W + kWave - 1) / kWave, (H + a.seg - 1) / a.seg, batch),
-                       dim3(kWave), lds, s, a);
-    return hip_fail(hipGetLastError());
+    int rc = launch_bounds_rows(qx, bx, batch, H, W, a, "box_bounds_row", s);
+    if (rc) return rc;
+    if ((rc = launch_transpose<unsigned>(qy, qx, batch, H, W, "box_transpose_codes", s))) return rc;
+    if ((rc = launch_bounds_rows(qx, bt, batch, W, H, a, "box_bounds_col", s))) return rc;
+    return launch_transpose<unsigned short>(bt, by, iters * batch, W, H, "box_transpose_bounds", s);
 }
 
 int launch_box_row(const float* src, float* dst, const unsigned short* bounds, int C, int batch, int H, int W, int h,

@@ -126,8 +126,8 @@ constexpr int kBoxMaxIters = 8;
 int box_check_radius(int h1);
 int launch_box_codes(const float* guide, int Cg, int batch, int H, int W, float s2, unsigned* qx, unsigned* qy,
                      hipStream_t s);
-int launch_box_bounds(const unsigned* qx, const unsigned* qy, unsigned short* bx, unsigned short* by, int batch,
-                      int H, int W, const unsigned* R, int iters, hipStream_t s);
+int launch_box_bounds(unsigned* qx, const unsigned* qy, unsigned short* bx, unsigned short* by, unsigned short* bt,
+                      int batch, int H, int W, const unsigned* R, int iters, hipStream_t s);
 int launch_box_row(const float* src, float* dst, const unsigned short* bounds, int C, int batch, int H, int W, int h,
                    hipStream_t s);
 int launch_box_col(const float* src, float* dst, const unsigned short* bounds, int C, int batch, int H, int W, int h,
