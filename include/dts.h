@@ -4,7 +4,9 @@
  * Method: A. Bapat and J.-M. Frahm, "The Domain Transform Solver", ECCV 2018
  * (arXiv:1805.04590).  Equation numbers count the paper's displayed equations in order:
  * Eq. (2) objective without the application term, Eq. (3) its gradient (the descent
- * direction), Eq. (8)-(9) the domain transform, Eq. (10) the edge-aware mean.
+ * direction), Eq. (6) the bilateral solver's per-pixel solution, Eq. (7) the variance
+ * confidence, Eq. (8)-(9) the domain transform, Eq. (10) the edge-aware mean, Eq. (11)
+ * the stereo objective.
  *
  * Conventions shared by every entry point
  *   - Every array pointer is a DEVICE pointer (memory of the current HIP device), fp32,
@@ -17,7 +19,8 @@
  *     same time.
  *   - `stream` is a hipStream_t (NULL = the default stream).  Every call only enqueues
  *     work on it and returns without synchronising, so calls may be captured into a HIP
- *     graph.  Inputs are never written; outputs must not alias inputs.
+ *     graph.  Inputs are never written; outputs must not alias inputs unless the entry
+ *     point says so.
  *   - Return value: DTS_OK (0) or a negative error code; nothing is enqueued when an
  *     argument check fails.  Values are not range-checked: NaN and Inf propagate.
  *   - Device-side failures (a bounded wait inside a kernel that timed out) set a flag in
@@ -40,7 +43,7 @@ extern "C" {
 #define DTS_EDEVICE (-5)    /* a kernel reported a device-side failure (status call)     */
 
 #define DTS_MAX_CHANNELS 16 /* Cg, Ct <= 16: the paper motivates 16-band imagery (Sec. 1) */
-#define DTS_MAX_WIDTH 16384  /* row pass: at most 16 waves x 4 tiles of 256 pixels */
+#define DTS_MAX_WIDTH 16384  /* row pass: at most 16 waves x 64 lanes x 16 pixels per row */
 #define DTS_MAX_HEIGHT 32768
 
 /* Solver parameters (Sec. 3.1 and Sec. 4).  sigma_s is the spatial standard deviation

@@ -215,6 +215,8 @@ static int box_begin(BoxCall& B, const float* guide, int Cg, int C, int batch, i
     int rc = box_radii(sigma_s, N, B.R);
     if (rc) return rc;
     char* base = static_cast<char*>(ws);
+    // no kernel of the box path reports a device-side failure: start from a clean status
+    if ((rc = launch_zero(base, kHeaderBytes, st))) return rc;
     B.qx = reinterpret_cast<unsigned*>(base + L.qx);
     B.qy = reinterpret_cast<unsigned*>(base + L.qy);
     B.bx = reinterpret_cast<unsigned short*>(base + L.bx);
@@ -784,6 +786,8 @@ int dts_support(const float* guide, int Cg, int batch, int H, int W, float sigma
     float* tmp = reinterpret_cast<float*>(base + L.tmp);
     Ctx ctx;
     ctx.stream = static_cast<hipStream_t>(stream);
+    // no kernel of the support path reports a device-side failure: start from a clean status
+    if ((rc = launch_zero(base, kHeaderBytes, ctx.stream))) return rc;
     RowPass rp{};
     rp.guide = guide;
     rp.dx_out = dx;

@@ -118,3 +118,15 @@ def test_solve_box_full_stereo_shape():
     ref = oracle.solve_box(c["guide"], c["target"], c["conf"], c["sigma_s"], c["sigma_r"], c["filter_iters"],
                            c["solver_iters"])
     assert np.abs(got - ref).max() <= SOLVE_TOL * c["value_range"]
+
+
+def test_box_calls_leave_a_clean_status():
+    # a workspace holding garbage reads DTS_OK after a call: every call clears the status
+    c = dts_inputs.random_case(9, 40, 60, 3, 1, T=2)
+    lib = dts.library()
+    ws = torch.full((lib.dts_box_workspace_bytes(1, 40, 60, 1, 3),), 255, dtype=torch.uint8, device="cuda")
+    dts.solve_box(dev(c["guide"]), dev(c["target"]), dev(c["conf"]), 6.0, 0.25, 3, 2, workspace=ws)
+    assert dts.workspace_status(ws) == dts.DTS_OK
+    ws.fill_(255)
+    dts.filter_box(dev(c["guide"]), dev(c["target"]), 6.0, 0.25, 3, workspace=ws)
+    assert dts.workspace_status(ws) == dts.DTS_OK

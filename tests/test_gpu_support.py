@@ -91,3 +91,12 @@ def test_full_size_stereo_shape():
     ref_c, ref_s = oracle.support_confidence(c["guide"], c["conf"], c["sigma_s"], c["sigma_r"])
     assert _rel_err(s.cpu().numpy(), ref_s) <= RTOL
     assert _rel_err(cw.cpu().numpy(), ref_c) <= RTOL
+
+
+def test_support_call_leaves_a_clean_status():
+    # a workspace holding garbage reads DTS_OK after a call: every call clears the status
+    c = dts_inputs.random_case(8, 40, 60, 3, 1)
+    lib = dts.library()
+    ws = torch.full((lib.dts_support_workspace_bytes(1, 40, 60),), 255, dtype=torch.uint8, device="cuda")
+    dts.support(dev(c["guide"]), 6.0, 0.25, workspace=ws)
+    assert dts.workspace_status(ws) == dts.DTS_OK
