@@ -235,13 +235,20 @@ static int box_mean(const BoxCall& B, const float* src, float* dst, int C, int b
     const float* x = src;
     for (int i = 0; i < N; ++i) {
         const int h = static_cast<int>(B.R[i] >> 8);
-        int rc = launch_box_row(x, B.t1, B.bx + px * i, C, batch, H, W, h, st);
+        // the row pass writes y (never the buffer it reads); a plain column pass builds its
+        // block prefix in the other buffer and writes its mean back over y
+        float* y = (x == B.t1) ? B.t2 : B.t1;
+        float* other = (y == B.t1) ? B.t2 : B.t1;
+        int rc = launch_box_row(x, y, B.bx + px * i, C, batch, H, W, h, st);
         if (rc) return rc;
         const bool last = i == N - 1;
-        rc = launch_box_col(B.t1, last ? dst : B.t2, B.by + px * i, C, batch, H, W, h, last ? zk : nullptr, tgt,
-                            conf, Cc, lambda, step, st);
+        if (last && zk) {
+            rc = launch_box_col(y, dst, B.by + px * i, C, batch, H, W, h, zk, tgt, conf, Cc, lambda, step, st);
+        } else {
+            rc = launch_box_col_prefixed(y, other, last ? dst : y, B.by + px * i, C, batch, H, W, st);
+        }
         if (rc) return rc;
-        x = B.t2;
+        x = y;
     }
     return DTS_OK;
 }

@@ -446,6 +446,74 @@ __global__ void __launch_bounds__(kWave) box_col_kernel(BoxPassArgs a) {
     }
 }
 
+// Plain column pass in two streaming kernels.
+//   box_colprefix_kernel: P[y] = sum of f over rows 32 (y / 32) .. y of the column (the
+//     prefix within aligned 32-row blocks, float32), one thread per column and block;
+//   box_colmean_kernel: the box sum of row o is P[hi] - P[lo - 1] plus the totals
+//     P[32 k + 31] of the blocks k from (lo - 1) / 32 to hi / 32 - 1, added in FP64: a sum
+//     carries only the float32 rounding of its own additions, as in box_col_kernel.
+// Both kernels run at full occupancy; the gathers of the second stay within a few rows
+// of the output row and are served by the caches.
+constexpr int kBoxPrefixRows = 32;
+
+__global__ void __launch_bounds__(256) box_colprefix_kernel(const float* __restrict__ src, float* __restrict__ P,
+                                                            int H, int W) {
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    if (x >= W) return;
+    const size_t plane = static_cast<size_t>(H) * W;
+    const int y0 = blockIdx.y * kBoxPrefixRows;
+    const int n = min(kBoxPrefixRows, H - y0);
+    const float* sc = src + blockIdx.z * plane + static_cast<size_t>(y0) * W + x;
+    float* pc = P + blockIdx.z * plane + static_cast<size_t>(y0) * W + x;
+    float v[kBoxPrefixRows];
+#pragma unroll
+    for (int r = 0; r < kBoxPrefixRows; ++r) v[r] = (r < n) ? sc[static_cast<size_t>(r) * W] : 0.0f;
+    float run = 0.0f;
+#pragma unroll
+    for (int r = 0; r < kBoxPrefixRows; ++r) {
+        run += v[r];
+        if (r < n) pc[static_cast<size_t>(r) * W] = run;
+    }
+}
+
+constexpr int kBoxMeanRows = 8;  // output rows per thread
+
+__global__ void __launch_bounds__(256) box_colmean_kernel(const float* __restrict__ P,
+                                                          const unsigned short* __restrict__ bounds,
+                                                          float* __restrict__ dst, int C, int H, int W) {
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    if (x >= W) return;
+    const size_t plane = static_cast<size_t>(H) * W;
+    const int bc = blockIdx.z, b = bc / C;
+    const int o0 = blockIdx.y * kBoxMeanRows;
+    const float* pc = P + static_cast<size_t>(bc) * plane + x;
+    const unsigned short* bdc = bounds + static_cast<size_t>(b) * plane + x;
+    float* dc = dst + static_cast<size_t>(bc) * plane + x;
+    unsigned bd[kBoxMeanRows];
+#pragma unroll
+    for (int q = 0; q < kBoxMeanRows; ++q) {
+        const int o = o0 + q;
+        bd[q] = (o < H) ? bdc[static_cast<size_t>(o) * W] : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < kBoxMeanRows; ++q) {
+        const int o = o0 + q;
+        if (o < H) {
+            const int lo = o - static_cast<int>(bd[q] & 255u), hi = o + static_cast<int>(bd[q] >> 8);
+            double sum = static_cast<double>(pc[static_cast<size_t>(hi) * W]);
+            int k = 0;
+            if (lo > 0) {
+                sum -= static_cast<double>(pc[static_cast<size_t>(lo - 1) * W]);
+                k = (lo - 1) >> 5;
+            }
+            for (; k < (hi >> 5); ++k)
+                sum += static_cast<double>(pc[static_cast<size_t>(32 * k + 31) * W]);
+            dc[static_cast<size_t>(o) * W] =
+                static_cast<float>(sum) * __builtin_amdgcn_rcpf(static_cast<float>(hi - lo + 1));
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------------------
@@ -548,6 +616,23 @@ int launch_box_row(const float* src, float* dst, const unsigned short* bounds, i
     const double px = static_cast<double>(batch) * H * W;
     ProfScope prof("box_row", px * (8.0 * C + 2.0), s);
     hipLaunchKernelGGL(box_row_kernel, dim3((W + kBoxSeg - 1) / kBoxSeg, H, batch), dim3(kBoxRowThreads), 0, s, a);
+    return hip_fail(hipGetLastError());
+}
+
+int launch_box_col_prefixed(const float* src, float* P, float* dst, const unsigned short* bounds, int C, int batch,
+                            int H, int W, hipStream_t s) {
+    const double px = static_cast<double>(batch) * H * W;
+    const unsigned gx = static_cast<unsigned>((W + 255) / 256);
+    {
+        ProfScope prof("box_col_prefix", px * 8.0 * C, s);
+        hipLaunchKernelGGL(box_colprefix_kernel, dim3(gx, (H + kBoxPrefixRows - 1) / kBoxPrefixRows, batch * C),
+                           dim3(256), 0, s, src, P, H, W);
+        if (int rc = hip_fail(hipGetLastError())) return rc;
+    }
+    // prefix in once, bounds in, mean out (the gathers beyond the first read are cache hits)
+    ProfScope prof("box_col_mean", px * 10.0 * C, s);
+    hipLaunchKernelGGL(box_colmean_kernel, dim3(gx, (H + kBoxMeanRows - 1) / kBoxMeanRows, batch * C), dim3(256), 0,
+                       s, P, bounds, dst, C, H, W);
     return hip_fail(hipGetLastError());
 }
 

@@ -130,6 +130,8 @@ int launch_box_bounds(unsigned* qx, const unsigned* qy, unsigned short* bx, unsi
                       int batch, int H, int W, const unsigned* R, int iters, hipStream_t s);
 int launch_box_row(const float* src, float* dst, const unsigned short* bounds, int C, int batch, int H, int W, int h,
                    hipStream_t s);
+int launch_box_col_prefixed(const float* src, float* P, float* dst, const unsigned short* bounds, int C, int batch,
+                            int H, int W, hipStream_t s);
 int launch_box_col(const float* src, float* dst, const unsigned short* bounds, int C, int batch, int H, int W, int h,
                    const float* zk, const float* tgt, const float* conf, int Cc, float lambda, float step,
                    hipStream_t s);
