@@ -52,40 +52,59 @@ __device__ __forceinline__ unsigned box_code(float acc, float s2) {
     return (q < 65536.0f) ? static_cast<unsigned>(q) : kBoxCodeCap;  // NaN takes the cap
 }
 
+// Four consecutive pixels per thread (float4 loads where the row allows them); every
+// pixel's arithmetic is the same sequence of rounded operations as for one pixel alone.
+constexpr int kCodePx = 4;
+
 __global__ void __launch_bounds__(256) box_codes_kernel(const float* __restrict__ guide, int Cg, int H, int W,
                                                         float s2, unsigned* __restrict__ qx,
                                                         unsigned* __restrict__ qy) {
 #pragma clang fp contract(off)
-    const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, b = blockIdx.z;
-    if (x >= W) return;
+    const int x0 = (blockIdx.x * 256 + threadIdx.x) * kCodePx, y = blockIdx.y, b = blockIdx.z;
+    if (x0 >= W) return;
     const size_t plane = static_cast<size_t>(H) * W;
-    const size_t i = static_cast<size_t>(y) * W + x;
-    const float* g = guide + static_cast<size_t>(b) * Cg * plane + i;
-    float ax = 0.0f, ay = 0.0f;
-    // bands four at a time: their loads are issued together, the sums stay in band order
-    for (int k0 = 0; k0 < Cg; k0 += 4) {
-        float v[4], l[4], u[4];
+    const size_t i0 = static_cast<size_t>(y) * W + x0;
+    const float* g = guide + static_cast<size_t>(b) * Cg * plane + i0;
+    const bool vec = (W % kCodePx) == 0;  // then x0 + 3 < W and every row is 16-byte aligned
+    float ax[kCodePx], ay[kCodePx];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const bool in = k0 + q < Cg;
-            const float* gk = g + static_cast<size_t>(in ? k0 + q : 0) * plane;
-            v[q] = in ? gk[0] : 0.0f;
-            l[q] = (in && x > 0) ? gk[-1] : v[q];
-            u[q] = (in && y > 0) ? gk[-static_cast<ptrdiff_t>(W)] : v[q];
+    for (int e = 0; e < kCodePx; ++e) ax[e] = ay[e] = 0.0f;
+    for (int k = 0; k < Cg; ++k) {
+        const float* gk = g + static_cast<size_t>(k) * plane;
+        float v[kCodePx], u[kCodePx];
+        if (vec) {
+            const float4 a = *reinterpret_cast<const float4*>(gk);
+            v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+            if (y > 0) {
+                const float4 c = *reinterpret_cast<const float4*>(gk - W);
+                u[0] = c.x; u[1] = c.y; u[2] = c.z; u[3] = c.w;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < kCodePx; ++e) {
+                v[e] = (x0 + e < W) ? gk[e] : 0.0f;
+                if (y > 0) u[e] = (x0 + e < W) ? gk[static_cast<ptrdiff_t>(e) - W] : 0.0f;
+            }
         }
+        const float left = (x0 > 0) ? gk[-1] : v[0];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if (k0 + q < Cg) {
-                const float ex = v[q] - l[q];
-                const float ey = v[q] - u[q];
-                ax = ax + ex * ex;
-                ay = ay + ey * ey;
+        for (int e = 0; e < kCodePx; ++e) {
+            const float ex = v[e] - (e == 0 ? left : v[e > 0 ? e - 1 : 0]);
+            ax[e] = ax[e] + ex * ex;
+            if (y > 0) {
+                const float ey = v[e] - u[e];
+                ay[e] = ay[e] + ey * ey;
             }
         }
     }
-    const size_t e = static_cast<size_t>(b) * plane + i;
-    qx[e] = (x > 0) ? box_code(ax, s2) : 0u;
-    qy[e] = (y > 0) ? box_code(ay, s2) : 0u;
+    const size_t e0 = static_cast<size_t>(b) * plane + i0;
+#pragma unroll
+    for (int e = 0; e < kCodePx; ++e) {
+        if (x0 + e < W) {
+            qx[e0 + e] = (x0 + e > 0) ? box_code(ax[e], s2) : 0u;
+            qy[e0 + e] = (y > 0) ? box_code(ay[e], s2) : 0u;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -560,8 +579,8 @@ int launch_box_codes(const float* guide, int Cg, int batch, int H, int W, float 
                      hipStream_t s) {
     const double total = static_cast<double>(batch) * H * W;
     ProfScope prof("box_codes", total * 4.0 * (Cg + 2), s);
-    hipLaunchKernelGGL(box_codes_kernel, dim3((W + 255) / 256, H, batch), dim3(256), 0, s, guide, Cg, H, W, s2,
-                       qx, qy);
+    hipLaunchKernelGGL(box_codes_kernel, dim3((W + 256 * kCodePx - 1) / (256 * kCodePx), H, batch), dim3(256), 0, s,
+                       guide, Cg, H, W, s2, qx, qy);
     return hip_fail(hipGetLastError());
 }
 
