@@ -60,7 +60,12 @@ __global__ void __launch_bounds__(256) box_codes_kernel(const float* __restrict_
                                                         float s2, unsigned* __restrict__ qx,
                                                         unsigned* __restrict__ qy) {
 #pragma clang fp contract(off)
-    const int x0 = (blockIdx.x * 256 + threadIdx.x) * kCodePx, y = blockIdx.y, b = blockIdx.z;
+    // Workgroups take (row, segment) units in XCD-contiguous bands: workgroup i runs on
+    // XCD i mod 8, and a row's read of the row above then usually hits that XCD's L2.
+    const int segs = (W + 256 * kCodePx - 1) / (256 * kCodePx);
+    const int unit = xcd_band_index(static_cast<int>(blockIdx.x), segs * H);
+    const int y = unit / segs, b = blockIdx.z;
+    const int x0 = ((unit - y * segs) * 256 + threadIdx.x) * kCodePx;
     if (x0 >= W) return;
     const size_t plane = static_cast<size_t>(H) * W;
     const size_t i0 = static_cast<size_t>(y) * W + x0;
@@ -579,8 +584,8 @@ int launch_box_codes(const float* guide, int Cg, int batch, int H, int W, float 
                      hipStream_t s) {
     const double total = static_cast<double>(batch) * H * W;
     ProfScope prof("box_codes", total * 4.0 * (Cg + 2), s);
-    hipLaunchKernelGGL(box_codes_kernel, dim3((W + 256 * kCodePx - 1) / (256 * kCodePx), H, batch), dim3(256), 0, s,
-                       guide, Cg, H, W, s2, qx, qy);
+    const unsigned units = static_cast<unsigned>((W + 256 * kCodePx - 1) / (256 * kCodePx)) * static_cast<unsigned>(H);
+    hipLaunchKernelGGL(box_codes_kernel, dim3(units, 1, batch), dim3(256), 0, s, guide, Cg, H, W, s2, qx, qy);
     return hip_fail(hipGetLastError());
 }
 
