@@ -421,8 +421,8 @@ def stereo_leg(steps, warmup):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the solve is not "
-              "sharded across GPUs in this build.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): libdts runs each "
+              "solve on a single GPU and has no multi-GPU sharding.", file=sys.stderr)
         sys.exit(2)
 
     import torch
