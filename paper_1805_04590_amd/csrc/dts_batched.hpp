@@ -32,7 +32,7 @@ struct BatchArgs {
     const BInst* inst;
     const int* phase_prefix;  // [n_phases][n + 1] first tile of each instance in a phase
     unsigned* tickets;        // [n_phases] tile counters, zeroed by the reset kernel
-    unsigned* barrier;        // workgroups that finished a phase (cumulative)
+    unsigned* barrier;        // barrier counters: groups, then workgroups per group (cumulative)
     const unsigned* launch;   // launch counter (epoch base of the carry words)
     int* status;
     int n, n_phases;
