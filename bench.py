@@ -91,9 +91,23 @@ def cpu_baseline(rows):
     case = dts_inputs.config3(rows=(0, rows))
     px = case["target"].shape[1] * case["target"].shape[2]
     t0 = time.perf_counter()
-    oracle.solve(case["guide"], case["target"], case["conf"], case["sigma_s"], case["sigma_r"],
-                 case["filter_iters"], case["solver_iters"], case["lam"], case["step"])
+    ref = oracle.solve(case["guide"], case["target"], case["conf"], case["sigma_s"], case["sigma_r"],
+                       case["filter_iters"], case["solver_iters"], case["lam"], case["step"])
     dt = time.perf_counter() - t0
+    err = None
+    try:
+        import torch
+
+        import paper_1805_04590_amd as dts
+
+        if torch.cuda.is_available():
+            g, t, c = (torch.from_numpy(case[k]).cuda() for k in ("guide", "target", "conf"))
+            z = dts.solve(g, t, c, case["sigma_s"], case["sigma_r"], case["filter_iters"], case["solver_iters"],
+                          case["lam"], case["step"]).cpu().numpy()
+            err = float(np.abs(z - ref).max())
+            del g, t, c
+    except Exception as e:  # the baseline itself stands without the comparison
+        log(f"  GPU comparison on the sample skipped: {e}")
     try:
         import threadpoolctl
         threads = max(p.get("num_threads", 1) for p in threadpoolctl.threadpool_info()) or 1
@@ -104,7 +118,7 @@ def cpu_baseline(rows):
                         f"workload, full solve (T={case['solver_iters']}), FP64 NumPy; "
                         f"{dt:.1f} s; elementwise NumPy runs on one core "
                         f"(BLAS pool {threads} threads unused)"),
-                seconds=dt)
+                gpu_max_abs_err=err, seconds=dt)
 
 
 def timed(fn, steps, warmup):
@@ -418,6 +432,51 @@ def stereo_leg(steps, warmup):
                 algorithmic_GBps=round(s_bytes / (ms_s / 1e3) / 1e9, 1))
 
 
+def sweep_leg(steps, warmup):
+    """Flat-throughput checks on the config-1 recipe (N = 3, T = 10, one-channel target):
+    Mpixel/s over image sizes 256^2 .. 8192^2, and the solve time over sigma_s x sigma_r at
+    2048^2 (the recursive filter's cost does not depend on either)."""
+    import ctypes
+
+    import torch
+
+    import dts_inputs
+    import paper_1805_04590_amd as dts
+
+    dev = torch.device("cuda:0")
+    lib = dts.library()
+
+    def prepare(n, seed):
+        c = dts_inputs.random_case(seed, n, n, 3, 1, sigma_s=8.0, sigma_r=0.2, T=10, n_poly=12)
+        g, t, cf = (torch.from_numpy(c[k]).to(dev) for k in ("guide", "target", "conf"))
+        p = dts.Params(8.0, 0.2, 3, 10).c()
+        ws = torch.empty(lib.dts_solve_workspace_bytes(1, n, n, 1, ctypes.byref(p)), dtype=torch.uint8,
+                         device=dev)
+        return g, t, cf, torch.empty_like(t), ws
+
+    sizes = []
+    for n in (256, 512, 1024, 2048, 4096, 8192):
+        g, t, cf, out, ws = prepare(n, 700 + n)
+        ms = timed(lambda: dts.solve(g, t, cf, 8.0, 0.2, 3, 10, out=out[None], workspace=ws), steps, warmup)
+        sizes.append(dict(size=n, ms=round(ms, 4), mpix_s=round(n * n / ms / 1e3, 1)))
+        log(f"  size {n}: {ms:.3f} ms, {n * n / ms / 1e3:.1f} Mpixel/s")
+        del g, t, cf, out, ws
+    n = 2048
+    g, t, cf, out, ws = prepare(n, 900)
+    sig = []
+    for ss in (16.0, 32.0, 128.0, 256.0):
+        for sr in (0.1, 0.3, 0.5, 0.7, 0.9):
+            ms = timed(lambda: dts.solve(g, t, cf, ss, sr, 3, 10, out=out[None], workspace=ws), steps, warmup)
+            sig.append(dict(sigma_s=ss, sigma_r=sr, ms=round(ms, 4)))
+    times = [r["ms"] for r in sig]
+    log(f"  sigma sweep at {n}^2: {min(times):.3f} .. {max(times):.3f} ms")
+    del g, t, cf, out, ws
+    torch.cuda.empty_cache()
+    return dict(workload="config-1 recipe, Cg=3, Ct=1, N=3, T=10", sizes=sizes,
+                sigma=dict(size=n, runs=sig, min_ms=min(times), max_ms=max(times),
+                           max_over_min=round(max(times) / min(times), 3)))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -454,6 +513,9 @@ def main():
         log("stereo leg (1920x1080 pair, T=20) ...")
         extras["stereo"] = stereo_leg(max(3, args.steps // 2), 2)
         log("  " + json.dumps(extras["stereo"]))
+        torch.cuda.empty_cache()
+        log("size and sigma sweeps (config-1 recipe) ...")
+        extras["sweeps"] = sweep_leg(max(3, args.steps // 2), 2)
 
     cpu = None
     if args.cpu_rows > 0:
