@@ -433,9 +433,10 @@ def stereo_leg(steps, warmup):
 
 
 def sweep_leg(steps, warmup):
-    """Flat-throughput checks on the config-1 recipe (N = 3, T = 10, one-channel target):
-    Mpixel/s over image sizes 256^2 .. 8192^2, and the solve time over sigma_s x sigma_r at
-    2048^2 (the recursive filter's cost does not depend on either)."""
+    """Scaling checks on the config-1 recipe (N = 3, one-channel target): Mpixel/s over
+    image sizes 256^2 .. 8192^2 (T = 10), the solve time over sigma_s x sigma_r at 2048^2
+    (the recursive filter's cost does not depend on either), and the time against the
+    number of solver iterations T at 2048^2 (linear)."""
     import ctypes
 
     import torch
@@ -470,11 +471,24 @@ def sweep_leg(steps, warmup):
             sig.append(dict(sigma_s=ss, sigma_r=sr, ms=round(ms, 4)))
     times = [r["ms"] for r in sig]
     log(f"  sigma sweep at {n}^2: {min(times):.3f} .. {max(times):.3f} ms")
+    # time against the number of solver iterations: a least-squares line and the largest
+    # relative deviation from it
+    its = []
+    for T in (1, 2, 5, 10, 20, 40):
+        ms = timed(lambda: dts.solve(g, t, cf, 8.0, 0.2, 3, T, out=out[None], workspace=ws), steps, warmup)
+        its.append(dict(T=T, ms=round(ms, 4)))
+    Ts = np.array([r["T"] for r in its], dtype=np.float64)
+    ms_T = np.array([r["ms"] for r in its], dtype=np.float64)
+    slope, icpt = np.polyfit(Ts, ms_T, 1)
+    dev_T = float(np.max(np.abs(ms_T - (slope * Ts + icpt)) / ms_T))
+    log(f"  iteration sweep at {n}^2: {slope:.4f} ms per iteration + {icpt:.4f} ms, max deviation {dev_T:.3f}")
     del g, t, cf, out, ws
     torch.cuda.empty_cache()
     return dict(workload="config-1 recipe, Cg=3, Ct=1, N=3, T=10", sizes=sizes,
                 sigma=dict(size=n, runs=sig, min_ms=min(times), max_ms=max(times),
-                           max_over_min=round(max(times) / min(times), 3)))
+                           max_over_min=round(max(times) / min(times), 3)),
+                iterations=dict(size=n, runs=its, ms_per_iteration=round(float(slope), 4),
+                                intercept_ms=round(float(icpt), 4), max_rel_deviation=round(dev_T, 4)))
 
 
 def main():
