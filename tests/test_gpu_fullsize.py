@@ -1,13 +1,14 @@
 """The full-size workloads on the GPU, in the launch configurations bench.py times.
 
-The multispectral 10240 x 10240 solve (16-band guide, T = 10) is too large for the FP64
-oracle to run whole within a test, so it is checked two ways:
-- against the oracle on a two-iteration, one-step solve of the same full-size inputs.
-  This covers every kernel of the full solve at its full launch shape: the fused distance
-  pass over 16 bands, the 40-chunk column pass, the streaming row pass and the update
-  epilogue;
+The multispectral 10240 x 10240 solve (16-band guide, T = 10) is checked three ways:
+- against one full FP64 oracle run of the same solve (about two minutes of host time);
+- against the oracle on a two-iteration, one-step solve of the same full-size inputs,
+  which isolates the first passes: the fused distance pass over 16 bands, the 40-chunk
+  column pass, the streaming row pass and the update epilogue;
 - by a property at the full T = 10 configuration: a constant target with uniform
-  confidence is a fixed point, held exactly.
+  confidence is a fixed point.
+The 8 x 1024^2 batch (T = 15) runs whole on the GPU; two of its images are compared with
+the oracle's forward solve.
 The 8 x 1024^2 forward + backward (T = 15) is checked by directional derivatives of its
 loss sum((z - r)^2).  The solve is linear in the target, so along a target direction the
 loss is quadratic and a central difference is exact up to rounding; along a confidence
@@ -32,6 +33,21 @@ def note(*what):
 def config3():
     note("generating the 10240 x 10240 x 16 workload")
     return dts_inputs.config3()
+
+
+def test_config3_full_solve_matches_oracle(config3):
+    c = config3
+    note("GPU solve N=3 T=10")
+    g, t, cf = (torch.from_numpy(c[k]).cuda() for k in ("guide", "target", "conf"))
+    got = dts.solve(g, t, cf, c["sigma_s"], c["sigma_r"], c["filter_iters"], c["solver_iters"]).cpu().numpy()
+    del g, t, cf
+    torch.cuda.empty_cache()
+    note("oracle solve N=3 T=10 (about two minutes)")
+    ref = oracle.solve(c["guide"], c["target"], c["conf"], c["sigma_s"], c["sigma_r"], c["filter_iters"],
+                       c["solver_iters"])
+    err = float(np.abs(got - ref).max())
+    note("max abs err", err)
+    assert err <= 1e-4
 
 
 def test_config3_two_passes_match_oracle(config3):
@@ -59,6 +75,20 @@ def test_config3_constant_target_is_a_fixed_point(config3):
     dev = float((z - 0.37).abs().max())
     note("max deviation", dev)
     assert dev <= 1e-6
+
+
+def test_config5_forward_matches_oracle():
+    c = dts_inputs.config5()
+    note("8 x 1024^2 forward, T=15")
+    g, t, cf = (torch.from_numpy(c[k]).cuda() for k in ("guide", "target", "conf"))
+    got = dts.solve(g, t, cf, c["sigma_s"], c["sigma_r"], c["filter_iters"], c["solver_iters"]).cpu().numpy()
+    for b in (0, 7):
+        note("oracle forward of image", b)
+        ref = oracle.solve(c["guide"][b], c["target"][b], c["conf"][b], c["sigma_s"], c["sigma_r"],
+                           c["filter_iters"], c["solver_iters"])
+        err = float(np.abs(got[b] - ref).max())
+        note("image", b, "max abs err", err)
+        assert err <= 1e-4
 
 
 def _loss(z, r):
