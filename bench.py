@@ -491,6 +491,32 @@ def sweep_leg(steps, warmup):
                                 intercept_ms=round(float(icpt), 4), max_rel_deviation=round(dev_T, 4)))
 
 
+def graph_leg(steps, warmup):
+    """Small solves, launch-bound: config 1 (256^2, T=10) and config 2 (1920x1080, T=20),
+    each as eager dts_solve calls and as replays of one captured HIP graph (SolveGraph)."""
+    import torch
+
+    import dts_inputs
+    import paper_1805_04590_amd as dts
+
+    dev = torch.device("cuda:0")
+    res = {}
+    for name, c in (("config1_256x256_T10", dts_inputs.config1()), ("config2_1920x1080_T20", dts_inputs.config2())):
+        g, t, cf = (torch.from_numpy(c[k]).to(dev) for k in ("guide", "target", "conf"))
+        args = (c["sigma_s"], c["sigma_r"], c["filter_iters"], c["solver_iters"])
+        sg = dts.SolveGraph(g, t, cf, *args)
+        ms_e = timed(lambda: dts.solve(sg.guide, sg.target, sg.conf, *args, out=sg.out, workspace=sg.workspace),
+                     steps * 4, warmup)
+        ms_g = timed(sg.replay, steps * 4, warmup)
+        px = t.shape[-1] * t.shape[-2]
+        res[name] = dict(eager_ms=round(ms_e, 4), graph_ms=round(ms_g, 4), eager_mpix_s=round(px / ms_e / 1e3, 1),
+                         graph_mpix_s=round(px / ms_g / 1e3, 1), speedup=round(ms_e / ms_g, 3))
+        log(f"  {name}: eager {ms_e:.3f} ms, graph {ms_g:.3f} ms")
+        del sg, g, t, cf
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -530,6 +556,8 @@ def main():
         torch.cuda.empty_cache()
         log("size and sigma sweeps (config-1 recipe) ...")
         extras["sweeps"] = sweep_leg(max(3, args.steps // 2), 2)
+        log("small solves: eager against one captured HIP graph ...")
+        extras["graph"] = graph_leg(max(3, args.steps // 2), 2)
 
     cpu = None
     if args.cpu_rows > 0:

@@ -46,6 +46,7 @@ __all__ = [
     "tune_row_segment",
     "batched_variants",
     "BatchedSolver",
+    "SolveGraph",
     "EXPORTED_SYMBOLS",
 ]
 
@@ -479,6 +480,43 @@ class BatchedSolver:
         with torch.cuda.graph(graph):
             self.run()
         return graph
+
+
+class SolveGraph:
+    """One dts_solve captured into a HIP graph (torch.cuda.CUDAGraph) for repeated solves of
+    one shape: the launches of a small image cost more than its passes, and a replay
+    issues them all at once.  The graph owns input, output and workspace buffers; copy new
+    inputs into ``guide`` / ``target`` / ``conf`` and call ``replay()``, which returns
+    ``out``.  Every launch of dts_solve only enqueues work and clears its workspace with
+    kernels, so the captured graph holds no memset nodes."""
+
+    def __init__(self, guide, target, conf, sigma_s, sigma_r, filter_iters=3, solver_iters=10, lam=0.99,
+                 step=0.99):
+        self.guide = _as4d(guide, "guide").clone()
+        self.target = _as4d(target, "target").clone()
+        self.conf = _as4d(conf, "conf").clone()
+        B, Ct, H, W = self.target.shape
+        self.args = (float(sigma_s), float(sigma_r), int(filter_iters), int(solver_iters), float(lam), float(step))
+        p = Params(*self.args).c()
+        self.out = torch.empty_like(self.target)
+        self.workspace = _workspace(library().dts_solve_workspace_bytes(B, H, W, Ct, ctypes.byref(p)),
+                                    self.target.device)
+        self.graph = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            self._run()  # warm-up outside the graph on the capture stream
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(self.graph):
+            self._run()
+
+    def _run(self):
+        solve(self.guide, self.target, self.conf, *self.args, out=self.out, workspace=self.workspace)
+
+    def replay(self):
+        self.graph.replay()
+        return self.out
 
 
 def workspace_status(ws):
