@@ -398,7 +398,7 @@ __global__ void __launch_bounds__(kWave * NWV) col_adjoint_kernel(ColAdjArgs a) 
             L.BJ[wave][c][lane] = BJ[c];
         }
         __syncthreads();
-        if (wave == 0) chunk_carries<NCH, NWV>(cctx, L, b, grp, strip, chunk, lane, valid, 2 * ncv);
+        chunk_carries<NCH, NWV>(cctx, L, b, grp, strip, chunk, lane, wave, valid, 2 * ncv);
         __syncthreads();
 
         float Xin[NCH], Yin[NCH];

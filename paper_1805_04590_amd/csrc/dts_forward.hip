@@ -227,8 +227,13 @@ int launch_row_pass(const RowPass& p, Ctx& ctx) {
 // ---------------------------------------------------------------------------------------
 // Column pass
 // ---------------------------------------------------------------------------------------
+// Waves per SIMD the register allocation must leave room for: the 40-row single-channel
+// chunk only pays off with two 8-wave workgroups per CU, i.e. at most 128 VGPRs.
+template <int CT, int R, int NWV>
+constexpr int col_min_waves() { return (CT == 1 && R == 40 && NWV == 8) ? 4 : 1; }
+
 template <int CT, int R, int NWV, int EPI>
-__global__ void __launch_bounds__(kWave * NWV) col_pass_kernel(ColArgs a) {
+__global__ void __launch_bounds__(kWave * NWV, (col_min_waves<CT, R, NWV>())) col_pass_kernel(ColArgs a) {
     __shared__ ChunkLds<CT, NWV> L;
     const CarryCtx cctx{a.carry, a.epoch, a.status, a.G, a.S, a.NG};
     // Persistent grid: workgroup p always processes chunk p % G, for the strips
@@ -311,6 +316,7 @@ static const ColVariant kColVariants[] = {
     DTS_COL_VARIANT(3, 16, 8),   // 7: 128
     DTS_COL_VARIANT(3, 8, 16),   // 8: 128
     DTS_COL_VARIANT(4, 16, 8),   // 9: 128
+    DTS_COL_VARIANT(1, 40, 8),   // 10: 320, held to 128 VGPRs
 };
 constexpr int kNumColVariants = sizeof(kColVariants) / sizeof(kColVariants[0]);
 constexpr int kMinChunkRows = 128;   // smallest R * NWV above: sizes the carry area
@@ -319,12 +325,16 @@ static int col_group(int C) { return C < 4 ? C : 4; }
 
 static int g_col_pin[5] = {-1, -1, -1, -1, -1};   // per channel-group size, -1 = default
 
-static int col_variant(int C) {
+// Default variant per channel-group size.  Single-channel passes over images of 2048 rows
+// or more take the 320-row chunk: more bytes in flight per workgroup and fewer chunks per
+// strip (10240 rows: 32 chunks, so 16 strips fill the 512 resident workgroups exactly).
+// Shorter images keep the 256-row chunk, whose extra chunks give them more parallelism.
+static int col_variant(int C, int H) {
     const int ct = col_group(C);
     const int pin = g_col_pin[ct];
     if (pin >= 0 && pin < kNumColVariants && kColVariants[pin].ct == ct) return pin;
     switch (ct) {
-        case 1: return 0;
+        case 1: return H >= 2048 ? 10 : 0;
         case 2: return 6;
         case 3: return 7;
         default: return 9;
@@ -358,7 +368,7 @@ size_t col_carry_words(int batch, int H, int W, int C) {
 }
 
 int launch_col_pass(const ColPass& p, Ctx& ctx) {
-    const ColVariant& v = kColVariants[col_variant(p.C)];
+    const ColVariant& v = kColVariants[col_variant(p.C, p.H)];
     ColArgs a;
     a.src = p.src;
     a.dst = p.dst;

@@ -374,7 +374,7 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, const CarryCtx& cctx,
         L.BJ[wave][c][lane] = BJ[c];
     }
     __syncthreads();
-    if (wave == 0) chunk_carries<CT, NWV>(cctx, L, b, grp, strip, chunk, lane, valid, ncv);
+    chunk_carries<CT, NWV>(cctx, L, b, grp, strip, chunk, lane, wave, valid, ncv);
     __syncthreads();
     hook();
 

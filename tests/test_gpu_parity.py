@@ -248,3 +248,31 @@ def test_workspace_status_is_clean():
     dts.solve(dev(case["guide"]), dev(case["target"]), dev(case["conf"]), 8.0, 0.2, 3, 2,
               workspace=ws)
     assert dts.workspace_status(ws) == 0
+
+
+def _variant_cases():
+    # every column-pass variant, pinned in turn: 2.5 chunks per strip plus a ragged row
+    # tail, three strips with a ragged column tail, and for four-channel groups a second,
+    # partial channel group
+    return [(v, ct, R, nw) for v, ct, R, nw in dts.col_variants()]
+
+
+@pytest.mark.parametrize("v,ct,R,nw", _variant_cases())
+def test_every_column_variant_matches_oracle(v, ct, R, nw):
+    H, W = int(2.5 * R * nw) + 3, 130
+    C = ct if ct < 4 else 5
+    announce("column variant", v, ct, R, nw, H, W, C)
+    case = dts_inputs.random_case(6100 + v, H, W, 3, C, Cc=1, sigma_s=12.0, sigma_r=0.2, T=2)
+    rdx, rdy = oracle.distances(case["guide"], 12.0, 0.2)
+    a = oracle.feedback_coefficients(12.0, 3)[0]
+    f = case["target"].astype(np.float64)
+    ref_col = np.moveaxis(oracle.rf1d_lines(np.moveaxis(f, -2, 0), (a ** rdy)[:, None, :]), 0, -2)
+    ref_solve = oracle_solve(case)
+    dts.tune_col_variant(ct, v)
+    try:
+        got_col = host(dts.col_pass(dev(case["target"]), dev(rdy.astype(np.float32)[None]), 12.0, 1, 3))
+        got_solve = host(gpu_solve(case))
+    finally:
+        dts.tune_col_variant(ct, -1)
+    assert np.abs(got_col[0] - ref_col).max() <= FILTER_TOL
+    assert np.abs(got_solve - ref_solve).max() <= SOLVE_TOL
