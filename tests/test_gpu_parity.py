@@ -276,3 +276,23 @@ def test_every_column_variant_matches_oracle(v, ct, R, nw):
         dts.tune_col_variant(ct, -1)
     assert np.abs(got_col[0] - ref_col).max() <= FILTER_TOL
     assert np.abs(got_solve - ref_solve).max() <= SOLVE_TOL
+
+
+@pytest.mark.parametrize("v,ct,R,nw", _variant_cases())
+def test_every_column_variant_on_long_strips(v, ct, R, nw):
+    # about 20 chunks per strip, so each look-back and look-ahead takes several round
+    # trips of NWV neighbours; two strips, the second ragged
+    H, W = int(19.5 * R * nw) + 5, 77
+    C = ct if ct < 4 else 5
+    announce("column variant, long strips", v, ct, R, nw, H, W, C)
+    case = dts_inputs.random_case(6200 + v, H, W, 2, C, Cc=1, sigma_s=40.0, sigma_r=0.3, T=1)
+    rdx, rdy = oracle.distances(case["guide"], 40.0, 0.3)
+    a = oracle.feedback_coefficients(40.0, 3)[0]
+    f = case["target"].astype(np.float64)
+    ref_col = np.moveaxis(oracle.rf1d_lines(np.moveaxis(f, -2, 0), (a ** rdy)[:, None, :]), 0, -2)
+    dts.tune_col_variant(ct, v)
+    try:
+        got_col = host(dts.col_pass(dev(case["target"]), dev(rdy.astype(np.float32)[None]), 40.0, 1, 3))
+    finally:
+        dts.tune_col_variant(ct, -1)
+    assert np.abs(got_col[0] - ref_col).max() <= FILTER_TOL
