@@ -88,7 +88,7 @@ def cpu_baseline(rows):
     import dts_inputs
     import oracle
 
-    case = dts_inputs.config3(rows=(0, rows))
+    case = dts_inputs.multispectral_10240(rows=(0, rows))
     px = case["target"].shape[1] * case["target"].shape[2]
     t0 = time.perf_counter()
     ref = oracle.solve(case["guide"], case["target"], case["conf"], case["sigma_s"], case["sigma_r"],
@@ -146,7 +146,7 @@ def batched_leg(steps, warmup, graph=True):
     import dts_inputs
     import paper_1805_04590_amd as dts
 
-    cases = dts_inputs.config4()
+    cases = dts_inputs.uneven_batch_64()
     dev = torch.device("cuda:0")
     probs = [dict(guide=torch.from_numpy(c["guide"]).to(dev), target=torch.from_numpy(c["target"]).to(dev),
                   conf=torch.from_numpy(c["conf"]).to(dev), sigma_s=c["sigma_s"], sigma_r=c["sigma_r"],
@@ -187,7 +187,7 @@ def fwd_bwd_leg(steps, warmup):
     import dts_inputs
     import paper_1805_04590_amd as dts
 
-    c = dts_inputs.config5()
+    c = dts_inputs.rgb_batch_8x1024()
     dev = torch.device("cuda:0")
     g = torch.from_numpy(c["guide"]).to(dev)
     t = torch.from_numpy(c["target"]).to(dev)
@@ -255,10 +255,10 @@ def solve_leg(args, dev):
     import dts_inputs
     import paper_1805_04590_amd as dts
 
-    H, W, Cg = dts_inputs.config3_shape()
+    H, W, Cg = dts_inputs.multispectral_shape()
     t0 = time.time()
     log(f"generating the {W}x{H}x{Cg} workload ...")
-    case = dts_inputs.config3()
+    case = dts_inputs.multispectral_10240()
     log(f"  generated in {time.time() - t0:.1f} s; uploading")
     guide = torch.from_numpy(case["guide"]).to(dev)
     target = torch.from_numpy(case["target"]).to(dev)
@@ -397,7 +397,7 @@ def stereo_leg(steps, warmup):
     import dts_inputs
     import paper_1805_04590_amd as dts
 
-    c = dts_inputs.config2_stereo()
+    c = dts_inputs.stereo_pair_1920x1080()
     dev = torch.device("cuda:0")
     L = torch.from_numpy(c["left"]).to(dev)
     R = torch.from_numpy(c["right"]).to(dev)
@@ -433,7 +433,7 @@ def stereo_leg(steps, warmup):
 
 
 def sweep_leg(steps, warmup):
-    """Scaling checks on the config-1 recipe (N = 3, one-channel target): Mpixel/s over
+    """Scaling checks on the polygon-scene recipe (N = 3, one-channel target): Mpixel/s over
     image sizes 256^2 .. 8192^2 (T = 10), the solve time over sigma_s x sigma_r at 2048^2
     (the recursive filter's cost does not depend on either), and the time against the
     number of solver iterations T at 2048^2 (linear)."""
@@ -484,7 +484,7 @@ def sweep_leg(steps, warmup):
     log(f"  iteration sweep at {n}^2: {slope:.4f} ms per iteration + {icpt:.4f} ms, max deviation {dev_T:.3f}")
     del g, t, cf, out, ws
     torch.cuda.empty_cache()
-    return dict(workload="config-1 recipe, Cg=3, Ct=1, N=3, T=10", sizes=sizes,
+    return dict(workload="polygon-scene recipe, Cg=3, Ct=1, N=3, T=10", sizes=sizes,
                 sigma=dict(size=n, runs=sig, min_ms=min(times), max_ms=max(times),
                            max_over_min=round(max(times) / min(times), 3)),
                 iterations=dict(size=n, runs=its, ms_per_iteration=round(float(slope), 4),
@@ -492,7 +492,7 @@ def sweep_leg(steps, warmup):
 
 
 def graph_leg(steps, warmup):
-    """Small solves, launch-bound: config 1 (256^2, T=10) and config 2 (1920x1080, T=20),
+    """Small solves, launch-bound: the 256^2 polygon scene (T=10) and the 1920x1080 disparity scene (T=20),
     each as eager dts_solve calls and as replays of one captured HIP graph (SolveGraph)."""
     import torch
 
@@ -501,7 +501,7 @@ def graph_leg(steps, warmup):
 
     dev = torch.device("cuda:0")
     res = {}
-    for name, c in (("config1_256x256_T10", dts_inputs.config1()), ("config2_1920x1080_T20", dts_inputs.config2())):
+    for name, c in (("polygon_256x256_T10", dts_inputs.polygon_256()), ("disparity_1920x1080_T20", dts_inputs.disparity_1920x1080())):
         g, t, cf = (torch.from_numpy(c[k]).to(dev) for k in ("guide", "target", "conf"))
         args = (c["sigma_s"], c["sigma_r"], c["filter_iters"], c["solver_iters"])
         sg = dts.SolveGraph(g, t, cf, *args)
@@ -554,7 +554,7 @@ def main():
         extras["stereo"] = stereo_leg(max(3, args.steps // 2), 2)
         log("  " + json.dumps(extras["stereo"]))
         torch.cuda.empty_cache()
-        log("size and sigma sweeps (config-1 recipe) ...")
+        log("size and sigma sweeps (polygon-scene recipe) ...")
         extras["sweeps"] = sweep_leg(max(3, args.steps // 2), 2)
         log("small solves: eager against one captured HIP graph ...")
         extras["graph"] = graph_leg(max(3, args.steps // 2), 2)

@@ -25,15 +25,15 @@ import numpy as np
 
 __all__ = [
     "polygon_scene",
-    "config1",
-    "config2",
-    "config3_shape",
-    "config3_labels",
-    "config3_guide_band",
-    "config3_target",
-    "config3",
-    "config4",
-    "config5",
+    "polygon_256",
+    "disparity_1920x1080",
+    "multispectral_shape",
+    "multispectral_labels",
+    "multispectral_guide_band",
+    "multispectral_target",
+    "multispectral_10240",
+    "uneven_batch_64",
+    "rgb_batch_8x1024",
     "random_case",
 ]
 
@@ -111,8 +111,8 @@ def _noisy_guide(rng, guide, sd):
     return np.clip(g, 0.0, 1.0).astype(np.float32)
 
 
-def _c1_style(seed, H, W, Cg, Ct, n_poly):
-    """The config-1 recipe at any size: polygon guide with noise sd 0.02, per-label
+def _polygon_case(seed, H, W, Cg, Ct, n_poly):
+    """The polygon-scene recipe at any size: polygon guide with noise sd 0.02, per-label
     U[0,1]^Ct target plus noise sd 0.05 clipped to [0,1], confidence U[0.1,1]^Ct."""
     rng = np.random.default_rng(seed)
     clean, labels = polygon_scene(rng, H, W, Cg, n_poly)
@@ -124,15 +124,15 @@ def _c1_style(seed, H, W, Cg, Ct, n_poly):
     return guide, target, conf, labels
 
 
-def config1(seed=0):
+def polygon_256(seed=0):
     """256x256 RGB guide, 12 polygons, 1-channel target; sigma_s=8, sigma_r=0.2, T=10."""
-    guide, target, conf, _ = _c1_style(seed, 256, 256, 3, 1, 12)
-    return dict(name="C1 256x256 RGB->1, T=10", guide=guide, target=target, conf=conf,
+    guide, target, conf, _ = _polygon_case(seed, 256, 256, 3, 1, 12)
+    return dict(name="polygon 256x256 RGB->1, T=10", guide=guide, target=target, conf=conf,
                 sigma_s=8.0, sigma_r=0.2, filter_iters=FILTER_ITERS, solver_iters=10,
                 lam=LAMBDA, step=STEP, value_range=1.0)
 
 
-def _config2_parts(seed):
+def _disparity_parts(seed):
     H, W, Cg, n_poly = 1080, 1920, 3, 32
     rng = np.random.default_rng(seed)
     clean, labels = polygon_scene(rng, H, W, Cg, n_poly)
@@ -153,15 +153,15 @@ def _config2_parts(seed):
     return guide, clean_disp, disp, conf
 
 
-def config2(seed=1):
+def disparity_1920x1080(seed=1):
     """1920x1080 RGB guide (32 polygons) with a disparity-like target in [0, 256).
 
     The stereo-refinement stand-in: per-label planar disparity a + b*x/W + c*y/H with
     a ~ U[16,224], b, c ~ U[-16,16], clipped to [0,256); 10% of pixels replaced by
     U[0,256) outliers; confidence 0.05 on outliers and U[0.5,1] elsewhere;
     sigma_s=16, sigma_r=0.1, T=20."""
-    guide, _, disp, conf = _config2_parts(seed)
-    return dict(name="C2 1920x1080 RGB->1 disparity, T=20", guide=guide,
+    guide, _, disp, conf = _disparity_parts(seed)
+    return dict(name="disparity 1920x1080 RGB->1, T=20", guide=guide,
                 target=disp.astype(np.float32)[None], conf=conf.astype(np.float32)[None],
                 sigma_s=16.0, sigma_r=0.1, filter_iters=FILTER_ITERS, solver_iters=20,
                 lam=LAMBDA, step=STEP, value_range=256.0)
@@ -185,13 +185,13 @@ STEREO_GAMMA = 0.001  # Sec. 4, stereo optimisation
 STEREO_EPS = 0.001    # Charbonnier epsilon of Sec. 3.3
 
 
-def config2_stereo(seed=1):
-    """The config-2 scene as a stereo pair: the guide is the left image, the right image
+def stereo_pair_1920x1080(seed=1):
+    """The 1920x1080 disparity scene as a stereo pair: the guide is the left image, the right image
     is warped by the clean planar disparity, the target is the disparity with its 10%
     outliers.  gamma and epsilon of the stereo refinement, sigma_s=16, sigma_r=0.1, T=20."""
-    guide, clean_disp, disp, conf = _config2_parts(seed)
+    guide, clean_disp, disp, conf = _disparity_parts(seed)
     right = warp_right(guide, clean_disp)
-    return dict(name="C2 stereo 1920x1080 RGB pair, disparity target, T=20", left=guide, right=right,
+    return dict(name="stereo 1920x1080 RGB pair, disparity target, T=20", left=guide, right=right,
                 target=disp.astype(np.float32)[None], conf=conf.astype(np.float32)[None],
                 sigma_s=16.0, sigma_r=0.1, filter_iters=FILTER_ITERS, solver_iters=20,
                 lam=LAMBDA, step=STEP, gamma=STEREO_GAMMA, eps=STEREO_EPS, value_range=256.0)
@@ -199,7 +199,7 @@ def config2_stereo(seed=1):
 
 def stereo_case(seed, H, W, Cg=3, d_max=16.0, sigma_s=8.0, sigma_r=0.2, T=5, gamma=STEREO_GAMMA,
                 eps=STEREO_EPS):
-    """A small synthetic stereo pair: config-1 style left image, per-label planar
+    """A small synthetic stereo pair: polygon-scene left image, per-label planar
     disparity in [0, d_max) with 10% outliers, right image warped by the clean disparity."""
     rng = np.random.default_rng(seed)
     n_poly = 8
@@ -219,27 +219,27 @@ def stereo_case(seed, H, W, Cg=3, d_max=16.0, sigma_s=8.0, sigma_r=0.2, T=5, gam
 
 
 # ---------------------------------------------------------------------------------------
-# Config 3: 10240 x 10240, 16 bands.  Generated in row blocks with per-block seeds so any
+# Multispectral scene: 10240 x 10240, 16 bands.  Generated in row blocks with per-block seeds so any
 # horizontal band can be produced on its own and equals the same rows of the full image.
 # ---------------------------------------------------------------------------------------
-C3_H = 10240
-C3_W = 10240
-C3_BANDS = 16
-C3_BLOCK = 512
-C3_SEED = 2
+MS_H = 10240
+MS_W = 10240
+MS_BANDS = 16
+MS_BLOCK = 512
+MS_SEED = 2
 
 
-def config3_shape():
-    return C3_H, C3_W, C3_BANDS
+def multispectral_shape():
+    return MS_H, MS_W, MS_BANDS
 
 
-def _c3_fields(seed):
+def _ms_fields(seed):
     rng = np.random.default_rng([seed, 0])
     fields = rng.standard_normal((2, 161, 161))
     cuts = [np.quantile(f, [1.0 / 3.0, 2.0 / 3.0]) for f in fields]
     rng1 = np.random.default_rng([seed, 1])
     base = rng1.uniform(0.1, 0.6, size=9)
-    gain = rng1.uniform(0.5, 1.5, size=(9, C3_BANDS))
+    gain = rng1.uniform(0.5, 1.5, size=(9, MS_BANDS))
     value = rng1.uniform(0.0, 1.0, size=9)
     return fields, cuts, base, gain, value
 
@@ -247,7 +247,7 @@ def _c3_fields(seed):
 def _bilinear_rows(field, ys, W):
     """Bilinear (corner-aligned) upsampling of a 161x161 field to rows ``ys`` of width W."""
     n = field.shape[0] - 1
-    fy = ys.astype(np.float64) * n / (C3_H - 1)
+    fy = ys.astype(np.float64) * n / (MS_H - 1)
     iy = np.minimum(np.floor(fy).astype(np.int64), n - 1)
     ty = (fy - iy)[:, None]
     rows = (1.0 - ty) * field[iy] + ty * field[iy + 1]
@@ -257,7 +257,7 @@ def _bilinear_rows(field, ys, W):
     return (1.0 - tx) * rows[:, ix] + tx * rows[:, ix + 1]
 
 
-def _c3_region(fields, cuts, ys, W):
+def _ms_region(fields, cuts, ys, W):
     lab = np.zeros((len(ys), W), dtype=np.int32)
     for f, (q1, q2), scale in zip(fields, cuts, (3, 1)):
         up = _bilinear_rows(f, ys, W)
@@ -265,26 +265,26 @@ def _c3_region(fields, cuts, ys, W):
     return lab
 
 
-def config3_labels(r0, r1, seed=C3_SEED):
+def multispectral_labels(r0, r1, seed=MS_SEED):
     """Region labels (0..8) of rows [r0, r1): two smooth random fields (161x161 Gaussian
     noise, bilinearly upsampled) thresholded at the terciles of the low-res fields."""
-    fields, cuts, *_ = _c3_fields(seed)
-    return _c3_region(fields, cuts, np.arange(r0, r1), C3_W)
+    fields, cuts, *_ = _ms_fields(seed)
+    return _ms_region(fields, cuts, np.arange(r0, r1), MS_W)
 
 
-def config3_guide_band(k, r0, r1, labels=None, seed=C3_SEED):
+def multispectral_guide_band(k, r0, r1, labels=None, seed=MS_SEED):
     """Band k of the 16-band guide on rows [r0, r1) (r0, r1 multiples of 512):
     clip(gain[region, k] * base[region] + N(0, 0.01), 0, 1)."""
-    fields, cuts, base, gain, _ = _c3_fields(seed)
+    fields, cuts, base, gain, _ = _ms_fields(seed)
     if labels is None:
-        labels = _c3_region(fields, cuts, np.arange(r0, r1), C3_W)
+        labels = _ms_region(fields, cuts, np.arange(r0, r1), MS_W)
     lut = (gain[:, k] * base).astype(np.float32)
-    out = np.empty((r1 - r0, C3_W), dtype=np.float32)
-    for b0 in range(r0, r1, C3_BLOCK):
-        b = b0 // C3_BLOCK
+    out = np.empty((r1 - r0, MS_W), dtype=np.float32)
+    for b0 in range(r0, r1, MS_BLOCK):
+        b = b0 // MS_BLOCK
         rng = np.random.default_rng([seed, 2, k, b])
-        sl = slice(b0 - r0, b0 - r0 + C3_BLOCK)
-        noise = rng.standard_normal((C3_BLOCK, C3_W), dtype=np.float32)
+        sl = slice(b0 - r0, b0 - r0 + MS_BLOCK)
+        noise = rng.standard_normal((MS_BLOCK, MS_W), dtype=np.float32)
         out[sl] = lut[labels[sl]] + np.float32(0.01) * noise
     np.clip(out, 0.0, 1.0, out=out)
     return out
@@ -293,32 +293,32 @@ def config3_guide_band(k, r0, r1, labels=None, seed=C3_SEED):
 _LOWRES_CACHE = {}
 
 
-def _c3_lowres_target(seed):
+def _ms_lowres_target(seed):
     if seed not in _LOWRES_CACHE:
-        fields, cuts, _, _, value = _c3_fields(seed)
-        centres = np.arange(8, C3_H, 16)
-        low_lab = _c3_region(fields, cuts, centres, C3_W)[:, 8::16]
+        fields, cuts, _, _, value = _ms_fields(seed)
+        centres = np.arange(8, MS_H, 16)
+        low_lab = _ms_region(fields, cuts, centres, MS_W)[:, 8::16]
         _LOWRES_CACHE[seed] = value[low_lab].astype(np.float32)
     return _LOWRES_CACHE[seed]
 
 
-def config3_target(r0, r1, seed=C3_SEED):
+def multispectral_target(r0, r1, seed=MS_SEED):
     """Target rows [r0, r1): the region value at the centre of each 16x16 block (a 640x640
     low-resolution map), nearest-upsampled x16, plus N(0, 0.02), clipped to [0,1]."""
-    low = _c3_lowres_target(seed)
-    out = np.empty((r1 - r0, C3_W), dtype=np.float32)
-    for b0 in range(r0, r1, C3_BLOCK):
-        b = b0 // C3_BLOCK
+    low = _ms_lowres_target(seed)
+    out = np.empty((r1 - r0, MS_W), dtype=np.float32)
+    for b0 in range(r0, r1, MS_BLOCK):
+        b = b0 // MS_BLOCK
         rng = np.random.default_rng([seed, 3, b])
-        rows = np.arange(b0, b0 + C3_BLOCK) // 16
+        rows = np.arange(b0, b0 + MS_BLOCK) // 16
         up = np.repeat(low[rows], 16, axis=1)
-        noise = rng.standard_normal((C3_BLOCK, C3_W), dtype=np.float32)
-        out[b0 - r0:b0 - r0 + C3_BLOCK] = up + np.float32(0.02) * noise
+        noise = rng.standard_normal((MS_BLOCK, MS_W), dtype=np.float32)
+        out[b0 - r0:b0 - r0 + MS_BLOCK] = up + np.float32(0.02) * noise
     np.clip(out, 0.0, 1.0, out=out)
     return out
 
 
-def config3(rows=(0, C3_H), seed=C3_SEED, workers=8):
+def multispectral_10240(rows=(0, MS_H), seed=MS_SEED, workers=8):
     """The 10240x10240, 16-band, 1-channel multispectral workload (or a full-width band
     of it): confidence 1, sigma_s=32, sigma_r=0.15, T=10.  The full guide is 6.7 GB.
     Tiles (band, 512-row block) are independently seeded, so a thread pool fills them in
@@ -326,34 +326,34 @@ def config3(rows=(0, C3_H), seed=C3_SEED, workers=8):
     from concurrent.futures import ThreadPoolExecutor
 
     r0, r1 = rows
-    assert r0 % C3_BLOCK == 0 and r1 % C3_BLOCK == 0 and 0 <= r0 < r1 <= C3_H
-    guide = np.empty((C3_BANDS, r1 - r0, C3_W), dtype=np.float32)
-    blocks = list(range(r0, r1, C3_BLOCK))
+    assert r0 % MS_BLOCK == 0 and r1 % MS_BLOCK == 0 and 0 <= r0 < r1 <= MS_H
+    guide = np.empty((MS_BANDS, r1 - r0, MS_W), dtype=np.float32)
+    blocks = list(range(r0, r1, MS_BLOCK))
     with ThreadPoolExecutor(max(1, workers)) as ex:
-        labels = dict(zip(blocks, ex.map(lambda b0: config3_labels(b0, b0 + C3_BLOCK, seed),
+        labels = dict(zip(blocks, ex.map(lambda b0: multispectral_labels(b0, b0 + MS_BLOCK, seed),
                                          blocks)))
 
         def fill(job):
             k, b0 = job
-            guide[k, b0 - r0:b0 - r0 + C3_BLOCK] = config3_guide_band(
-                k, b0, b0 + C3_BLOCK, labels=labels[b0], seed=seed)
+            guide[k, b0 - r0:b0 - r0 + MS_BLOCK] = multispectral_guide_band(
+                k, b0, b0 + MS_BLOCK, labels=labels[b0], seed=seed)
 
-        list(ex.map(fill, [(k, b0) for k in range(C3_BANDS) for b0 in blocks]))
-        target = np.empty((1, r1 - r0, C3_W), dtype=np.float32)
+        list(ex.map(fill, [(k, b0) for k in range(MS_BANDS) for b0 in blocks]))
+        target = np.empty((1, r1 - r0, MS_W), dtype=np.float32)
 
         def fill_t(b0):
-            target[0, b0 - r0:b0 - r0 + C3_BLOCK] = config3_target(b0, b0 + C3_BLOCK, seed)
+            target[0, b0 - r0:b0 - r0 + MS_BLOCK] = multispectral_target(b0, b0 + MS_BLOCK, seed)
 
         list(ex.map(fill_t, blocks))
     conf = np.ones_like(target)
-    return dict(name="C3 10240x10240 16-band->1, T=10", guide=guide, target=target, conf=conf,
+    return dict(name="multispectral 10240x10240 16-band->1, T=10", guide=guide, target=target, conf=conf,
                 sigma_s=32.0, sigma_r=0.15, filter_iters=FILTER_ITERS, solver_iters=10,
                 lam=LAMBDA, step=STEP, value_range=1.0)
 
 
-def config4(n=64, seed0=100, workers=8):
+def uneven_batch_64(n=64, seed0=100, workers=8):
     """64 uneven instances: W ~ U{320..1920}, H ~ U{240..1080}, Cg in {1,3,8,16},
-    Ct in {1,2,3}, sigma_s ~ U[4,32], sigma_r ~ U[0.05,0.3], T=10; scenes as config 1.
+    Ct in {1,2,3}, sigma_s ~ U[4,32], sigma_r ~ U[0.05,0.3], T=10; polygon scenes.
     Instances are independently seeded, so a thread pool builds them in any order."""
     from concurrent.futures import ThreadPoolExecutor
 
@@ -365,8 +365,8 @@ def config4(n=64, seed0=100, workers=8):
         Ct = int(rng.integers(1, 4))
         sigma_s = float(rng.uniform(4.0, 32.0))
         sigma_r = float(rng.uniform(0.05, 0.3))
-        guide, target, conf, _ = _c1_style(seed0 + 1000 + i, H, W, Cg, Ct, 12)
-        return dict(name=f"C4[{i}] {W}x{H} Cg={Cg} Ct={Ct}", guide=guide, target=target,
+        guide, target, conf, _ = _polygon_case(seed0 + 1000 + i, H, W, Cg, Ct, 12)
+        return dict(name=f"uneven[{i}] {W}x{H} Cg={Cg} Ct={Ct}", guide=guide, target=target,
                     conf=conf, sigma_s=sigma_s, sigma_r=sigma_r, filter_iters=FILTER_ITERS,
                     solver_iters=10, lam=LAMBDA, step=STEP, value_range=1.0)
 
@@ -374,16 +374,16 @@ def config4(n=64, seed0=100, workers=8):
         return list(ex.map(one, range(n)))
 
 
-def config5(n=8, size=1024, seed0=200, ref_seed=299, workers=8):
-    """Batch of 8 1024x1024 RGB guides with 3-channel targets and confidences (config-1
+def rgb_batch_8x1024(n=8, size=1024, seed0=200, ref_seed=299, workers=8):
+    """Batch of 8 1024x1024 RGB guides with 3-channel targets and confidences (polygon-scene
     scenes), T=15, and the seeded reference r ~ U[0,1] of the loss sum((z^T - r)^2)."""
     from concurrent.futures import ThreadPoolExecutor
 
     with ThreadPoolExecutor(max(1, workers)) as ex:
-        parts = list(ex.map(lambda i: _c1_style(seed0 + i, size, size, 3, 3, 12), range(n)))
+        parts = list(ex.map(lambda i: _polygon_case(seed0 + i, size, size, 3, 3, 12), range(n)))
     rng = np.random.default_rng(ref_seed)
     ref = rng.uniform(0.0, 1.0, size=(n, 3, size, size)).astype(np.float32)
-    return dict(name=f"C5 {n}x{size}x{size} RGB->3, T=15",
+    return dict(name=f"rgb batch {n}x{size}x{size} RGB->3, T=15",
                 guide=np.stack([p[0] for p in parts]), target=np.stack([p[1] for p in parts]),
                 conf=np.stack([p[2] for p in parts]), ref=ref,
                 sigma_s=8.0, sigma_r=0.2, filter_iters=FILTER_ITERS, solver_iters=15,
@@ -391,9 +391,9 @@ def config5(n=8, size=1024, seed0=200, ref_seed=299, workers=8):
 
 
 def random_case(seed, H, W, Cg, Ct, Cc=None, sigma_s=6.0, sigma_r=0.25, T=3, n_poly=4):
-    """Small config-1 style case of any shape for parity tests (Cc = 1 or Ct)."""
+    """Small polygon-scene case of any shape for parity tests (Cc = 1 or Ct)."""
     Cc = Ct if Cc is None else Cc
-    guide, target, conf, _ = _c1_style(seed, H, W, Cg, Ct, n_poly)
+    guide, target, conf, _ = _polygon_case(seed, H, W, Cg, Ct, n_poly)
     if Cc == 1:
         conf = conf[:1].copy()
     return dict(name=f"rand{seed} {W}x{H} Cg={Cg} Ct={Ct} Cc={Cc}", guide=guide, target=target,

@@ -117,9 +117,9 @@ def test_autotuner_picks_and_caches(tmp_path):
         del os.environ["DTS_TUNE_CACHE"]
 
 
-def test_config4_full_matches_single_solves():
-    cases = dts_inputs.config4()
-    print("CASE config 4 (64 uneven solves)", flush=True)
+def test_uneven_batch_64_matches_single_solves():
+    cases = dts_inputs.uneven_batch_64()
+    print("CASE 64 uneven solves", flush=True)
     probs = problems_of(cases)
     bs = dts.BatchedSolver(probs, variant=0)
     outs = bs.run()

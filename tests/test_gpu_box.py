@@ -111,7 +111,7 @@ def test_solve_box_zero_iterations_copies_the_target():
 def test_solve_box_full_stereo_shape():
     # the 1920 x 1080 disparity workload (sigma_s = 16, sigma_r = 0.1, T = 20); the
     # disparities lie in [0, 256) and are compared at 1e-4 of that range
-    c = dts_inputs.config2(seed=1)
+    c = dts_inputs.disparity_1920x1080(seed=1)
     print("CASE box solve 1920x1080 T=20", flush=True)
     got = dts.solve_box(dev(c["guide"]), dev(c["target"]), dev(c["conf"]), c["sigma_s"], c["sigma_r"],
                         c["filter_iters"], c["solver_iters"]).cpu().numpy()

@@ -68,7 +68,7 @@ def test_output_may_alias_input():
 
 
 def test_full_size_stereo_shape():
-    c = dts_inputs.config2()
+    c = dts_inputs.disparity_1920x1080()
     print("CASE variance confidence 1920x1080", flush=True)
     z = c["target"] / np.float32(c["value_range"])  # disparities scaled to [0, 1)
     got = dts.variance_confidence(dev(c["guide"]), dev(z), c["sigma_s"], c["sigma_r"], 0.05)

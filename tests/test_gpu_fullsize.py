@@ -30,13 +30,13 @@ def note(*what):
 
 
 @pytest.fixture(scope="module")
-def config3():
+def multispectral_10240():
     note("generating the 10240 x 10240 x 16 workload")
-    return dts_inputs.config3()
+    return dts_inputs.multispectral_10240()
 
 
-def test_config3_full_solve_matches_oracle(config3):
-    c = config3
+def test_multispectral_10240_full_solve_matches_oracle(multispectral_10240):
+    c = multispectral_10240
     note("GPU solve N=3 T=10")
     g, t, cf = (torch.from_numpy(c[k]).cuda() for k in ("guide", "target", "conf"))
     got = dts.solve(g, t, cf, c["sigma_s"], c["sigma_r"], c["filter_iters"], c["solver_iters"]).cpu().numpy()
@@ -50,8 +50,8 @@ def test_config3_full_solve_matches_oracle(config3):
     assert err <= 1e-4
 
 
-def test_config3_two_passes_match_oracle(config3):
-    c = config3
+def test_multispectral_10240_two_passes_match_oracle(multispectral_10240):
+    c = multispectral_10240
     N, T = 2, 1
     note("GPU solve N=2 T=1")
     g, t, cf = (torch.from_numpy(c[k]).cuda() for k in ("guide", "target", "conf"))
@@ -65,8 +65,8 @@ def test_config3_two_passes_match_oracle(config3):
     assert err <= 1e-4
 
 
-def test_config3_constant_target_is_a_fixed_point(config3):
-    c = config3
+def test_multispectral_10240_constant_target_is_a_fixed_point(multispectral_10240):
+    c = multispectral_10240
     note("GPU solve N=3 T=10, constant target")
     g = torch.from_numpy(c["guide"]).cuda()
     t = torch.full((1,) + c["guide"].shape[1:], 0.37, dtype=torch.float32, device="cuda")
@@ -77,8 +77,8 @@ def test_config3_constant_target_is_a_fixed_point(config3):
     assert dev <= 1e-6
 
 
-def test_config5_forward_matches_oracle():
-    c = dts_inputs.config5()
+def test_rgb_batch_8x1024_forward_matches_oracle():
+    c = dts_inputs.rgb_batch_8x1024()
     note("8 x 1024^2 forward, T=15")
     g, t, cf = (torch.from_numpy(c[k]).cuda() for k in ("guide", "target", "conf"))
     got = dts.solve(g, t, cf, c["sigma_s"], c["sigma_r"], c["filter_iters"], c["solver_iters"]).cpu().numpy()
@@ -95,8 +95,8 @@ def _loss(z, r):
     return float(((z.double() - r.double()) ** 2).sum())
 
 
-def test_config5_gradients_match_directional_derivatives():
-    c = dts_inputs.config5()
+def test_rgb_batch_8x1024_gradients_match_directional_derivatives():
+    c = dts_inputs.rgb_batch_8x1024()
     note("8 x 1024^2 forward + backward")
     g, t, cf, r = (torch.from_numpy(c[k]).cuda() for k in ("guide", "target", "conf", "ref"))
     ss, sr, N, T = c["sigma_s"], c["sigma_r"], c["filter_iters"], c["solver_iters"]

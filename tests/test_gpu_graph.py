@@ -15,7 +15,7 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
 
 
-@pytest.mark.parametrize("which", ["config1", "config2"])
+@pytest.mark.parametrize("which", ["polygon_256", "disparity_1920x1080"])
 def test_graph_replays_match_eager(which):
     c = getattr(dts_inputs, which)()
     print("CASE graph", c["name"], flush=True)
@@ -38,6 +38,6 @@ def test_graph_replays_match_eager(which):
     got = sg.replay()[0].clone()
     eager2 = dts.solve(g, t2, cf, *args)
     assert float((got - eager2).abs().max()) <= tol
-    if which == "config1":
+    if which == "polygon_256":
         ref = oracle.solve(c["guide"], t2.cpu().numpy(), c["conf"], *args)
         assert np.abs(got.cpu().numpy() - ref).max() <= 1e-4

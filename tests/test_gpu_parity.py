@@ -177,23 +177,23 @@ def test_solve_matches_oracle(H, W, Cg, Ct, Cc, T):
     assert err <= SOLVE_TOL, err
 
 
-def test_solve_config1_full():
-    case = dts_inputs.config1()
+def test_solve_polygon_256_full():
+    case = dts_inputs.polygon_256()
     announce(case["name"])
     got = host(gpu_solve(case))
     ref = oracle_solve(case)
     err = np.abs(got - ref).max()
-    print("C1 max abs err", err, flush=True)
+    print("polygon 256x256 max abs err", err, flush=True)
     assert err <= SOLVE_TOL
 
 
-def test_solve_config2_full():
-    case = dts_inputs.config2()
+def test_solve_disparity_1920x1080_full():
+    case = dts_inputs.disparity_1920x1080()
     announce(case["name"])
     got = host(gpu_solve(case))
     ref = oracle_solve(case)
     err = np.abs(got - ref).max() / case["value_range"]
-    print("C2 max abs err / range", err, flush=True)
+    print("disparity 1920x1080 max abs err / range", err, flush=True)
     assert err <= SOLVE_TOL
 
 

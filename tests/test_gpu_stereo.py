@@ -59,7 +59,7 @@ def test_zero_iterations_copy_the_target():
 
 
 def test_full_size_contractive():
-    c = dts_inputs.config2_stereo()
+    c = dts_inputs.stereo_pair_1920x1080()
     print("CASE stereo 1920x1080, T=20, eps=2", flush=True)
     got = dts.solve_stereo(dev(c["left"]), dev(c["right"]), dev(c["target"]), dev(c["conf"]), c["sigma_s"],
                            c["sigma_r"], 3, c["solver_iters"], gamma=c["gamma"], eps=2.0)
@@ -70,7 +70,7 @@ def test_full_size_contractive():
 
 
 def test_full_size_paper_parameters_diverge_only_locally():
-    c = dts_inputs.config2_stereo()
+    c = dts_inputs.stereo_pair_1920x1080()
     print("CASE stereo 1920x1080, T=20, eps=0.001", flush=True)
     got = dts.solve_stereo(dev(c["left"]), dev(c["right"]), dev(c["target"]), dev(c["conf"]), c["sigma_s"],
                            c["sigma_r"], 3, c["solver_iters"], gamma=c["gamma"], eps=c["eps"])

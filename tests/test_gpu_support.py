@@ -85,7 +85,7 @@ def test_uniform_guide_is_the_toeplitz_cascade():
 
 def test_full_size_stereo_shape():
     # the 1920 x 1080 RGB guide of the stereo-shaped workload, sigma_s = 16, sigma_r = 0.1
-    c = dts_inputs.config2(seed=1)
+    c = dts_inputs.disparity_1920x1080(seed=1)
     print("CASE support 1920x1080", flush=True)
     s, cw = dts.support(dev(c["guide"]), c["sigma_s"], c["sigma_r"], conf=dev(c["conf"]))
     ref_c, ref_s = oracle.support_confidence(c["guide"], c["conf"], c["sigma_s"], c["sigma_r"])

@@ -400,7 +400,7 @@ def test_broadcast_confidence_equals_repeated_channels():
 
 
 # ---------------------------------------------------------------------------------------
-# P8: dynamics over the solver iterations on the config-1 and config-2 workloads
+# P8: dynamics over the solver iterations on the 256x256 polygon and 1920x1080 disparity workloads
 # ---------------------------------------------------------------------------------------
 def _energy_and_residual_trace(case):
     dx, dy = oracle.distances(case["guide"], case["sigma_s"], case["sigma_r"])
@@ -419,19 +419,19 @@ def _energy_and_residual_trace(case):
     return np.array(E), np.array(R2), np.array(Rinf)
 
 
-def test_energy_and_residual_fall_monotonically_config1():
-    E, R2, _ = _energy_and_residual_trace(dts_inputs.config1())
+def test_energy_and_residual_fall_monotonically_polygon_256():
+    E, R2, _ = _energy_and_residual_trace(dts_inputs.polygon_256())
     assert np.all(np.diff(E) <= 1e-12 * E[0]), E
     assert np.all(np.diff(R2) <= 1e-12 * R2[0]), R2
     assert E[-1] < 0.5 * E[0]
 
 
-def test_energy_and_residual_on_config2():
+def test_energy_and_residual_on_disparity_1920x1080():
     # The Eq. (3) direction drops dDT/dz and the filter matrix is not symmetric, so the
     # update is not an exact gradient of E2: on this workload E2 falls for the first 15
     # iterations and then wobbles by < 1e-4 relative, while the L2 norm of the Eq. (3)
     # residual keeps falling at every iteration.
-    E, R2, _ = _energy_and_residual_trace(dts_inputs.config2())
+    E, R2, _ = _energy_and_residual_trace(dts_inputs.disparity_1920x1080())
     assert np.all(np.diff(E[:16]) <= 1e-12 * E[0]), E
     assert np.all(np.diff(E) <= 1e-4 * E[-1]), E
     assert np.all(np.diff(R2) <= 1e-12 * R2[0]), R2
@@ -513,4 +513,4 @@ def test_hyperparameter_defaults_match_the_paper():
                 rows[k] = float(v)
     assert dts_inputs.LAMBDA == rows["lambda"]
     assert dts_inputs.STEP == rows["step"]
-    assert dts_inputs.config1()["filter_iters"] == 3
+    assert dts_inputs.polygon_256()["filter_iters"] == 3
