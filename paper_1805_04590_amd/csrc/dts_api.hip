@@ -28,7 +28,6 @@ int hip_fail(hipError_t e) {
 
 constexpr size_t kAlign = 256;
 constexpr size_t kHeaderBytes = 256;
-constexpr size_t kTicketOffset = 64;
 constexpr int kMaxFilterIters = 64;
 constexpr long long kMaxSolverIters = 1 << 20;
 
@@ -104,9 +103,6 @@ static int check_shape(int batch, int H, int W) {
     // mask lanes by pushing their offset past 2^31: keep every plane offset below 2^31
     if ((static_cast<size_t>(H) + 64) * static_cast<size_t>(W) * 4 >= (static_cast<size_t>(1) << 31))
         return DTS_ENOTSUP;
-    // every column pass launch takes one ticket per chunk: keep the counter in 32 bits
-    const double elems = static_cast<double>(batch) * H * W;
-    if (elems * DTS_MAX_CHANNELS > 9.0e15) return DTS_ENOTSUP;
     return DTS_OK;
 }
 
@@ -269,13 +265,12 @@ static int begin_call(Setup& S, void* ws, size_t ws_bytes, int batch, int H, int
     char* base = static_cast<char*>(ws);
     S.ctx.stream = static_cast<hipStream_t>(stream);
     S.ctx.status = reinterpret_cast<int*>(base);
-    S.ctx.ticket = reinterpret_cast<unsigned*>(base + kTicketOffset);
     S.ctx.carry = reinterpret_cast<unsigned long long*>(base + S.L.carry);
     S.ctx.carry_words = S.L.carry_bytes / sizeof(unsigned long long);
     S.dx = reinterpret_cast<float*>(base + S.L.dx);
     S.dy = reinterpret_cast<float*>(base + S.L.dy);
     S.tmp = with_tmp ? reinterpret_cast<float*>(base + S.L.tmp) : nullptr;
-    // status word, ticket counter and carry words start from zero on every call, so the
+    // the status word and the carry words start from zero on every call, so the
     // status read back afterwards describes the most recent call on this workspace
     int rc = launch_zero(base, kHeaderBytes, S.ctx.stream);
     if (rc) return rc;
@@ -439,7 +434,6 @@ int dts_solve_backward(const float* guide, int Cg, const float* target, const fl
     Ctx ctx;
     ctx.stream = static_cast<hipStream_t>(stream);
     ctx.status = reinterpret_cast<int*>(base);
-    ctx.ticket = reinterpret_cast<unsigned*>(base + kTicketOffset);
     ctx.carry = reinterpret_cast<unsigned long long*>(base + L.carry);
     ctx.carry_words = L.carry_bytes / sizeof(unsigned long long);
     float* dx = reinterpret_cast<float*>(base + L.dx);
@@ -891,7 +885,6 @@ int dts_col_pass(const float* src, float* dst, const float* dy, int C, int batch
     Ctx ctx;
     ctx.stream = static_cast<hipStream_t>(stream);
     ctx.status = reinterpret_cast<int*>(base);
-    ctx.ticket = reinterpret_cast<unsigned*>(base + kTicketOffset);
     ctx.carry = reinterpret_cast<unsigned long long*>(base + kHeaderBytes);
     ctx.carry_words = (need - kHeaderBytes) / sizeof(unsigned long long);
     if ((rc = launch_zero(base, need, ctx.stream))) return rc;

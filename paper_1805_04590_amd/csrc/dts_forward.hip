@@ -435,14 +435,12 @@ __global__ void copy_kernel(float* __restrict__ dst, const float* __restrict__ s
         dst[i] = src[i];
 }
 
-// Clears `bytes` bytes at any alignment: 16-byte stores over the aligned middle, byte
-// stores over the unaligned head and tail.
 // Eq. (7): c = exp(-V / (2 sigma_c^2)) with V = DT(z^2) - DT(z)^2, from the filtered
 // pairs: plane 2c of `m` holds DT(z_c), plane 2c + 1 holds DT(z_c^2).  k = -log2(e) /
 // (2 sigma_c^2).  V is used as computed (not clipped at zero).
 __global__ void __launch_bounds__(256) variance_confidence_kernel(const float* __restrict__ m,
-                                                                   float* __restrict__ conf, int C,
-                                                                   size_t plane, size_t total, float k) {
+                                                                   float* __restrict__ conf, size_t plane,
+                                                                   size_t total, float k) {
     const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
     for (size_t e = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += stride) {
         const size_t pc = e / plane;  // b * C + c
@@ -461,7 +459,7 @@ int launch_variance_confidence(const float* moments, float* conf, int C, int bat
     const size_t blocks = std::min<size_t>((total + 255) / 256, 65536);
     ProfScope prof("variance_confidence", static_cast<double>(total) * 12.0, s);
     hipLaunchKernelGGL(variance_confidence_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
-                       moments, conf, C, plane, total, static_cast<float>(k));
+                       moments, conf, plane, total, static_cast<float>(k));
     return hip_fail(hipGetLastError());
 }
 
@@ -517,6 +515,8 @@ int launch_stereo_data_grad(const float* z, const float* t, const float* c, cons
     return hip_fail(hipGetLastError());
 }
 
+// Clears `bytes` bytes at any alignment: 16-byte stores over the aligned middle, byte
+// stores over the unaligned head and tail.
 int launch_zero(void* ptr, size_t bytes, hipStream_t s) {
     if (bytes == 0) return 0;
     unsigned char* p = static_cast<unsigned char*>(ptr);

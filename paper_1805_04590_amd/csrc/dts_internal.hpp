@@ -7,17 +7,14 @@
 
 namespace dts {
 
-// Per-call launch context: the stream, the workspace header words used by the column
-// passes (device status flag, ticket counter) and the carry-word area.  The host counts
-// tickets and epochs so every column-pass launch of one call has a fresh epoch and a
-// disjoint ticket range.
+// Per-call launch context: the stream, the workspace's device status word and the
+// carry-word area of the column passes.  The host counts epochs so every column-pass
+// launch of one call tags its carry words with a fresh epoch.
 struct Ctx {
     hipStream_t stream = nullptr;
     int* status = nullptr;
-    unsigned* ticket = nullptr;
     unsigned long long* carry = nullptr;
     size_t carry_words = 0;
-    unsigned ticket_base = 0;
     unsigned epoch = 0;
 };
 
