@@ -73,6 +73,9 @@ def parse():
                     help="time the batched leg with direct launches instead of graph replays")
     ap.add_argument("--no-solve", action="store_true",
                     help="skip the single-image solve (for profiling the other legs alone)")
+    ap.add_argument("--batched-only", type=int, default=None, metavar="VARIANT",
+                    help="profiling mode: only the 64 uneven solves, batched kernel variant VARIANT, "
+                         "direct launches, no one-by-one comparison")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first fill and copy a MIB-sized float32 buffer with torch: kernels of "
                          "known traffic that calibrate the hardware byte counters")
@@ -135,7 +138,7 @@ def timed(fn, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
-def batched_leg(steps, warmup, graph=True):
+def batched_leg(steps, warmup, graph=True, variant=None, sequential=True):
     """64 uneven solves: one graph-captured persistent launch (graph=False: the launch
     made directly) against the same solves run one by one through dts_solve (workspaces
     preallocated)."""
@@ -152,9 +155,13 @@ def batched_leg(steps, warmup, graph=True):
                   conf=torch.from_numpy(c["conf"]).to(dev), sigma_s=c["sigma_s"], sigma_r=c["sigma_r"],
                   filter_iters=3, solver_iters=10) for c in cases]
     px = sum(c["target"].shape[1] * c["target"].shape[2] for c in cases)
-    bs = dts.BatchedSolver(probs)  # autotuned variant
+    bs = dts.BatchedSolver(probs, variant=variant)  # None: autotuned
     ms_b = timed(bs.capture().replay if graph else bs.run, steps, warmup)
     bs.status()
+    if not sequential:
+        return dict(workload="64 uneven solves 320-1920 x 240-1080, Cg in {1,3,8,16}, Ct 1-3, T=10",
+                    pixels=px, variant=bs.variant, launch="hip graph replay" if graph else "direct",
+                    batched_ms=round(ms_b, 3), batched_mpix_s=round(px / ms_b / 1e3, 1))
     outs = [torch.empty_like(q["target"]) for q in probs]
     wss = []
     for q in probs:
@@ -538,6 +545,11 @@ def main():
         log(f"calibration: fill and 3 copies of {4 * n} bytes")
         del a, b
         torch.cuda.empty_cache()
+    if args.batched_only is not None:
+        log("batched solves only (profiling mode) ...")
+        b = batched_leg(args.steps, args.warmup, graph=False, variant=args.batched_only, sequential=False)
+        log("  " + json.dumps(b))
+        return
     sol = None if args.no_solve else solve_leg(args, dev)
 
     extras = {}
