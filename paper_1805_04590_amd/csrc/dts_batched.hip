@@ -97,7 +97,7 @@ struct RowLds {
 template <int S>
 __device__ __forceinline__ void row_band_solo(const RowArgs& a, int y0, int y1, int wave) {
     for (int y = y0 + wave; y < y1; y += kBatchWaves)
-        row_line<S, false, true>(a, y, 0, 0, 1, true, nullptr, nullptr, nullptr);
+        row_line<S, false, true, false, true>(a, y, 0, 0, 1, true, nullptr, nullptr, nullptr);
 }
 
 // Rows [y0, y1) of one instance.  gw == 1: one wave per row (row_band_solo); otherwise
@@ -115,7 +115,7 @@ __device__ __forceinline__ void row_band(const RowArgs& ra, int y0, int y1, int 
     for (int y = y0; y < y1; y += groups) {
         const int yy = y + rg;
         const bool live = yy < y1;
-        row_line<S, false, false>(ra, live ? yy : 0, 0, gwv, gw, live, RL.fagg + rg * gw,
+        row_line<S, false, false, false, true>(ra, live ? yy : 0, 0, gwv, gw, live, RL.fagg + rg * gw,
                                   RL.bagg + rg * gw, RL.wfirst + rg * (gw + 1));
     }
 }
@@ -127,9 +127,12 @@ __device__ __forceinline__ void row_band(const RowArgs& ra, int y0, int y1, int 
 __device__ __forceinline__ void dist_band(const BInst& I, int y0, int y1) {
     const int W = I.W, Cg = I.Cg;
     const size_t plane = static_cast<size_t>(I.H) * W;
-    const float* __restrict__ guide = I.guide;
-    float* __restrict__ dx = I.dx;
-    float* __restrict__ dy = I.dy;
+    // global, not generic, accesses: the planes' addresses come from the descriptor table
+    typedef __attribute__((address_space(1))) const float gcfloat;
+    typedef __attribute__((address_space(1))) float gfloat;
+    gcfloat* __restrict__ guide = (gcfloat*)I.guide;
+    gfloat* __restrict__ dx = (gfloat*)I.dx;
+    gfloat* __restrict__ dy = (gfloat*)I.dy;
     const float s2 = I.s2;
     constexpr int kU = 4;
     for (int y = y0; y < y1; ++y) {
@@ -138,13 +141,13 @@ __device__ __forceinline__ void dist_band(const BInst& I, int y0, int y1) {
             const ptrdiff_t dl = (x > 0) ? 1 : 0;
             const ptrdiff_t du = (y > 0) ? W : 0;
             float ax = 0.f, ay = 0.f;
-            const float* g = guide + o;
+            gcfloat* g = guide + o;
             int k = 0;
             for (; k + kU <= Cg; k += kU) {
                 float v[kU], l[kU], u[kU];
 #pragma unroll
                 for (int q = 0; q < kU; ++q) {
-                    const float* gq = g + q * plane;
+                    gcfloat* gq = g + q * plane;
                     v[q] = gq[0];
                     l[q] = gq[-dl];
                     u[q] = gq[-du];

@@ -38,9 +38,8 @@ struct CarryWords {
 };
 
 template <int NCH>
-__device__ __forceinline__ unsigned long long* carry_word(const CarryCtx& a, size_t strip_base, int j,
-                                                          int k, int col) {
-    return a.carry + ((strip_base + j) * CarryWords<NCH>::kWords + k) * kWave + col;
+__device__ __forceinline__ gword* carry_word(const CarryCtx& a, size_t strip_base, int j, int k, int col) {
+    return global_word(a.carry + ((strip_base + j) * CarryWords<NCH>::kWords + k) * kWave + col);
 }
 
 // Per-wave aggregates of one chunk (written by every wave), the carries into every wave
@@ -153,8 +152,8 @@ __device__ void resolve_carry(const CarryCtx& a, ChunkLds<NCH, NWV>& L, size_t s
                 // Wait for the blocking neighbour j gently: poll only its first inclusive
                 // word and its aggregate factor, sleeping longer and longer between polls,
                 // and stage the next round trip only once one of them has been written.
-                unsigned long long* pi0 = carry_word<NCH>(a, strip_base, j, wIncl, col);
-                unsigned long long* pa0 = carry_word<NCH>(a, strip_base, j, wA, col);
+                gword* pi0 = carry_word<NCH>(a, strip_base, j, wIncl, col);
+                gword* pa0 = carry_word<NCH>(a, strip_base, j, wA, col);
                 int backoff = 1;
                 while (true) {
                     const unsigned long long u =

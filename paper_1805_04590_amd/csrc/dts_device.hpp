@@ -134,15 +134,21 @@ __device__ __forceinline__ void scan_down_dpp(float& a, float& b, int lane) {
 // Carry words: a float value tagged with the epoch of the launch that wrote it, stored
 // and loaded as one 64-bit device-scope atomic so a reader never sees a value without its
 // tag.  Words from older launches carry older epochs and read as "not yet written".
-__device__ __forceinline__ void publish(unsigned long long* p, unsigned epoch, float v) {
+// They are addressed as global memory explicitly: a kernel that takes the carry area's
+// address from a table in memory would otherwise access them as generic (flat) memory,
+// and every later LDS wait of the workgroup would also wait for those accesses.
+typedef __attribute__((address_space(1))) unsigned long long gword;
+
+__device__ __forceinline__ gword* global_word(unsigned long long* p) { return (gword*)p; }
+
+__device__ __forceinline__ void publish(gword* p, unsigned epoch, float v) {
     const unsigned long long word =
         (static_cast<unsigned long long>(epoch) << 32) | __float_as_uint(v);
     __hip_atomic_store(p, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ bool peek(const unsigned long long* p, unsigned epoch, float& v) {
-    const unsigned long long word = __hip_atomic_load(
-        const_cast<unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ bool peek(gword* p, unsigned epoch, float& v) {
+    const unsigned long long word = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     v = __uint_as_float(static_cast<unsigned>(word));
     return static_cast<unsigned>(word >> 32) == epoch;
 }
@@ -191,6 +197,54 @@ __device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, unsigned voff, 
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff,
                                        float v) {
     __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 0);
+}
+
+// S consecutive floats of a row through a buffer resource over the whole plane: lane
+// elements [n0, n0 + S) of the row at byte offset `row` (elements at or past `n` read 0
+// and are not written).  `vec`: the row is 16-byte aligned and n is a multiple of 4, so
+// every 4-float piece is wholly inside or wholly past the row end and moves as one
+// 128-bit access; otherwise element by element.  Buffer accesses count on the vector
+// memory counter only, so waiting for them never waits on LDS or scalar traffic (and
+// the reverse), unlike generic (flat) accesses through pointers loaded from memory.
+template <int S>
+__device__ __forceinline__ void bload_seg(__amdgpu_buffer_rsrc_t r, unsigned row, int n0, int n, bool vec,
+                                          float (&v)[S]) {
+    if (vec) {
+#pragma unroll
+        for (int e = 0; e < S; e += 4) {
+            const unsigned o = (n0 + e < n) ? row + static_cast<unsigned>(n0 + e) * 4u : kInvalidOffset;
+            const auto q = __builtin_amdgcn_raw_buffer_load_b128(r, o, 0, 0);
+            v[e] = __uint_as_float(q[0]);
+            v[e + 1] = __uint_as_float(q[1]);
+            v[e + 2] = __uint_as_float(q[2]);
+            v[e + 3] = __uint_as_float(q[3]);
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < S; ++e)
+            v[e] = bload(r, (n0 + e < n) ? row + static_cast<unsigned>(n0 + e) * 4u : kInvalidOffset, 0);
+    }
+}
+
+template <int S>
+__device__ __forceinline__ void bstore_seg(__amdgpu_buffer_rsrc_t r, unsigned row, int n0, int n, bool vec,
+                                           const float (&v)[S]) {
+    if (vec) {
+#pragma unroll
+        for (int e = 0; e < S; e += 4) {
+            const unsigned o = (n0 + e < n) ? row + static_cast<unsigned>(n0 + e) * 4u : kInvalidOffset;
+            __amdgpu_buffer_rsrc_t rr = r;
+            const uint32_t q0 = __float_as_uint(v[e]), q1 = __float_as_uint(v[e + 1]);
+            const uint32_t q2 = __float_as_uint(v[e + 2]), q3 = __float_as_uint(v[e + 3]);
+            typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+            const u32x4 q = {q0, q1, q2, q3};
+            __builtin_amdgcn_raw_buffer_store_b128(q, rr, o, 0, 0);
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < S; ++e)
+            bstore(r, (n0 + e < n) ? row + static_cast<unsigned>(n0 + e) * 4u : kInvalidOffset, 0, v[e]);
+    }
 }
 
 // Scalar add the compiler cannot fold away, so a row offset advances as one running SGPR

@@ -115,7 +115,11 @@ __device__ __forceinline__ void row_filter_solo(const float (&w)[S], float wlast
 // SOLO: the row belongs to one wave alone (nw = 1): no LDS, no barrier, and the waves of
 // a workgroup may call it independently.  SQ: src holds C / 2 channels and output channel
 // c filters src channel c / 2, squared when c is odd (the pairs z, z^2 of Eq. (7)).
-template <int S, bool DIST, bool SOLO = false, bool SQ = false>
+// BUF: the distances and the signal move through buffer resources (bload_seg /
+// bstore_seg), for callers whose pointers come from memory: accessed through them
+// directly they compile to generic (flat) accesses, which every LDS wait of the scans
+// would also wait for.
+template <int S, bool DIST, bool SOLO = false, bool SQ = false, bool BUF = false>
 __device__ __forceinline__ void row_line(const RowArgs& a, int y, int b, int wave, int nw, bool live,
                                          float2* fagg, float2* bagg, float* wfirst) {
     const int lane = lane_id();
@@ -162,9 +166,14 @@ __device__ __forceinline__ void row_line(const RowArgs& a, int y, int b, int wav
             w[e] = (n > 0 && n < We) ? weight(ax[e], a.log2a) : 0.f;
         }
     } else {
-        const float* dr = a.d + static_cast<size_t>(b) * plane + static_cast<size_t>(y) * W;
         float dv[S];
-        load_seg<S>(dr, n0, We, vec, 1.f, dv);
+        if constexpr (BUF) {
+            bload_seg<S>(plane_rsrc(a.d + static_cast<size_t>(b) * plane, plane * sizeof(float)),
+                         static_cast<unsigned>(y) * static_cast<unsigned>(W) * 4u, n0, We, vec, dv);
+        } else {
+            const float* dr = a.d + static_cast<size_t>(b) * plane + static_cast<size_t>(y) * W;
+            load_seg<S>(dr, n0, We, vec, 1.f, dv);
+        }
 #pragma unroll
         for (int e = 0; e < S; ++e) {
             const int n = n0 + e;
@@ -188,7 +197,11 @@ __device__ __forceinline__ void row_line(const RowArgs& a, int y, int b, int wav
         const size_t soff =
             (static_cast<size_t>(b) * cin + (SQ ? c >> 1 : c)) * plane + static_cast<size_t>(y) * W;
         float f[S];
-        load_seg<S>(a.src + soff, n0, We, vec, 0.f, f);
+        if constexpr (BUF)
+            bload_seg<S>(plane_rsrc(a.src + (soff - static_cast<size_t>(y) * W), plane * sizeof(float)),
+                         static_cast<unsigned>(y) * static_cast<unsigned>(W) * 4u, n0, We, vec, f);
+        else
+            load_seg<S>(a.src + soff, n0, We, vec, 0.f, f);
         if (SQ && (c & 1)) {
 #pragma unroll
             for (int e = 0; e < S; ++e) f[e] *= f[e];
@@ -247,7 +260,11 @@ __device__ __forceinline__ void row_line(const RowArgs& a, int y, int b, int wav
             k = fmaf(wn, k - f[e], f[e]);
             f[e] = k;
         }
-        store_seg<S>(a.dst + roff, n0, We, vec, f);
+        if constexpr (BUF)
+            bstore_seg<S>(plane_rsrc(a.dst + (roff - static_cast<size_t>(y) * W), plane * sizeof(float)),
+                          static_cast<unsigned>(y) * static_cast<unsigned>(W) * 4u, n0, We, vec, f);
+        else
+            store_seg<S>(a.dst + roff, n0, We, vec, f);
     }
 }
 
