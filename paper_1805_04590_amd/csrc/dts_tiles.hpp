@@ -122,12 +122,24 @@ __device__ __forceinline__ void row_filter_solo(const float (&w)[S], float wlast
 template <int S, bool DIST, bool SOLO = false, bool SQ = false, bool BUF = false>
 __device__ __forceinline__ void row_line(const RowArgs& a, int y, int b, int wave, int nw, bool live,
                                          float2* fagg, float2* bagg, float* wfirst) {
+    static_assert(!(DIST && BUF), "the buffer path serves plain row passes only");
     const int lane = lane_id();
     const int H = a.H, W = a.W;
     const int We = live ? W : 0;  // pixels of the row this group touches
     const size_t plane = static_cast<size_t>(H) * W;
     const int n0 = (wave * kWave + lane) * S;
     const bool vec = (W & 3) == 0;
+
+    // BUF: each channel's row is loaded one channel ahead (channel 0 with the distances),
+    // so its loads are in flight while the previous channel is scanned: a row then costs
+    // about one memory round trip instead of one per channel plus one for the distances.
+    const int cin = SQ ? a.C >> 1 : a.C;
+    [[maybe_unused]] const unsigned rowoff = static_cast<unsigned>(y) * static_cast<unsigned>(W) * 4u;
+    [[maybe_unused]] const auto load_ch = [&](int c, float (&v)[S]) {
+        const size_t pl = static_cast<size_t>(b) * cin + (SQ ? c >> 1 : c);
+        bload_seg<S>(plane_rsrc(a.src + pl * plane, plane * sizeof(float)), rowoff, n0, We, vec, v);
+    };
+    float f[S];
 
     float w[S];
     if constexpr (DIST) {
@@ -168,8 +180,9 @@ __device__ __forceinline__ void row_line(const RowArgs& a, int y, int b, int wav
     } else {
         float dv[S];
         if constexpr (BUF) {
-            bload_seg<S>(plane_rsrc(a.d + static_cast<size_t>(b) * plane, plane * sizeof(float)),
-                         static_cast<unsigned>(y) * static_cast<unsigned>(W) * 4u, n0, We, vec, dv);
+            bload_seg<S>(plane_rsrc(a.d + static_cast<size_t>(b) * plane, plane * sizeof(float)), rowoff, n0,
+                         We, vec, dv);
+            if (a.C > 0) load_ch(0, f);
         } else {
             const float* dr = a.d + static_cast<size_t>(b) * plane + static_cast<size_t>(y) * W;
             load_seg<S>(dr, n0, We, vec, 1.f, dv);
@@ -191,17 +204,16 @@ __device__ __forceinline__ void row_line(const RowArgs& a, int y, int b, int wav
         if (lane == kWave - 1) wlast = wfirst[wave + 1];
     }
 
-    const int cin = SQ ? a.C >> 1 : a.C;
     for (int c = 0; c < a.C; ++c) {
         const size_t roff = (static_cast<size_t>(b) * a.C + c) * plane + static_cast<size_t>(y) * W;
-        const size_t soff =
-            (static_cast<size_t>(b) * cin + (SQ ? c >> 1 : c)) * plane + static_cast<size_t>(y) * W;
-        float f[S];
-        if constexpr (BUF)
-            bload_seg<S>(plane_rsrc(a.src + (soff - static_cast<size_t>(y) * W), plane * sizeof(float)),
-                         static_cast<unsigned>(y) * static_cast<unsigned>(W) * 4u, n0, We, vec, f);
-        else
+        [[maybe_unused]] float fn[S];
+        if constexpr (BUF) {
+            if (c + 1 < a.C) load_ch(c + 1, fn);
+        } else {
+            const size_t soff =
+                (static_cast<size_t>(b) * cin + (SQ ? c >> 1 : c)) * plane + static_cast<size_t>(y) * W;
             load_seg<S>(a.src + soff, n0, We, vec, 0.f, f);
+        }
         if (SQ && (c & 1)) {
 #pragma unroll
             for (int e = 0; e < S; ++e) f[e] *= f[e];
@@ -260,11 +272,16 @@ __device__ __forceinline__ void row_line(const RowArgs& a, int y, int b, int wav
             k = fmaf(wn, k - f[e], f[e]);
             f[e] = k;
         }
-        if constexpr (BUF)
-            bstore_seg<S>(plane_rsrc(a.dst + (roff - static_cast<size_t>(y) * W), plane * sizeof(float)),
-                          static_cast<unsigned>(y) * static_cast<unsigned>(W) * 4u, n0, We, vec, f);
-        else
+        if constexpr (BUF) {
+            bstore_seg<S>(plane_rsrc(a.dst + (roff - static_cast<size_t>(y) * W), plane * sizeof(float)), rowoff,
+                          n0, We, vec, f);
+            if (c + 1 < a.C) {
+#pragma unroll
+                for (int e = 0; e < S; ++e) f[e] = fn[e];
+            }
+        } else {
             store_seg<S>(a.dst + roff, n0, We, vec, f);
+        }
     }
 }
 
