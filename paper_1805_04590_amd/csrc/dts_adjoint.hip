@@ -480,15 +480,20 @@ static int col_adj_capacity() {
     return cached[dev];
 }
 
-// target channels per group, rows per wave, waves per workgroup
+// target channels per group, rows per wave, waves per workgroup.  One channel per
+// group: a group of two needs 185 VGPRs, i.e. one 8-wave workgroup per CU, against 124
+// and two per CU for one channel; the extra distance and gradient reads of the smaller
+// groups cost less than the lost occupancy (8 x 1024^2, 3 channels, T = 15: forward +
+// backward 20.61 ms with groups of two, 19.95 ms with groups of one).
+constexpr int kAdjGroupChannels = 1;
 constexpr int kAdjRowsPerWave = 16;
 constexpr int kAdjWaves = 8;
 constexpr int kAdjChunkRows = kAdjRowsPerWave * kAdjWaves;
 
-int col_adjoint_groups(int C) { return (C + 1) / 2; }  // at most 2 target channels per group
+int col_adjoint_groups(int C) { return (C + kAdjGroupChannels - 1) / kAdjGroupChannels; }
 
 size_t col_adjoint_carry_words(int batch, int H, int W, int C) {
-    const int cta = C >= 2 ? 2 : 1;
+    const int cta = kAdjGroupChannels;
     const size_t G = (H + kAdjChunkRows - 1) / kAdjChunkRows;
     const size_t S = (W + kWave - 1) / kWave;
     const size_t NG = (C + cta - 1) / cta;
@@ -523,7 +528,7 @@ int launch_col_adjoint(const ColAdj& p, Ctx& ctx) {
     a.batch = p.batch;
     a.log2a = p.log2a;
     a.ln_a = p.log2a * 0.69314718055994530942f;
-    const int cta = p.C >= 2 ? 2 : 1;
+    const int cta = kAdjGroupChannels;
     a.G = (p.H + kAdjChunkRows - 1) / kAdjChunkRows;
     a.S = (p.W + kWave - 1) / kWave;
     a.NG = (p.C + cta - 1) / cta;
@@ -532,7 +537,7 @@ int launch_col_adjoint(const ColAdj& p, Ctx& ctx) {
     a.status = ctx.status;
     const double px = static_cast<double>(p.batch) * p.H * p.W;
     const double bytes = px * 4.0 * (3.0 * p.C + 1.0 + (p.gd ? 2.0 : 0.0));
-    return cta == 2 ? launch_col_adj_t<2>(a, ctx.stream, bytes) : launch_col_adj_t<1>(a, ctx.stream, bytes);
+    return launch_col_adj_t<kAdjGroupChannels>(a, ctx.stream, bytes);
 }
 
 // ---------------------------------------------------------------------------------------
