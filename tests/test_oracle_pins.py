@@ -407,13 +407,12 @@ def _energy_and_residual_trace(case):
     _, its = oracle.solve(case["guide"], case["target"], case["conf"], case["sigma_s"],
                           case["sigma_r"], case["filter_iters"], case["solver_iters"],
                           case["lam"], case["step"], return_iterates=True, dists=(dx, dy))
-    t = case["target"].astype(np.float64)
-    c = case["conf"].astype(np.float64)
     E, R2, Rinf = [], [], []
     for z in its:
-        zbar = oracle.dt_filter(z, dx, dy, case["sigma_s"], case["filter_iters"])
-        E.append(0.5 * case["lam"] * np.sum((z - zbar) ** 2) + 0.5 * np.sum(c * (z - t) ** 2))
-        r = case["lam"] * (z - zbar) + c * (z - t)
+        E.append(oracle.energy_e2(z, case["target"], case["conf"], dx, dy, case["sigma_s"],
+                                  case["filter_iters"], case["lam"]))
+        r = oracle.residual(z, case["target"], case["conf"], dx, dy, case["sigma_s"],
+                            case["filter_iters"], case["lam"])
         R2.append(np.sqrt(np.sum(r * r)))
         Rinf.append(np.abs(r).max())
     return np.array(E), np.array(R2), np.array(Rinf)
@@ -438,17 +437,81 @@ def test_energy_and_residual_on_disparity_1920x1080():
     assert E[-1] < 0.1 * E[0]
 
 
-def test_energy_helpers_agree_with_trace():
-    case = dts_inputs.random_case(3, 20, 24, 3, 2)
-    dx, dy = oracle.distances(case["guide"], case["sigma_s"], case["sigma_r"])
-    z = case["target"].astype(np.float64) * 0.9
-    e = oracle.energy_e2(z, case["target"], case["conf"], dx, dy, case["sigma_s"])
-    zbar = oracle.dt_filter(z, dx, dy, case["sigma_s"], 3)
-    manual = 0.99 / 2 * np.sum((z - zbar) ** 2) + 0.5 * np.sum(
-        case["conf"] * (z - case["target"]) ** 2)
-    assert abs(e - manual) < 1e-12 * manual
-    r = oracle.residual(z, case["target"], case["conf"], dx, dy, case["sigma_s"])
-    assert r.shape == z.shape
+# The two diagnostics of reading R6, pinned to the explicitly summed filter matrix (built
+# above from pure-Python pass matrices, independently of the oracle's filter) and to
+# each other.  With A that matrix and C = diag(c):
+#   E2(z) = lam/2 |(I - A) z|^2 + 1/2 (z - t)^T C (z - t),
+#   grad E2 = lam (I - A)^T (I - A) z + C (z - t),
+#   residual(z) = lam (I - A) z + C (z - t)  (the Eq. (3) direction: grad E2 with DT(z)
+#   held fixed), so grad E2 = residual - lam A^T (I - A) z.
+def _energy_case(seed, H=4, W=5):
+    g, t, c = _tiny(seed, H=H, W=W)
+    s_s, s_r = 3.0, 0.3
+    dx, dy = oracle.distances(g, s_s, s_r)
+    A = explicit_dt_matrix(dx, dy, oracle.feedback_coefficients(s_s, 3))
+    z = np.random.default_rng(seed + 1000).uniform(size=t.shape)
+    return g, t, c, dx, dy, s_s, A, z
+
+
+def test_energy_e2_matches_dense_closed_form():
+    _, t, c, dx, dy, s_s, A, z = _energy_case(71)
+    lam = 0.99
+    n = A.shape[0]
+    v = (np.eye(n) - A) @ z.ravel()
+    d = (z - t).ravel()
+    closed = 0.5 * lam * float(v @ v) + 0.5 * float(d @ (c.ravel() * d))
+    e = oracle.energy_e2(z, t, c, dx, dy, s_s, 3, lam)
+    assert abs(e - closed) <= 1e-13 * closed, (e, closed)
+
+
+def test_residual_matches_dense_closed_form():
+    _, t, c, dx, dy, s_s, A, z = _energy_case(72)
+    lam = 0.99
+    n = A.shape[0]
+    closed = lam * (np.eye(n) - A) @ z.ravel() + c.ravel() * (z - t).ravel()
+    r = oracle.residual(z, t, c, dx, dy, s_s, 3, lam)
+    np.testing.assert_allclose(r.ravel(), closed, atol=1e-14)
+
+
+def test_energy_gradient_is_residual_plus_the_frozen_filter_term():
+    # Central differences of E2 (a quadratic, so exact up to rounding) against the
+    # residual: they differ exactly by the derivative of DT(z), which the Eq. (3)
+    # direction leaves out.  A lam/2-for-lam slip in E2, a sign in either function or a
+    # transposed A fails this.
+    _, t, c, dx, dy, s_s, A, z = _energy_case(73)
+    lam = 0.99
+    n = A.shape[0]
+    r = oracle.residual(z, t, c, dx, dy, s_s, 3, lam).ravel()
+    frozen_term = lam * A.T @ ((np.eye(n) - A) @ z.ravel())
+    h = 1e-4
+    for j in range(n):
+        zp, zm = z.copy(), z.copy()
+        zp.flat[j] += h
+        zm.flat[j] -= h
+        fd = (oracle.energy_e2(zp, t, c, dx, dy, s_s, 3, lam)
+              - oracle.energy_e2(zm, t, c, dx, dy, s_s, 3, lam)) / (2 * h)
+        assert abs(fd - (r[j] - frozen_term[j])) <= 1e-9, (j, fd, r[j] - frozen_term[j])
+
+
+def test_residual_vanishes_at_the_eq4_solution_and_drives_one_step():
+    # Eq. (4): at the solution of (lam (I - A) + C) z = C t the Eq. (3) direction is zero;
+    # and one descent step from the target is t - step * residual(t).
+    g, t, c, dx, dy, s_s, A, _ = _energy_case(74)
+    lam, step = 0.99, 0.99
+    n = A.shape[0]
+    zstar = np.linalg.solve(lam * (np.eye(n) - A) + np.diag(c.ravel()), c.ravel() * t.ravel())
+    r = oracle.residual(zstar.reshape(t.shape), t, c, dx, dy, s_s, 3, lam)
+    assert np.abs(r).max() <= 1e-13
+    assert np.abs(oracle.residual(t, t, c, dx, dy, s_s, 3, lam)).max() > 1e-3
+    z1 = oracle.solve(g, t, c, s_s, 0.3, 3, 1, lam, step)
+    np.testing.assert_allclose(z1, t - step * oracle.residual(t, t, c, dx, dy, s_s, 3, lam), atol=1e-15)
+
+
+def test_energy_is_zero_at_a_constant_fixed_point():
+    g, _, c, dx, dy, s_s, _, _ = _energy_case(75)
+    t = np.full((1,) + dx.shape, 0.42)
+    assert oracle.energy_e2(t, t, c, dx, dy, s_s, 3) <= 1e-28
+    assert np.abs(oracle.residual(t, t, c, dx, dy, s_s, 3)).max() <= 1e-15
 
 
 # ---------------------------------------------------------------------------------------
