@@ -269,6 +269,11 @@ int dts_col_variant_count(void);
 int dts_col_variant_info(int variant, int* group_channels, int* rows_per_wave, int* waves);
 /* Pin `variant` for channel groups of `group_channels` (1..4); -1 restores the default. */
 int dts_tune_col_variant(int group_channels, int variant);
+/* on != 0 (the default): the persistent column passes keep all chunks of a strip on one
+ * XCD (workgroups are dealt to the 8 XCDs in turn), so the carry words a chunk waits for
+ * are written from its own XCD; 0: chunk p % G of strip group p / G.  Results agree to
+ * fp32 rounding. */
+int dts_tune_col_xcd(int on);
 /* Pixels per lane of the row pass: 4, 8 or 16; 0 restores the default, which depends on
  * the row width.  Rows whose width needs more than 16 waves at this setting fall back to
  * the default. */

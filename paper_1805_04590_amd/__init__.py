@@ -44,6 +44,7 @@ __all__ = [
     "col_variants",
     "tune_col_variant",
     "tune_row_segment",
+    "tune_col_xcd",
     "batched_variants",
     "BatchedSolver",
     "SolveGraph",
@@ -90,6 +91,7 @@ EXPORTED_SYMBOLS = (
     "dts_col_variant_info",
     "dts_tune_col_variant",
     "dts_tune_row_segment",
+    "dts_tune_col_xcd",
     "dts_batched_variant_count",
     "dts_batched_variant_info",
     "dts_batched_workspace_bytes",
@@ -242,6 +244,8 @@ def library():
     lib.dts_tune_col_variant.restype = i
     lib.dts_tune_row_segment.argtypes = [i]
     lib.dts_tune_row_segment.restype = i
+    lib.dts_tune_col_xcd.argtypes = [i]
+    lib.dts_tune_col_xcd.restype = i
     PP = ctypes.POINTER(_Problem)
     BP = ctypes.POINTER(_BatchedPlan)
     lib.dts_batched_variant_count.argtypes = []
@@ -393,6 +397,11 @@ def tune_col_variant(group_channels, variant):
 
 def tune_row_segment(pixels_per_lane):
     _check(library().dts_tune_row_segment(int(pixels_per_lane)), "dts_tune_row_segment")
+
+
+def tune_col_xcd(on):
+    """Keep every column strip's chunks on one XCD (default) or deal them round-robin."""
+    _check(library().dts_tune_col_xcd(1 if on else 0), "dts_tune_col_xcd")
 
 
 def batched_variants():

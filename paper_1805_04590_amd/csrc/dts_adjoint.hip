@@ -300,7 +300,7 @@ struct ColAdjArgs {
     float* gd;        // dL/d(dy) accumulator, one plane set per channel group, or null
     int C, H, W, batch;
     float log2a, ln_a;
-    int G, S, NG, groups;
+    int G, S, NG, groups, xcd;
     unsigned long long* carry;
     unsigned epoch;
     int* status;
@@ -311,8 +311,10 @@ __global__ void __launch_bounds__(kWave * NWV) col_adjoint_kernel(ColAdjArgs a) 
     constexpr int NCH = 2 * CTA;
     __shared__ ChunkLds<NCH, NWV> L;
     const CarryCtx cctx{a.carry, a.epoch, a.status, a.G, a.S, a.NG};
-    const int chunk = static_cast<int>(blockIdx.x % a.G);
-    const int group = static_cast<int>(blockIdx.x / a.G);
+    const ChunkSlot slot = chunk_slot(static_cast<int>(blockIdx.x), a.G, a.xcd);
+    const int chunk = slot.chunk;
+    const int group = slot.group;
+    if (group >= a.groups) return;
     const int n_strips = a.batch * a.NG * a.S;
 #pragma unroll 1
     for (int sid = group; sid < n_strips; sid += a.groups) {
@@ -505,9 +507,10 @@ static int launch_col_adj_t(ColAdjArgs a, hipStream_t s, double bytes) {
     const int cap = col_adj_capacity<CTA, kAdjRowsPerWave, kAdjWaves>();
     if (cap <= 0) return hip_fail(hipErrorNoDevice);
     if (a.G > cap) return DTS_ENOTSUP;
-    const long long n_strips = static_cast<long long>(a.batch) * a.NG * a.S;
-    a.groups = static_cast<int>(std::min<long long>(cap / a.G, n_strips));
-    const unsigned n = static_cast<unsigned>(a.groups) * a.G;
+    const ColGrid grid = col_grid(cap, a.G, static_cast<long long>(a.batch) * a.NG * a.S);
+    a.groups = grid.groups;
+    a.xcd = grid.xcd;
+    const unsigned n = grid.n;
     ProfScope prof("col_adjoint", bytes, s);
     hipLaunchKernelGGL((col_adjoint_kernel<CTA, kAdjRowsPerWave, kAdjWaves>), dim3(n),
                        dim3(kWave * kAdjWaves), 0, s, a);

@@ -912,6 +912,8 @@ int dts_tune_col_variant(int group_channels, int variant) {
     return tune_col_variant(group_channels, variant);
 }
 
+int dts_tune_col_xcd(int on) { return tune_col_xcd(on); }
+
 int dts_tune_row_segment(int pixels_per_lane) { return tune_row_segment(pixels_per_lane); }
 
 int dts_workspace_status(void* workspace, void* stream) {

@@ -8,11 +8,22 @@
 //   backward Y[n] = w[n+1] Y[n+1] + (1 - w[n+1]) X[n]
 // After a chunk has run both recurrences with zero carries it knows, per channel,
 //   X[end]   = A X_in + B,      Y[first] = BJ + BQ X_in + P Y_in,
-// where X_in is X at the row above the chunk and Y_in is Y at the row below it.  The
-// chunks of a strip exchange these through tagged 64-bit words in device memory: first a
-// look-back resolves X_in from earlier chunks, then a look-ahead resolves Y_in from later
-// chunks; every wave of the workgroup reads one neighbour per round trip.  Within a
-// workgroup the same algebra composes the waves through LDS.
+// where X_in is X at the row above the chunk and Y_in is Y at the row below it, A the
+// product of the chunk's weights and P the product of the weights that link its rows to
+// the row below.  Each chunk publishes these five aggregates as soon as its own rows are
+// scanned, and then resolves both carries from its neighbours' aggregates alone:
+//   X_in(k) = B(k-1) + A(k-1) (B(k-2) + A(k-2) (...)),
+//   Y_in(k) = sum_{j>k} [prod_{k<m<j} P(m)] (BJ(j) + BQ(j) X_in(j)),
+// with X_in(j) carried forward from X_in(k + 1) = A(k) X_in(k) + B(k).  No chunk waits
+// for another chunk's carries, only for its aggregates.
+//
+// Every weight is a^d with a < 1 and d >= 1 (Eq. (8)-(9)), so a carry fades by at least a
+// factor a per row.  A walk stops once the product of the factors still to be applied
+// falls below 2^-40: what it leaves out is below 2^-40 of the largest magnitude on the
+// line, far under one fp32 rounding of the result.  Where the product does not fall that
+// far, the walk runs to the first or last chunk and is exact.  Which neighbours a chunk
+// composes, and in which order, depends on the data only, so a given launch shape gives
+// bitwise-identical results on every run.
 #pragma once
 
 #include "dts_device.hpp"
@@ -28,139 +39,261 @@ struct CarryCtx {
 
 template <int NCH>
 struct CarryWords {
-    static constexpr int kFwdA = 0;                  // product of the chunk's weights
-    static constexpr int kFwdB = 1;                  // + c: forward output, zero carry-in
-    static constexpr int kFwdIncl = 1 + NCH;         // + c: forward output at the chunk end
-    static constexpr int kBwdP = 1 + 2 * NCH;        // backward carry factor
-    static constexpr int kBwdAlpha = 2 + 2 * NCH;    // + c: backward output, zero carry-in
-    static constexpr int kBwdIncl = 2 + 3 * NCH;     // + c: backward output at chunk start
-    static constexpr int kWords = 2 + 4 * NCH;
+    static constexpr int kA = 0;            // product of the chunk's weights
+    static constexpr int kB = 1;            // + c: forward output at the chunk end, zero carry-in
+    static constexpr int kP = 1 + NCH;      // backward carry factor
+    static constexpr int kBQ = 2 + NCH;     // backward output's factor on the forward carry-in
+    static constexpr int kBJ = 3 + NCH;     // + c: backward output at the chunk start, zero carries
+    static constexpr int kWords = 3 + 2 * NCH;
 };
+
+// A walk stops once the product of the factors still to be applied is below this.
+constexpr float kCarryNegligible = 0x1p-40f;
 
 template <int NCH>
 __device__ __forceinline__ gword* carry_word(const CarryCtx& a, size_t strip_base, int j, int k, int col) {
     return global_word(a.carry + ((strip_base + j) * CarryWords<NCH>::kWords + k) * kWave + col);
 }
 
-// Per-wave aggregates of one chunk (written by every wave), the carries into every wave
-// (written by wave 0 after the exchange), one column per lane, and the staging area of
-// the look-back / look-ahead: in each round trip wave v reads the words of the v-th
-// neighbour still to be composed and leaves here what it found.
+// Per-wave aggregates of one chunk (written by every wave), and, in a union, the staging
+// area of the exchange and the carries into every wave (written by wave 0 once the
+// exchange is over), one column per lane.  In each round trip of the exchange, wave v of
+// the first half stages the aggregates of the v-th earlier neighbour still to be
+// composed, and wave NWV/2 + v those of the v-th later one.
 template <int NCH, int NWV>
 struct ChunkLds {
     float A[NWV][kWave], P[NWV][kWave], BQ[NWV][kWave];
     float B[NWV][NCH][kWave], BJ[NWV][NCH][kWave];
-    float Jin[NWV][NCH][kWave];
-    union {                      // Kin is written only once both walks are over
-        float Kin[NWV][NCH][kWave];
-        float nV[NWV][NCH][kWave];  // neighbour's inclusive value if nS == 2, else its aggregate offset
+    union {
+        struct {
+            float Jin[NWV][NCH][kWave];
+            float Kin[NWV][NCH][kWave];
+        };
+        struct {
+            float A[NWV][kWave], P[NWV][kWave], BQ[NWV][kWave];
+            float B[NWV][NCH][kWave], BJ[NWV][NCH][kWave];
+            int ok[NWV][kWave];   // the staged neighbour's words were all written
+        } n;
     };
-    float nA[NWV][kWave];        // neighbour's aggregate factor
-    int nS[NWV][kWave];          // 2 inclusive written, 1 aggregate written, 0 neither yet
-    int nJ[kWave];               // per lane: the next neighbour to read, or kWalkDone
-    int more;                    // some lane of wave 0 is still walking
+    // State of the two walks per lane, kept here between round trips so that it holds no
+    // registers while the staging loads are in flight (see chunk_carries).
+    float FA[kWave], PA[kWave], V[kWave], GXa[kWave];
+    float FB[NCH][kWave], U[NCH][kWave], GXb[NCH][kWave];
+    int fj[kWave], bj[kWave];     // per lane: next neighbour of each walk, or kWalkDone
+    int more;                     // some lane of wave 0 is still walking
 };
 
 constexpr int kWalkDone = -0x40000000;
 
-// Resolve one chunk's carry from its neighbours, one column per lane, with all NWV waves
-// of the workgroup (every wave must call it; the result is valid in wave 0).  Going away
-// from the chunk (towards chunk 0 for the forward carry, towards the last chunk for the
-// backward one), each neighbour j contributes either its inclusive value (which ends the
-// walk) or its affine aggregate x -> A x + B (composed in, walk on).  One round trip reads
-// NWV neighbours, one per wave, and wave 0 composes them in order.  Lanes with `live`
-// false (columns past the right edge) take no part.
+// True when all `ncv` tagged words of channel block k carry the launch's epoch.
+template <int NCH>
+__device__ __forceinline__ bool tags_ok(const unsigned long long (&w)[NCH], int ncv, unsigned ep) {
+    bool ok = true;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+        if (c < ncv) ok = ok && static_cast<unsigned>(w[c] >> 32) == ep;
+    return ok;
+}
+
+__device__ __forceinline__ unsigned long long load_word(gword* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ float word_value(unsigned long long w) {
+    return __uint_as_float(static_cast<unsigned>(w));
+}
+
+// All waves of a chunk's workgroup: wave 0 composes the waves into the chunk aggregates
+// and publishes them; all waves stage neighbours' aggregates; wave 0 resolves the carries
+// and writes every wave's carry-in X_in (L.Jin) and Y_in (L.Kin).  `ncv` channels are
+// valid; `valid` is false for lanes past the right edge of the image.
 template <int NCH, int NWV>
-__device__ void resolve_carry(const CarryCtx& a, ChunkLds<NCH, NWV>& L, size_t strip_base, int col,
-                              int wave, int chunk, int dir, int wA, int wB, int wIncl, int ncv,
-                              bool live, float (&carry)[NCH]) {
+__device__ void chunk_carries(const CarryCtx& a, ChunkLds<NCH, NWV>& L, int b, int grp, int strip,
+                              int chunk, int lane, int wave, bool valid, int ncv) {
+    static_assert(NWV >= 2 && NWV % 2 == 0, "the exchange splits the waves in two halves");
+    using CW = CarryWords<NCH>;
+    constexpr int NH = NWV / 2;
+    const size_t strip_base =
+        ((static_cast<size_t>(b) * a.NG + grp) * a.S + strip) * static_cast<size_t>(a.G);
     const unsigned ep = a.epoch;
     const int G = a.G;
-    float GA = 1.f, GB[NCH];
+
+    // chunk aggregates: wave 0 composes the waves top to bottom and leaves them in the
+    // staging area (free until the exchange starts); then every wave publishes some of
+    // the words, so no wave holds them all in registers
+    if (wave == 0) {
+        float CA = 1.f, CP = 1.f, CBQ = 0.f, CB[NCH], CBJ[NCH];
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) GB[c] = carry[c] = 0.f;
-    int j = chunk + dir;           // wave 0: next neighbour of this lane
-    bool done = !live;
+        for (int c = 0; c < NCH; ++c) CB[c] = CBJ[c] = 0.f;
+#pragma unroll
+        for (int v = 0; v < NWV; ++v) {
+            // wave v's forward carry-in is CA X_in + CB (before wave v is composed in)
+            const float BQv = L.BQ[v][lane];
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) CBJ[c] = fmaf(CP, fmaf(BQv, CB[c], L.BJ[v][c][lane]), CBJ[c]);
+            CBQ = fmaf(CP, BQv * CA, CBQ);
+            CP *= L.P[v][lane];
+            const float Av = L.A[v][lane];
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) CB[c] = fmaf(Av, CB[c], L.B[v][c][lane]);
+            CA *= Av;
+        }
+        L.n.A[0][lane] = CA;
+        L.n.P[0][lane] = CP;
+        L.n.BQ[0][lane] = CBQ;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            L.n.B[0][c][lane] = CB[c];
+            L.n.BJ[0][c][lane] = CBJ[c];
+        }
+    }
+
+    // the exchange.  Forward walk: X_in = FB + FA * (rest).  Backward walk:
+    // Y_in = U + V X_in(k + 1) + PA * (rest), with X_in(j) = GXa X_in(k + 1) + GXb for the
+    // next neighbour j.  Wave 0 owns the walks; their state lives in LDS.
+    if (wave == 0) {
+        L.FA[lane] = 1.f;
+        L.PA[lane] = 1.f;
+        L.V[lane] = 0.f;
+        L.GXa[lane] = 1.f;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) L.FB[c][lane] = L.U[c][lane] = L.GXb[c][lane] = 0.f;
+        L.fj[lane] = (valid && chunk > 0) ? chunk - 1 : kWalkDone;
+        L.bj[lane] = (valid && chunk + 1 < G) ? chunk + 1 : kWalkDone;
+    }
+    __syncthreads();
+    if (valid) {
+#pragma unroll
+        for (int k = wave; k < CW::kWords; k += NWV) {
+            float v;
+            bool live = true;
+            if (k == CW::kA) {
+                v = L.n.A[0][lane];
+            } else if (k < CW::kP) {
+                v = L.n.B[0][k - CW::kB][lane];
+                live = k - CW::kB < ncv;
+            } else if (k == CW::kP) {
+                v = L.n.P[0][lane];
+            } else if (k == CW::kBQ) {
+                v = L.n.BQ[0][lane];
+            } else {
+                v = L.n.BJ[0][k - CW::kBJ][lane];
+                live = k - CW::kBJ < ncv;
+            }
+            if (live) publish(carry_word<NCH>(a, strip_base, chunk, k, lane), ep, v);
+        }
+    }
     int spins = 0;
     while (true) {
-        if (wave == 0) L.nJ[col] = done ? kWalkDone : j;
         __syncthreads();
         {
-            const int jl = L.nJ[col];
-            const int jq = jl + wave * dir;
-            int st = 0;
+            const bool fwd = wave < NH;
+            const int q = fwd ? wave : wave - NH;
+            const int jl = fwd ? L.fj[lane] : L.bj[lane];
+            const int jq = fwd ? jl - q : jl + q;
+            bool ok = false;
             if (jl != kWalkDone && jq >= 0 && jq < G) {
-                unsigned long long wi[NCH], wb[NCH];
+                unsigned long long wb[NCH];
 #pragma unroll
                 for (int c = 0; c < NCH; ++c)
-                    if (c < ncv) {
-                        wi[c] = __hip_atomic_load(carry_word<NCH>(a, strip_base, jq, wIncl + c, col),
-                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        wb[c] = __hip_atomic_load(carry_word<NCH>(a, strip_base, jq, wB + c, col),
-                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    }
-                const unsigned long long wa = __hip_atomic_load(
-                    carry_word<NCH>(a, strip_base, jq, wA, col), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                bool inc_ok = true, agg_ok = static_cast<unsigned>(wa >> 32) == ep;
+                    if (c < ncv) wb[c] = load_word(carry_word<NCH>(a, strip_base, jq, CW::kB + c, lane));
+                const unsigned long long wa = load_word(carry_word<NCH>(a, strip_base, jq, CW::kA, lane));
+                ok = static_cast<unsigned>(wa >> 32) == ep && tags_ok<NCH>(wb, ncv, ep);
+                L.n.A[wave][lane] = word_value(wa);
 #pragma unroll
-                for (int c = 0; c < NCH; ++c)
-                    if (c < ncv) {
-                        inc_ok = inc_ok && static_cast<unsigned>(wi[c] >> 32) == ep;
-                        agg_ok = agg_ok && static_cast<unsigned>(wb[c] >> 32) == ep;
-                    }
-                st = inc_ok ? 2 : agg_ok ? 1 : 0;
-                L.nA[wave][col] = __uint_as_float(static_cast<unsigned>(wa));
+                for (int c = 0; c < NCH; ++c) L.n.B[wave][c][lane] = (c < ncv) ? word_value(wb[c]) : 0.f;
+                if (!fwd) {
+                    unsigned long long wj[NCH];
 #pragma unroll
-                for (int c = 0; c < NCH; ++c)
-                    L.nV[wave][c][col] =
-                        (c < ncv) ? __uint_as_float(static_cast<unsigned>(inc_ok ? wi[c] : wb[c])) : 0.f;
+                    for (int c = 0; c < NCH; ++c)
+                        if (c < ncv) wj[c] = load_word(carry_word<NCH>(a, strip_base, jq, CW::kBJ + c, lane));
+                    const unsigned long long wp = load_word(carry_word<NCH>(a, strip_base, jq, CW::kP, lane));
+                    const unsigned long long wq = load_word(carry_word<NCH>(a, strip_base, jq, CW::kBQ, lane));
+                    ok = ok && static_cast<unsigned>(wp >> 32) == ep && static_cast<unsigned>(wq >> 32) == ep &&
+                         tags_ok<NCH>(wj, ncv, ep);
+                    L.n.P[wave][lane] = word_value(wp);
+                    L.n.BQ[wave][lane] = word_value(wq);
+#pragma unroll
+                    for (int c = 0; c < NCH; ++c) L.n.BJ[wave][c][lane] = (c < ncv) ? word_value(wj[c]) : 0.f;
+                }
             }
-            L.nS[wave][col] = st;
+            L.n.ok[wave][lane] = ok ? 1 : 0;
         }
         __syncthreads();
         if (wave == 0) {
-            bool stalled = false;
+            int fj = L.fj[lane], bj = L.bj[lane];
+            bool fstall = false, bstall = false, progressed = false;
+            if (fj != kWalkDone) {
+                float FA = L.FA[lane], FB[NCH];
 #pragma unroll
-            for (int q = 0; q < NWV; ++q) {
-                if (done || stalled) continue;
-                if (j < 0 || j >= G) {  // walked past the first / last chunk: the aggregate is exact
+                for (int c = 0; c < NCH; ++c) FB[c] = L.FB[c][lane];
 #pragma unroll
-                    for (int c = 0; c < NCH; ++c) carry[c] = GB[c];
-                    done = true;
-                    continue;
+                for (int q = 0; q < NH; ++q) {
+                    if (fj == kWalkDone || fstall) continue;
+                    if (fj < 0 || FA < kCarryNegligible) {
+                        fj = kWalkDone;
+                    } else if (L.n.ok[q][lane]) {
+#pragma unroll
+                        for (int c = 0; c < NCH; ++c) FB[c] = fmaf(FA, L.n.B[q][c][lane], FB[c]);
+                        FA *= L.n.A[q][lane];
+                        --fj;
+                        progressed = true;
+                    } else {
+                        fstall = true;
+                    }
                 }
-                const int st = L.nS[q][col];
-                if (st == 2) {
+                if (fj != kWalkDone && (fj < 0 || FA < kCarryNegligible)) fj = kWalkDone;
+                L.FA[lane] = FA;
 #pragma unroll
-                    for (int c = 0; c < NCH; ++c) carry[c] = fmaf(GA, L.nV[q][c][col], GB[c]);
-                    done = true;
-                } else if (st == 1) {
+                for (int c = 0; c < NCH; ++c) L.FB[c][lane] = FB[c];
+            }
+            if (bj != kWalkDone) {
+                float PA = L.PA[lane], V = L.V[lane], GXa = L.GXa[lane], U[NCH], GXb[NCH];
 #pragma unroll
-                    for (int c = 0; c < NCH; ++c) GB[c] = fmaf(GA, L.nV[q][c][col], GB[c]);
-                    GA *= L.nA[q][col];
-                    j += dir;
-                } else {
-                    stalled = true;
+                for (int c = 0; c < NCH; ++c) {
+                    U[c] = L.U[c][lane];
+                    GXb[c] = L.GXb[c][lane];
+                }
+#pragma unroll
+                for (int q = NH; q < NWV; ++q) {
+                    if (bj == kWalkDone || bstall) continue;
+                    if (bj >= G || PA < kCarryNegligible) {
+                        bj = kWalkDone;
+                    } else if (L.n.ok[q][lane]) {
+                        const float bq = L.n.BQ[q][lane], aj = L.n.A[q][lane];
+#pragma unroll
+                        for (int c = 0; c < NCH; ++c) {
+                            U[c] = fmaf(PA, fmaf(bq, GXb[c], L.n.BJ[q][c][lane]), U[c]);
+                            GXb[c] = fmaf(aj, GXb[c], L.n.B[q][c][lane]);
+                        }
+                        V = fmaf(PA, bq * GXa, V);
+                        GXa *= aj;
+                        PA *= L.n.P[q][lane];
+                        ++bj;
+                        progressed = true;
+                    } else {
+                        bstall = true;
+                    }
+                }
+                if (bj != kWalkDone && (bj >= G || PA < kCarryNegligible)) bj = kWalkDone;
+                L.PA[lane] = PA;
+                L.V[lane] = V;
+                L.GXa[lane] = GXa;
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    L.U[c][lane] = U[c];
+                    L.GXb[c][lane] = GXb[c];
                 }
             }
-            if (!done && (j < 0 || j >= G)) {
-#pragma unroll
-                for (int c = 0; c < NCH; ++c) carry[c] = GB[c];
-                done = true;
-            }
-            if (!done && stalled) {
-                // Wait for the blocking neighbour j gently: poll only its first inclusive
-                // word and its aggregate factor, sleeping longer and longer between polls,
-                // and stage the next round trip only once one of them has been written.
-                gword* pi0 = carry_word<NCH>(a, strip_base, j, wIncl, col);
-                gword* pa0 = carry_word<NCH>(a, strip_base, j, wA, col);
+            if (progressed) spins = 0;
+            if (fstall || bstall) {
+                // Wait for the blocking neighbour gently: poll only its first word,
+                // sleeping longer and longer between polls, and stage the next round trip
+                // once it has been written.
+                gword* pw = carry_word<NCH>(a, strip_base, fstall ? fj : bj, CW::kA, lane);
                 int backoff = 1;
                 while (true) {
-                    const unsigned long long u =
-                        __hip_atomic_load(pi0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    const unsigned long long v =
-                        __hip_atomic_load(pa0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    if (static_cast<unsigned>(u >> 32) == ep || static_cast<unsigned>(v >> 32) == ep) break;
+                    if (static_cast<unsigned>(load_word(pw) >> 32) == ep) break;
                     spins += backoff;
                     if (spins > kSpinLimit) break;
                     for (int i = 0; i < backoff; ++i) __builtin_amdgcn_s_sleep(2);
@@ -168,116 +301,35 @@ __device__ void resolve_carry(const CarryCtx& a, ChunkLds<NCH, NWV>& L, size_t s
                 }
                 if (spins > kSpinLimit) {
                     flag_error(a.status, kErrSpinTimeout);
-#pragma unroll
-                    for (int c = 0; c < NCH; ++c) carry[c] = GB[c];
-                    done = true;
+                    fj = bj = kWalkDone;
                 }
-            } else if (!stalled) {
-                spins = 0;
             }
-            const bool any = __ballot(!done) != 0;
-            if (col == 0) L.more = any ? 1 : 0;
+            L.fj[lane] = fj;
+            L.bj[lane] = bj;
+            const bool any = __ballot(fj != kWalkDone || bj != kWalkDone) != 0;
+            if (lane == 0) L.more = any ? 1 : 0;
         }
         __syncthreads();
         if (L.more == 0) break;
     }
-}
 
-// All waves of a chunk's workgroup: wave 0 composes the waves into the chunk aggregates
-// and publishes them, all waves take part in the exchange of carries with the other
-// chunks of the strip, and wave 0 writes every wave's carry-in X_in (L.Jin) and Y_in
-// (L.Kin).  `ncv` channels are valid; `valid` is false for lanes past the right edge of
-// the image.
-template <int NCH, int NWV>
-__device__ void chunk_carries(const CarryCtx& a, ChunkLds<NCH, NWV>& L, int b, int grp, int strip,
-                              int chunk, int lane, int wave, bool valid, int ncv) {
-    using CW = CarryWords<NCH>;
-    const size_t strip_base =
-        ((static_cast<size_t>(b) * a.NG + grp) * a.S + strip) * static_cast<size_t>(a.G);
-    const unsigned ep = a.epoch;
-    // chunk-level forward aggregate: compose the waves in order
-    float CA = 1.f, CB[NCH];
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) CB[c] = 0.f;
     if (wave == 0) {
+        // forward carry into every wave, then the backward carry from the bottom wave up
+        float xe[NCH], kv[NCH];
 #pragma unroll
-        for (int v = 0; v < NWV; ++v) {
-            const float Av = L.A[v][lane];
-#pragma unroll
-            for (int c = 0; c < NCH; ++c) CB[c] = fmaf(Av, CB[c], L.B[v][c][lane]);
-            CA *= Av;
-        }
-        if (chunk > 0 && valid) {
-            publish(carry_word<NCH>(a, strip_base, chunk, CW::kFwdA, lane), ep, CA);
-#pragma unroll
-            for (int c = 0; c < NCH; ++c)
-                if (c < ncv) publish(carry_word<NCH>(a, strip_base, chunk, CW::kFwdB + c, lane), ep, CB[c]);
-        }
-    }
-    float Jc[NCH];
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) Jc[c] = 0.f;
-    if (chunk > 0)
-        resolve_carry<NCH, NWV>(a, L, strip_base, lane, wave, chunk, -1, CW::kFwdA, CW::kFwdB, CW::kFwdIncl,
-                                ncv, valid, Jc);
-    float CP = 1.f, alpha[NCH];
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) alpha[c] = 0.f;
-    if (wave == 0) {
-        if (valid) {
-#pragma unroll
-            for (int c = 0; c < NCH; ++c)
-                if (c < ncv)
-                    publish(carry_word<NCH>(a, strip_base, chunk, CW::kFwdIncl + c, lane), ep,
-                            fmaf(CA, Jc[c], CB[c]));
-        }
-        // forward carry into every wave, and the chunk-level backward aggregate
-        float jv[NCH];
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) jv[c] = Jc[c];
+        for (int c = 0; c < NCH; ++c) xe[c] = L.FB[c][lane];
 #pragma unroll
         for (int v = 0; v < NWV; ++v) {
             const float Av = L.A[v][lane];
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
-                L.Jin[v][c][lane] = jv[c];
-                jv[c] = fmaf(Av, jv[c], L.B[v][c][lane]);
+                L.Jin[v][c][lane] = xe[c];
+                xe[c] = fmaf(Av, xe[c], L.B[v][c][lane]);
             }
         }
+        // xe is now X_in of the next chunk
 #pragma unroll
-        for (int v = NWV - 1; v >= 0; --v) {
-            const float Pv = L.P[v][lane], BQv = L.BQ[v][lane];
-#pragma unroll
-            for (int c = 0; c < NCH; ++c)
-                alpha[c] = fmaf(Pv, alpha[c], fmaf(BQv, L.Jin[v][c][lane], L.BJ[v][c][lane]));
-            CP *= Pv;
-        }
-        if (chunk < a.G - 1 && valid) {
-            publish(carry_word<NCH>(a, strip_base, chunk, CW::kBwdP, lane), ep, CP);
-#pragma unroll
-            for (int c = 0; c < NCH; ++c)
-                if (c < ncv)
-                    publish(carry_word<NCH>(a, strip_base, chunk, CW::kBwdAlpha + c, lane), ep, alpha[c]);
-        }
-    }
-    float Kc[NCH];
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) Kc[c] = 0.f;
-    if (chunk < a.G - 1)
-        resolve_carry<NCH, NWV>(a, L, strip_base, lane, wave, chunk, +1, CW::kBwdP, CW::kBwdAlpha,
-                                CW::kBwdIncl, ncv, valid, Kc);
-    if (wave == 0) {
-        if (valid) {
-#pragma unroll
-            for (int c = 0; c < NCH; ++c)
-                if (c < ncv)
-                    publish(carry_word<NCH>(a, strip_base, chunk, CW::kBwdIncl + c, lane), ep,
-                            fmaf(CP, Kc[c], alpha[c]));
-        }
-        // backward carry into every wave (Y at the row after the wave's last row)
-        float kv[NCH];
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) kv[c] = Kc[c];
+        for (int c = 0; c < NCH; ++c) kv[c] = fmaf(L.V[lane], xe[c], L.U[c][lane]);
 #pragma unroll
         for (int v = NWV - 1; v >= 0; --v) {
             const float Pv = L.P[v][lane], BQv = L.BQ[v][lane];
@@ -290,7 +342,23 @@ __device__ void chunk_carries(const CarryCtx& a, ChunkLds<NCH, NWV>& L, int b, i
     }
 }
 
+// Chunk and strip group of workgroup p in a persistent column grid with G chunks per
+// strip.  With `xcd` set, strip groups are dealt to the XCDs in turn and all G chunks of a
+// group run on that group's XCD (workgroup p runs on XCD p % 8), so the carry words a
+// chunk polls were written by workgroups of its own XCD; otherwise workgroup p takes
+// chunk p % G of group p / G.  Groups at or past the launch's group count have no work.
+struct ChunkSlot {
+    int chunk, group;
+};
+__device__ __forceinline__ ChunkSlot chunk_slot(int p, int G, int xcd) {
+    if (xcd) {
+        const int k = p / kXcds;
+        return ChunkSlot{k % G, (k / G) * kXcds + p % kXcds};
+    }
+    return ChunkSlot{p % G, p / G};
+}
+
 // Words of carry area per (strip, chunk) for NCH channels, for workspace sizing.
-constexpr int carry_words_per_chunk(int nch) { return 2 + 4 * nch; }
+constexpr int carry_words_per_chunk(int nch) { return 3 + 2 * nch; }
 
 }  // namespace dts

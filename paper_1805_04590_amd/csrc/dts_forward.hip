@@ -236,11 +236,13 @@ template <int CT, int R, int NWV, int EPI>
 __global__ void __launch_bounds__(kWave * NWV, (col_min_waves<CT, R, NWV>())) col_pass_kernel(ColArgs a) {
     __shared__ ChunkLds<CT, NWV> L;
     const CarryCtx cctx{a.carry, a.epoch, a.status, a.G, a.S, a.NG};
-    // Persistent grid: workgroup p always processes chunk p % G, for the strips
-    // p / G, p / G + groups, ...; every strip's chunks are thus held by G workgroups of
+    // Persistent grid: a workgroup always processes the same chunk of the strips
+    // group, group + groups, ...; every strip's chunks are thus held by G workgroups of
     // the same launch that are all running, and none ever waits on one not yet started.
-    const int chunk = static_cast<int>(blockIdx.x % a.G);
-    const int group = static_cast<int>(blockIdx.x / a.G);
+    const ChunkSlot slot = chunk_slot(static_cast<int>(blockIdx.x), a.G, a.xcd);
+    const int chunk = slot.chunk;
+    const int group = slot.group;
+    if (group >= a.groups) return;
     const int n_strips = a.batch * a.NG * a.S;
 #pragma unroll 1
     for (int sid = group; sid < n_strips; sid += a.groups) {
@@ -358,6 +360,47 @@ int col_variant_info(int variant, int* ct, int* rows_per_wave, int* waves) {
 
 int num_col_variants() { return kNumColVariants; }
 
+static int g_col_xcd = 1;
+
+int tune_col_xcd(int on) {
+    g_col_xcd = on ? 1 : 0;
+    return DTS_OK;
+}
+
+static int device_cus() {
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    if (cached[dev] == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+        cached[dev] = cus;
+    }
+    return cached[dev];
+}
+
+// Strips in flight and grid size of a persistent column pass.  The XCD-local form needs
+// the CUs split evenly over the XCDs and a strip's G chunks to fit in one XCD's share of
+// the capacity; its grid is a whole number of rounds of the 8 XCDs, and the workgroups of
+// groups past n_strips exit at once.
+ColGrid col_grid(int cap, int G, long long n_strips) {
+    ColGrid g{};
+    const int cus = device_cus();
+    const int per_xcd = (cus > 0 && cus % kXcds == 0) ? cap / kXcds : 0;
+    if (g_col_xcd && per_xcd >= G) {
+        const long long groups = std::min<long long>(static_cast<long long>(per_xcd / G) * kXcds, n_strips);
+        const long long rounds = (groups + kXcds - 1) / kXcds;
+        g.groups = static_cast<int>(groups);
+        g.n = static_cast<unsigned>(rounds * kXcds * G);
+        g.xcd = 1;
+        return g;
+    }
+    g.groups = static_cast<int>(std::min<long long>(cap / G, n_strips));
+    g.n = static_cast<unsigned>(g.groups) * G;
+    g.xcd = 0;
+    return g;
+}
+
 size_t col_carry_words(int batch, int H, int W, int C) {
     // sized for the smallest chunk of any variant so every variant fits
     const int ct = col_group(C);
@@ -400,9 +443,10 @@ int launch_col_pass(const ColPass& p, Ctx& ctx) {
     const int cap = v.capacity(mode);
     if (cap <= 0) return hip_fail(hipErrorNoDevice);
     if (a.G > cap) return DTS_ENOTSUP;
-    const long long n_strips = static_cast<long long>(p.batch) * a.NG * a.S;
-    a.groups = static_cast<int>(std::min<long long>(cap / a.G, n_strips));
-    const unsigned n = static_cast<unsigned>(a.groups) * a.G;
+    const ColGrid grid = col_grid(cap, a.G, static_cast<long long>(p.batch) * a.NG * a.S);
+    a.groups = grid.groups;
+    a.xcd = grid.xcd;
+    const unsigned n = grid.n;
     // algorithmic bytes: signal in and out, distances in; the update epilogue also reads
     // z^k, the target and the confidence (or z^k and the data-term gradient)
     const double px = static_cast<double>(p.batch) * a.H * a.W;

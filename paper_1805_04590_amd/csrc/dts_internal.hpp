@@ -152,6 +152,17 @@ class ProfScope {
     long index_ = -1;
 };
 
+// Grid of a persistent column pass: `groups` strips in flight, `n` workgroups, and
+// whether the chunks of each strip are kept on one XCD (see chunk_slot).  `cap` is the
+// kernel's co-resident workgroup capacity, G the chunks per strip.
+struct ColGrid {
+    int groups;
+    unsigned n;
+    int xcd;
+};
+ColGrid col_grid(int cap, int G, long long n_strips);
+int tune_col_xcd(int on);
+
 // Error bookkeeping shared by the translation units.
 int hip_fail(hipError_t e);
 

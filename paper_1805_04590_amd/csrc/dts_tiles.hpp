@@ -302,7 +302,8 @@ struct ColArgs {
     int C, H, W;
     float log2a;
     int G, S, NG, batch;
-    int groups;  // strips processed at once: the grid holds groups * G workgroups
+    int groups;  // strips processed at once
+    int xcd;     // 1: every strip's chunks on one XCD (chunk_slot)
     unsigned long long* carry;
     unsigned epoch;
     int* status;

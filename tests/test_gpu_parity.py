@@ -296,3 +296,42 @@ def test_every_column_variant_on_long_strips(v, ct, R, nw):
     finally:
         dts.tune_col_variant(ct, -1)
     assert np.abs(got_col[0] - ref_col).max() <= FILTER_TOL
+
+
+def test_column_carries_without_truncation():
+    # A nearly flat guide and a very wide kernel (sigma_s = 2000) keep every product of
+    # weights along a strip above the point where a carry walk may stop early, so each
+    # chunk composes the aggregates of every other chunk of its strip: 32 chunks, eight
+    # round trips of the exchange each way.
+    H, W = 10240, 70
+    announce("column pass, untruncated walks", H, W)
+    rng = np.random.default_rng(17)
+    guide = (0.5 + 1e-6 * rng.standard_normal((1, H, W))).astype(np.float32)
+    f = rng.uniform(size=(1, H, W)).astype(np.float32)
+    rdx, rdy = oracle.distances(guide, 2000.0, 0.5)
+    a = oracle.feedback_coefficients(2000.0, 3)[0]
+    assert a ** (rdy.max() * H) > 2.0 ** -30  # no walk may stop before the strip's end
+    ref = np.moveaxis(oracle.rf1d_lines(np.moveaxis(f.astype(np.float64), -2, 0), (a ** rdy)[:, None, :]), 0, -2)
+    dy = dev(rdy.astype(np.float32)[None])
+    x = dev(f)
+    got = host(dts.col_pass(x, dy, 2000.0, 1, 3))
+    assert np.abs(got[0] - ref).max() <= FILTER_TOL
+    again = host(dts.col_pass(x, dy, 2000.0, 1, 3))
+    assert np.array_equal(got, again)
+
+
+@pytest.mark.parametrize("H,W,Ct", [(1500, 300, 1), (2600, 130, 3), (10240, 64, 1)])
+def test_multi_chunk_solve_is_bitwise_reproducible(H, W, Ct):
+    # Which neighbours a chunk composes, and in which order, depends on the data only, so
+    # repeated solves agree bit for bit however the chunks' workgroups are timed; other
+    # work runs between the calls.
+    announce("bitwise reproducible", H, W, Ct)
+    case = dts_inputs.random_case(8100 + H, H, W, 3, Ct, Cc=1, sigma_s=24.0, sigma_r=0.2, T=3)
+    g, t, c = dev(case["guide"]), dev(case["target"]), dev(case["conf"])
+    first = host(dts.solve(g, t, c, 24.0, 0.2, 3, 3))
+    for rep in range(3):
+        dts.solve(g[:, :, :200 + rep].contiguous(), t[:, :, :200 + rep].contiguous(),
+                  c[:, :, :200 + rep].contiguous(), 24.0, 0.2, 3, 2)
+        assert np.array_equal(host(dts.solve(g, t, c, 24.0, 0.2, 3, 3)), first), rep
+    if H <= 2600:
+        assert np.abs(first - oracle_solve(case)).max() <= SOLVE_TOL
