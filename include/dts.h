@@ -86,6 +86,23 @@ int dts_solve(const float* guide, int Cg, const float* target, const float* conf
               int Ct, int batch, int H, int W, const dts_params* p, float* out,
               float* checkpoints, void* workspace, size_t workspace_bytes, void* stream);
 
+/* dts_solve_noalloc -- dts_solve for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, hosts that forbid allocation): the same
+ * arguments and results as dts_solve without a workspace.  The workspace dts_solve
+ * would need (dts_solve_workspace_bytes) lives instead in a 64 MiB scratch array that
+ * the library holds on every device it runs on until the process ends, so the call
+ * allocates nothing.  Returns DTS_ENOTSUP when dts_solve_workspace_bytes exceeds
+ * 64 MiB (67108864 bytes; e.g. a 1-channel 2048 x 2048 or 3-channel 1920 x 1080 solve fits,
+ * a 1-channel 2400 x 2400 one does not).
+ * All calls on one device share that array: calls that may overlap on one device (other
+ * streams, other threads) race and must be serialised by the caller.  The array keeps
+ * the last call's contents; each call clears what must start at zero.  A device-side
+ * failure flag (see dts_workspace_status) lands in the shared array and is not reported:
+ * callers that need it use dts_solve with their own workspace. */
+int dts_solve_noalloc(const float* guide, int Cg, const float* target, const float* conf, int Cc,
+                      int Ct, int batch, int H, int W, const dts_params* p, float* out,
+                      float* checkpoints, void* stream);
+
 /* dts_solve_backward -- reverse-mode gradient of a scalar loss through dts_solve (not in
  * the paper; derived from Eq. (3) and the filter by the chain rule).  Given
  * grad_out = dL/dz^T and the T checkpoints written by dts_solve with the same inputs, it

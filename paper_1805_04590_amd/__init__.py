@@ -34,6 +34,7 @@ __all__ = [
     "solve_stereo",
     "solve",
     "solve_backward",
+    "solve_noalloc",
     "DTSFunction",
     "workspace_status",
     "distances",
@@ -68,6 +69,7 @@ EXPORTED_SYMBOLS = (
     "dts_filter",
     "dts_solve",
     "dts_solve_backward",
+    "dts_solve_noalloc",
     "dts_workspace_status",
     "dts_strerror",
     "dts_last_hip_error",
@@ -207,6 +209,8 @@ def library():
     lib.dts_solve_backward.argtypes = [fp, i, fp, fp, i, i, i, i, i, P, fp, fp, fp, fp, fp,
                                        vp, sz, vp]
     lib.dts_solve_backward.restype = i
+    lib.dts_solve_noalloc.argtypes = [fp, i, fp, fp, i, i, i, i, i, P, fp, fp, vp]
+    lib.dts_solve_noalloc.restype = i
     lib.dts_solve_stereo_workspace_bytes.argtypes = [i, i, i]
     lib.dts_solve_stereo_workspace_bytes.restype = sz
     lib.dts_solve_stereo.argtypes = [fp, fp, i, fp, fp, i, i, i, P, f, f, fp, vp, sz, vp]
@@ -730,6 +734,32 @@ def solve(guide, target, conf, sigma_s, sigma_r, filter_iters=3, solver_iters=10
     if checkpoints:
         return res, ck
     return res
+
+
+def solve_noalloc(guide, target, conf, out, sigma_s, sigma_r, filter_iters=3, solver_iters=10, lam=0.99,
+                  step=0.99, checkpoints=None):
+    """``dts_solve_noalloc``: z^T into the caller's ``out`` (and the iterates into the caller's
+    ``checkpoints``, [T][B][Ct][H][W], if given) with the library's own 64 MiB scratch in
+    place of a workspace, so nothing is allocated here either; raises DTSError
+    (DTS_ENOTSUP) above that size.  Calls on one device must not overlap."""
+    g = _as4d(guide, "guide")
+    t = _as4d(target, "target")
+    c = _as4d(conf, "conf")
+    o = _as4d(out, "out")
+    B, Ct, H, W = t.shape
+    if g.shape[0] != B or g.shape[2:] != t.shape[2:] or c.shape[0] != B or c.shape[2:] != t.shape[2:]:
+        raise ValueError("guide/target/conf disagree in batch or image size")
+    if o.shape != t.shape or o.device != t.device:
+        raise ValueError("out must be a tensor shaped like target on its device")
+    T = int(solver_iters)
+    if checkpoints is not None:
+        _check_plane(checkpoints, "checkpoints", (T,) + tuple(t.shape), t.device)
+    p = Params(sigma_s, sigma_r, filter_iters, solver_iters, lam, step).c()
+    rc = library().dts_solve_noalloc(_ptr(g), g.shape[1], _ptr(t), _ptr(c), c.shape[1], Ct, B, H, W,
+                                     ctypes.byref(p), _ptr(o),
+                                     _ptr(checkpoints) if checkpoints is not None and T else None, _stream())
+    _check(rc, "dts_solve_noalloc")
+    return out
 
 
 def solve_backward(guide, target, conf, checkpoints, grad_out, sigma_s, sigma_r, filter_iters=3,

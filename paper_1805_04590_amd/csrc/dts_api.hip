@@ -277,6 +277,33 @@ static int begin_call(Setup& S, void* ws, size_t ws_bytes, int batch, int H, int
     return launch_zero(base + S.L.carry, S.L.carry_bytes, S.ctx.stream);
 }
 
+// Scratch memory of dts_solve_noalloc: the workspace of one solve lives in this array,
+// which every device the library runs on holds once (from module load to process end).
+// Host code must never pass the array's name to a kernel or a copy: on the host it only
+// names the symbol.  Its device address comes from hipGetSymbolAddress, taken once per
+// device with that device current.
+constexpr size_t kScratchBytes = static_cast<size_t>(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static int scratch_address(void** out) {
+    static void* ptrs[64] = {};
+    static std::mutex mu;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e);
+    if (dev < 0 || dev >= 64) return DTS_ENOTSUP;
+    std::lock_guard<std::mutex> lock(mu);
+    if (ptrs[dev] == nullptr) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e);
+        if (ptr == nullptr) return hip_fail(hipErrorInvalidSymbol);
+        ptrs[dev] = ptr;
+    }
+    *out = ptrs[dev];
+    return DTS_OK;
+}
+
 }  // namespace dts
 
 using namespace dts;
@@ -409,6 +436,20 @@ int dts_solve(const float* guide, int Cg, const float* target, const float* conf
         }
     }
     return DTS_OK;
+}
+
+int dts_solve_noalloc(const float* guide, int Cg, const float* target, const float* conf, int Cc, int Ct,
+                      int batch, int H, int W, const dts_params* p, float* out, float* checkpoints,
+                      void* stream) {
+    if (!p) return DTS_EINVAL;
+    const size_t need = dts_solve_workspace_bytes(batch, H, W, Ct, p);
+    if (need == 0) return DTS_EINVAL;
+    if (need > kScratchBytes) return DTS_ENOTSUP;
+    void* ws = nullptr;
+    const int rc = scratch_address(&ws);
+    if (rc) return rc;
+    return dts_solve(guide, Cg, target, conf, Cc, Ct, batch, H, W, p, out, checkpoints, ws, kScratchBytes,
+                     stream);
 }
 
 int dts_solve_backward(const float* guide, int Cg, const float* target, const float* conf, int Cc,
