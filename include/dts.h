@@ -125,17 +125,19 @@ size_t dts_solve_stereo_workspace_bytes(int batch, int H, int W);
  * image, a Charbonnier target term c rho(z - t) with rho(r) = sqrt(r^2 + epsilon^2), and
  * the photometric term gamma/2 sum_k (I_L,k(x) - I_R,k(x - z))^2 of a rectified pair.
  * Gradient descent with the edge-aware mean held fixed, as for dts_solve:
- *   z^0 = t,  z^{k+1} = z^k - step (lambda (z^k - DT(z^k)) + D(z^k)),
+ *   z^0 = init (the target t if init is NULL),
+ *   z^{k+1} = z^k - step (lambda (z^k - DT(z^k)) + D(z^k)),
  *   D = c rho'(z - t) + gamma sum_k (I_L,k - I_R,k(x - z)) dI_R,k/dx (x - z).
  * Disparities are in pixels: left pixel (x, y) matches the right image at (x - z, y),
  * read linearly along the row, the position clamped to [0, W - 1] (slope 0 where
  * clamped).  left, right [batch][Cg][H][W]; target, conf, out [batch][1][H][W]; p gives
- * sigma_s, sigma_r, filter_iters, solver_iters (T = 0 copies the target), lambda, step.
- * gamma >= 0, epsilon > 0 (Sec. 4 uses 0.001 for both).  out must not alias target,
- * conf or the images.  Errors as dts_solve. */
+ * sigma_s, sigma_r, filter_iters, solver_iters (T = 0 copies z^0), lambda, step.
+ * init is NULL or [batch][1][H][W] (restarting a descent from a given iterate: the data
+ * term keeps using the target).  gamma >= 0, epsilon > 0 (Sec. 4 uses 0.001 for both).
+ * out must not alias target, conf, init or the images.  Errors as dts_solve. */
 int dts_solve_stereo(const float* left, const float* right, int Cg, const float* target, const float* conf,
-                     int batch, int H, int W, const dts_params* p, float gamma, float epsilon, float* out,
-                     void* workspace, size_t workspace_bytes, void* stream);
+                     const float* init, int batch, int H, int W, const dts_params* p, float gamma, float epsilon,
+                     float* out, void* workspace, size_t workspace_bytes, void* stream);
 
 /* ---- Variance-based confidence (Eq. (7), Sec. 3.1) ---- */
 
@@ -291,6 +293,14 @@ int dts_tune_col_variant(int group_channels, int variant);
  * are written from its own XCD; 0: chunk p % G of strip group p / G.  Results agree to
  * fp32 rounding. */
 int dts_tune_col_xcd(int on);
+/* Bounded waits of the column passes' carry exchange (also inside dts_solve_batched).
+ * polls > 0: a wait gives up after about this many polls (default 2^21, each followed by
+ * a short sleep), flags DTS_EDEVICE in the workspace status and lets its kernel finish;
+ * 0 restores the default.  polls < 0 exercises that failure path: the waits look for a
+ * tag that no kernel writes and give up after -polls polls, so every call with carries to
+ * exchange (a column pass over more than one chunk) completes and reports DTS_EDEVICE;
+ * its results are not defined.  Process-wide; set it before enqueuing work. */
+int dts_tune_spin_limit(int polls);
 /* Pixels per lane of the row pass: 4, 8 or 16; 0 restores the default, which depends on
  * the row width.  Rows whose width needs more than 16 waves at this setting fall back to
  * the default. */

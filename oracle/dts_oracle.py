@@ -598,15 +598,21 @@ def energy_stereo(z, zbar, left, right, target, conf, lam, gamma, eps):
 
 
 def solve_stereo(left, right, target, conf, sigma_s, sigma_r, filter_iters=3, solver_iters=10,
-                 lam=0.99, step=0.99, gamma=0.001, eps=0.001):
+                 lam=0.99, step=0.99, gamma=0.001, eps=0.001, return_iterates=False):
     """Stereo refinement (Sec. 3.3, Eq. (11), readings S1-S5): z^0 = t, then
         z^{k+1} = z^k - step * (lam * (z^k - DT(z^k)) + D(z^k)),
-    DT guided by the left image.  target and conf are [1][H][W]; returns z^T."""
+    DT guided by the left image.  target and conf are [1][H][W]; returns z^T (and the
+    list z^0..z^T if ``return_iterates``)."""
     t = np.asarray(target, dtype=np.float64)
     dx, dy = distances(left, sigma_s, sigma_r)
     z = t.copy()
+    iterates = [z.copy()] if return_iterates else None
     for _ in range(int(solver_iters)):
         zbar = dt_filter(z, dx, dy, sigma_s, filter_iters)
         z = z - step * (lam * (z - zbar) + stereo_data_gradient(left, right, z, target, conf, gamma, eps))
+        if return_iterates:
+            iterates.append(z.copy())
+    if return_iterates:
+        return z, iterates
     return z
 

@@ -46,6 +46,7 @@ __all__ = [
     "tune_col_variant",
     "tune_row_segment",
     "tune_col_xcd",
+    "tune_spin_limit",
     "batched_variants",
     "BatchedSolver",
     "SolveGraph",
@@ -94,6 +95,7 @@ EXPORTED_SYMBOLS = (
     "dts_tune_col_variant",
     "dts_tune_row_segment",
     "dts_tune_col_xcd",
+    "dts_tune_spin_limit",
     "dts_batched_variant_count",
     "dts_batched_variant_info",
     "dts_batched_workspace_bytes",
@@ -213,7 +215,7 @@ def library():
     lib.dts_solve_noalloc.restype = i
     lib.dts_solve_stereo_workspace_bytes.argtypes = [i, i, i]
     lib.dts_solve_stereo_workspace_bytes.restype = sz
-    lib.dts_solve_stereo.argtypes = [fp, fp, i, fp, fp, i, i, i, P, f, f, fp, vp, sz, vp]
+    lib.dts_solve_stereo.argtypes = [fp, fp, i, fp, fp, fp, i, i, i, P, f, f, fp, vp, sz, vp]
     lib.dts_solve_stereo.restype = i
     lib.dts_variance_confidence_workspace_bytes.argtypes = [i, i, i, i]
     lib.dts_variance_confidence_workspace_bytes.restype = sz
@@ -250,6 +252,8 @@ def library():
     lib.dts_tune_row_segment.restype = i
     lib.dts_tune_col_xcd.argtypes = [i]
     lib.dts_tune_col_xcd.restype = i
+    lib.dts_tune_spin_limit.argtypes = [i]
+    lib.dts_tune_spin_limit.restype = i
     PP = ctypes.POINTER(_Problem)
     BP = ctypes.POINTER(_BatchedPlan)
     lib.dts_batched_variant_count.argtypes = []
@@ -321,6 +325,30 @@ def _check_plane(t, name, shape, device):
         raise ValueError(f"{name} must be a contiguous float32 {list(shape)} tensor on {device}")
 
 
+def _check_image(t, name, B, H, W, device, channels=None):
+    """t ([B][C][H][W], already through _as4d) matches the call's batch, image size and
+    device, and has a channel count in `channels` (any if None)."""
+    if t.shape[0] != B or tuple(t.shape[2:]) != (H, W) or t.device != device:
+        raise ValueError(f"{name} must be [{B}][C][{H}][{W}] on {device} (got {list(t.shape)} on {t.device})")
+    if channels is not None and t.shape[1] not in channels:
+        raise ValueError(f"{name} must have {' or '.join(str(c) for c in sorted(set(channels)))} channels")
+
+
+def _out_like(out, ref, name="out"):
+    """The caller's output tensor, checked to be shaped and placed like `ref`."""
+    o = _as4d(out, name)
+    if o.shape != ref.shape or o.device != ref.device:
+        raise ValueError(f"{name} must be {list(ref.shape)} on {ref.device} (got {list(o.shape)} on {o.device})")
+    return o
+
+
+def _finish(ws, internal, check, what):
+    """Reads the workspace's device status (a bounded wait that gave up) when asked to, or
+    by default when the workspace was allocated here and nobody else could read it."""
+    if check or (check is None and internal):
+        _check(library().dts_workspace_status(_ptr(ws), _stream()), what + " (device status)")
+
+
 def _workspace(nbytes, device):
     if nbytes == 0:
         raise DTSError(DTS_EINVAL, "workspace size query")
@@ -343,24 +371,28 @@ def row_pass(src, dx, sigma_s, iter, filter_iters=3, out=None):
     x = _as4d(src, "src")
     B, C, H, W = x.shape
     _check_plane(dx, "dx", (B, H, W), x.device)
-    out = torch.empty_like(x) if out is None else _as4d(out, "out")
+    out = torch.empty_like(x) if out is None else _out_like(out, x)
     _check(library().dts_row_pass(_ptr(x), _ptr(out), _ptr(dx), C, B, H, W, float(sigma_s),
                                   int(iter), int(filter_iters), _stream()), "dts_row_pass")
     return out
 
 
-def col_pass(src, dy, sigma_s, iter, filter_iters=3, out=None, workspace=None):
-    """One causal+anticausal recursive pass along columns for filter iteration ``iter``."""
+def col_pass(src, dy, sigma_s, iter, filter_iters=3, out=None, workspace=None, check=None):
+    """One causal+anticausal recursive pass along columns for filter iteration ``iter``.
+    ``check``: read the workspace's device status afterwards (default: only when the
+    workspace is allocated here)."""
     x = _as4d(src, "src")
     B, C, H, W = x.shape
     _check_plane(dy, "dy", (B, H, W), x.device)
-    out = torch.empty_like(x) if out is None else _as4d(out, "out")
+    out = torch.empty_like(x) if out is None else _out_like(out, x)
     lib = library()
-    if workspace is None:
+    internal = workspace is None
+    if internal:
         workspace = _workspace(lib.dts_pass_workspace_bytes(B, H, W, C), x.device)
     _check(lib.dts_col_pass(_ptr(x), _ptr(out), _ptr(dy), C, B, H, W, float(sigma_s), int(iter),
                             int(filter_iters), _ptr(workspace), workspace.numel(), _stream()),
            "dts_col_pass")
+    _finish(workspace, internal, check, "dts_col_pass")
     return out
 
 
@@ -408,6 +440,12 @@ def tune_col_xcd(on):
     _check(library().dts_tune_col_xcd(1 if on else 0), "dts_tune_col_xcd")
 
 
+def tune_spin_limit(polls):
+    """Bounded waits of the carry exchange: polls > 0 sets the bound, 0 the default, and
+    polls < 0 makes every wait give up (to exercise the DTS_EDEVICE path)."""
+    _check(library().dts_tune_spin_limit(int(polls)), "dts_tune_spin_limit")
+
+
 def batched_variants():
     """[(index, rows_per_wave, group_channels, row_tile_pixels)] of the batched kernel's
     shapes."""
@@ -433,11 +471,14 @@ class BatchedSolver:
     def __init__(self, problems, lam=0.99, step=0.99, variant=None, tune_iters=2):
         self.problems = []
         for q in problems:
-            g = _as4d(q["guide"], "guide")[0]
-            t = _as4d(q["target"], "target")[0]
-            c = _as4d(q["conf"], "conf")[0]
+            g4, t4, c4 = (_as4d(q[k], k) for k in ("guide", "target", "conf"))
+            if g4.shape[0] != 1 or t4.shape[0] != 1 or c4.shape[0] != 1:
+                raise ValueError("a batched problem holds one image: [C][H][W] (or [1][C][H][W]) tensors")
+            g, t, c = g4[0], t4[0], c4[0]
             if g.shape[1:] != t.shape[1:] or c.shape[1:] != t.shape[1:]:
                 raise ValueError("guide/target/conf disagree in image size")
+            if g.device != t.device or c.device != t.device:
+                raise ValueError("guide/target/conf must be on one device")
             self.problems.append(dict(guide=g, target=t, conf=c, sigma_s=float(q["sigma_s"]),
                                       sigma_r=float(q["sigma_r"]),
                                       filter_iters=int(q.get("filter_iters", 3)),
@@ -473,9 +514,13 @@ class BatchedSolver:
                "dts_batched_prepare")
         self.variant = variant
 
-    def run(self):
+    def run(self, check=False):
+        """Enqueue the solves; ``check=True`` also waits for them and raises DTSError if a
+        bounded wait inside the kernel gave up (not while capturing a graph)."""
         _check(library().dts_solve_batched(ctypes.byref(self.plan), _ptr(self.workspace), _stream()),
                "dts_solve_batched")
+        if check:
+            self.status()
         return self.outputs
 
     def status(self):
@@ -538,71 +583,77 @@ def workspace_status(ws):
     return DTS_OK
 
 
-def filter(guide, src, sigma_s, sigma_r, filter_iters=3, out=None, workspace=None):
-    """DT(src): the edge-aware domain-transform filter guided by ``guide`` (Sec. 3.2)."""
+def filter(guide, src, sigma_s, sigma_r, filter_iters=3, out=None, workspace=None, check=None):
+    """DT(src): the edge-aware domain-transform filter guided by ``guide`` (Sec. 3.2).
+    ``check``: read the workspace's device status afterwards (default: only when the
+    workspace is allocated here)."""
     g = _as4d(guide, "guide")
     x = _as4d(src, "src")
     B, Cs, H, W = x.shape
-    if g.shape[0] != B or g.shape[2:] != x.shape[2:]:
-        raise ValueError("guide and src disagree in batch or image size")
+    _check_image(g, "guide", B, H, W, x.device)
     lib = library()
-    if out is None:
-        out = torch.empty_like(x)
-    else:
-        out = _as4d(out, "out")
-    if workspace is None:
+    out = torch.empty_like(x) if out is None else _out_like(out, x)
+    internal = workspace is None
+    if internal:
         workspace = _workspace(lib.dts_filter_workspace_bytes(B, H, W, Cs), x.device)
     rc = lib.dts_filter(_ptr(g), g.shape[1], _ptr(x), _ptr(out), Cs, B, H, W, float(sigma_s),
                         float(sigma_r), int(filter_iters), _ptr(workspace), workspace.numel(),
                         _stream())
     _check(rc, "dts_filter")
+    _finish(workspace, internal, check, "dts_filter")
     return out if src.dim() == 4 else out[0]
 
 
 def solve_stereo(left, right, target, conf, sigma_s, sigma_r, filter_iters=3, solver_iters=10,
-                 lam=0.99, step=0.99, gamma=0.001, eps=0.001, out=None, workspace=None):
+                 lam=0.99, step=0.99, gamma=0.001, eps=0.001, out=None, workspace=None, check=None,
+                 init=None):
     """Disparity refinement of Eq. (11) (Sec. 3.3): smoothness guided by ``left``, a
     Charbonnier target term and the photometric term against ``right``.  left/right
-    [B][Cg][H][W] (or [Cg][H][W]); target/conf [B][1][H][W] (or [1][H][W])."""
+    [B][Cg][H][W] (or [Cg][H][W]); target/conf [B][1][H][W] (or [1][H][W]).  ``init``
+    (shaped like target) restarts the descent from that iterate instead of the target."""
     L = _as4d(left, "left")
     R = _as4d(right, "right")
     t = _as4d(target, "target")
     c = _as4d(conf, "conf")
     B, Cg, H, W = L.shape
-    if R.shape != L.shape:
-        raise ValueError("left and right images differ in shape")
-    if t.shape != (B, 1, H, W) or c.shape != (B, 1, H, W):
-        raise ValueError("target and conf must be [B][1][H][W] like the images")
+    if R.shape != L.shape or R.device != L.device:
+        raise ValueError("left and right images differ in shape or device")
+    if t.shape != (B, 1, H, W) or c.shape != (B, 1, H, W) or t.device != L.device or c.device != L.device:
+        raise ValueError("target and conf must be [B][1][H][W] like the images, on their device")
+    z0 = None
+    if init is not None:
+        z0 = _as4d(init, "init")
+        if z0.shape != t.shape or z0.device != t.device:
+            raise ValueError("init must be shaped like target, on its device")
     lib = library()
-    out = torch.empty_like(t) if out is None else _as4d(out, "out")
-    if out.shape != t.shape:
-        raise ValueError("out must have the shape of target")
-    if workspace is None:
+    out = torch.empty_like(t) if out is None else _out_like(out, t)
+    internal = workspace is None
+    if internal:
         nbytes = lib.dts_solve_stereo_workspace_bytes(B, H, W)
         if nbytes == 0:
             raise DTSError(DTS_EINVAL, "dts_solve_stereo_workspace_bytes")
         workspace = _workspace(nbytes, t.device)
     p = Params(sigma_s, sigma_r, filter_iters, solver_iters, lam, step).c()
-    rc = lib.dts_solve_stereo(_ptr(L), _ptr(R), Cg, _ptr(t), _ptr(c), B, H, W, ctypes.byref(p),
+    rc = lib.dts_solve_stereo(_ptr(L), _ptr(R), Cg, _ptr(t), _ptr(c), _ptr(z0), B, H, W, ctypes.byref(p),
                               float(gamma), float(eps), _ptr(out), _ptr(workspace), workspace.numel(),
                               _stream())
     _check(rc, "dts_solve_stereo")
+    _finish(workspace, internal, check, "dts_solve_stereo")
     return out if target.dim() == 4 else out[0]
 
 
-def variance_confidence(guide, z, sigma_s, sigma_r, sigma_c, filter_iters=3, out=None, workspace=None):
+def variance_confidence(guide, z, sigma_s, sigma_r, sigma_c, filter_iters=3, out=None, workspace=None,
+                        check=None):
     """Confidence from the edge-aware variance of z (Eq. (7)): exp(-(DT(z^2) - DT(z)^2) /
     (2 sigma_c^2)) per channel, DT guided by ``guide`` as in ``filter``.  ``out`` may be z."""
     g = _as4d(guide, "guide")
     x = _as4d(z, "z")
     B, C, H, W = x.shape
-    if g.shape[0] != B or g.shape[2:] != x.shape[2:]:
-        raise ValueError("guide and z disagree in batch or image size")
+    _check_image(g, "guide", B, H, W, x.device)
     lib = library()
-    out = torch.empty_like(x) if out is None else _as4d(out, "out")
-    if out.shape != x.shape:
-        raise ValueError("out must have the shape of z")
-    if workspace is None:
+    out = torch.empty_like(x) if out is None else _out_like(out, x)
+    internal = workspace is None
+    if internal:
         nbytes = lib.dts_variance_confidence_workspace_bytes(B, H, W, C)
         if nbytes == 0:
             raise DTSError(DTS_EINVAL, "dts_variance_confidence_workspace_bytes")
@@ -611,6 +662,7 @@ def variance_confidence(guide, z, sigma_s, sigma_r, sigma_c, filter_iters=3, out
                                      float(sigma_s), float(sigma_r), int(filter_iters),
                                      float(sigma_c), _ptr(workspace), workspace.numel(), _stream())
     _check(rc, "dts_variance_confidence")
+    _finish(workspace, internal, check, "dts_variance_confidence")
     return out if z.dim() == 4 else out[0]
 
 
@@ -631,12 +683,9 @@ def filter_box(guide, src, sigma_s, sigma_r, filter_iters=3, out=None, workspace
     g = _as4d(guide, "guide")
     x = _as4d(src, "src")
     B, C, H, W = x.shape
-    if g.shape[0] != B or g.shape[2:] != x.shape[2:]:
-        raise ValueError("guide and src disagree in batch or image size")
+    _check_image(g, "guide", B, H, W, x.device)
     lib = library()
-    out = torch.empty_like(x) if out is None else _as4d(out, "out")
-    if out.shape != x.shape:
-        raise ValueError("out must have the shape of src")
+    out = torch.empty_like(x) if out is None else _out_like(out, x)
     if workspace is None:
         workspace = _workspace(lib.dts_box_workspace_bytes(B, H, W, C, int(filter_iters)), x.device)
     _check(lib.dts_filter_box(_ptr(g), g.shape[1], _ptr(x), _ptr(out), C, B, H, W, float(sigma_s),
@@ -652,11 +701,11 @@ def solve_box(guide, target, conf, sigma_s, sigma_r, filter_iters=3, solver_iter
     t = _as4d(target, "target")
     c = _as4d(conf, "conf")
     B, Ct, H, W = t.shape
-    if g.shape[0] != B or g.shape[2:] != t.shape[2:] or c.shape[0] != B or c.shape[2:] != t.shape[2:]:
-        raise ValueError("guide/target/conf disagree in batch or image size")
+    _check_image(g, "guide", B, H, W, t.device)
+    _check_image(c, "conf", B, H, W, t.device, (1, Ct))
     p = Params(sigma_s, sigma_r, filter_iters, solver_iters, lam, step).c()
     lib = library()
-    out = torch.empty_like(t) if out is None else _as4d(out, "out")
+    out = torch.empty_like(t) if out is None else _out_like(out, t)
     if workspace is None:
         workspace = _workspace(lib.dts_box_workspace_bytes(B, H, W, Ct, int(filter_iters)), t.device)
     _check(lib.dts_solve_box(_ptr(g), g.shape[1], _ptr(t), _ptr(c), c.shape[1], Ct, B, H, W, ctypes.byref(p),
@@ -705,31 +754,35 @@ def support(guide, sigma_s, sigma_r, filter_iters=3, conf=None, out=None, conf_o
 
 
 def solve(guide, target, conf, sigma_s, sigma_r, filter_iters=3, solver_iters=10, lam=0.99,
-          step=0.99, checkpoints=False, out=None, workspace=None):
+          step=0.99, checkpoints=False, out=None, workspace=None, check=None):
     """z^T of the Eq. (3) gradient descent started at z^0 = target.
 
     With ``checkpoints=True`` also returns the [T][B][Ct][H][W] tensor of iterates
-    z^0..z^{T-1} that ``solve_backward`` consumes."""
+    z^0..z^{T-1} that ``solve_backward`` consumes.  ``check``: wait for the solve and
+    read the workspace's device status (default: only when the workspace is allocated
+    here, since nobody else could read it); a caller passing ``workspace`` may read it
+    later with ``workspace_status``."""
     g = _as4d(guide, "guide")
     t = _as4d(target, "target")
     c = _as4d(conf, "conf")
     B, Ct, H, W = t.shape
-    if g.shape[0] != B or g.shape[2:] != t.shape[2:] or c.shape[0] != B or c.shape[2:] != t.shape[2:]:
-        raise ValueError("guide/target/conf disagree in batch or image size")
+    _check_image(g, "guide", B, H, W, t.device)
+    _check_image(c, "conf", B, H, W, t.device, (1, Ct))
     p = Params(sigma_s, sigma_r, filter_iters, solver_iters, lam, step).c()
     lib = library()
-    if out is None:
-        out = torch.empty_like(t)
+    out = torch.empty_like(t) if out is None else _out_like(out, t)
     ck = None
     if checkpoints:
         ck = torch.empty((max(int(solver_iters), 0),) + tuple(t.shape), dtype=torch.float32,
                          device=t.device)
-    if workspace is None:
+    internal = workspace is None
+    if internal:
         workspace = _workspace(lib.dts_solve_workspace_bytes(B, H, W, Ct, ctypes.byref(p)), t.device)
     rc = lib.dts_solve(_ptr(g), g.shape[1], _ptr(t), _ptr(c), c.shape[1], Ct, B, H, W,
                        ctypes.byref(p), _ptr(out), _ptr(ck) if ck is not None and ck.numel() else None,
                        _ptr(workspace), workspace.numel(), _stream())
     _check(rc, "dts_solve")
+    _finish(workspace, internal, check, "dts_solve")
     res = out if target.dim() == 4 else out[0]
     if checkpoints:
         return res, ck
@@ -764,13 +817,18 @@ def solve_noalloc(guide, target, conf, out, sigma_s, sigma_r, filter_iters=3, so
 
 def solve_backward(guide, target, conf, checkpoints, grad_out, sigma_s, sigma_r, filter_iters=3,
                    solver_iters=10, lam=0.99, step=0.99, need=(True, True, True),
-                   workspace=None):
-    """(dL/dtarget, dL/dconf, dL/dguide) given dL/dz^T and the checkpoints of ``solve``."""
+                   workspace=None, check=None):
+    """(dL/dtarget, dL/dconf, dL/dguide) given dL/dz^T and the checkpoints of ``solve``.
+    ``check`` as for ``solve``."""
     g = _as4d(guide, "guide")
     t = _as4d(target, "target")
     c = _as4d(conf, "conf")
     go = _as4d(grad_out, "grad_out")
     B, Ct, H, W = t.shape
+    _check_image(g, "guide", B, H, W, t.device)
+    _check_image(c, "conf", B, H, W, t.device, (1, Ct))
+    if go.shape != t.shape or go.device != t.device:
+        raise ValueError(f"grad_out must be {list(t.shape)} on {t.device} like the target")
     T = int(solver_iters)
     if checkpoints.shape != (T,) + tuple(t.shape) or checkpoints.dtype != torch.float32 \
             or not checkpoints.is_contiguous() or checkpoints.device != t.device:
@@ -780,7 +838,8 @@ def solve_backward(guide, target, conf, checkpoints, grad_out, sigma_s, sigma_r,
     gt = torch.empty_like(t) if need[0] else None
     gc = torch.empty_like(c) if need[1] else None
     gg = torch.empty_like(g) if need[2] else None
-    if workspace is None:
+    internal = workspace is None
+    if internal:
         workspace = _workspace(lib.dts_solve_backward_workspace_bytes(
             B, H, W, g.shape[1], Ct, ctypes.byref(p)), t.device)
     rc = lib.dts_solve_backward(_ptr(g), g.shape[1], _ptr(t), _ptr(c), c.shape[1], Ct, B, H, W,
@@ -788,6 +847,7 @@ def solve_backward(guide, target, conf, checkpoints, grad_out, sigma_s, sigma_r,
                                 _ptr(gt), _ptr(gc), _ptr(gg), _ptr(workspace), workspace.numel(),
                                 _stream())
     _check(rc, "dts_solve_backward")
+    _finish(workspace, internal, check, "dts_solve_backward")
     squeeze = target.dim() == 3
     fix = (lambda x: x[0] if (x is not None and squeeze) else x)
     return fix(gt), fix(gc), fix(gg)
@@ -795,14 +855,19 @@ def solve_backward(guide, target, conf, checkpoints, grad_out, sigma_s, sigma_r,
 
 class DTSFunction(torch.autograd.Function):
     """z^T = solve(guide, target, conf) with gradients for all three inputs through the
-    hand-written adjoint (per-iteration checkpoints, recomputed filter passes)."""
+    hand-written adjoint (per-iteration checkpoints, recomputed filter passes).
+    ``apply(guide, target, conf, params, check=True)``: with ``check`` the forward and the
+    backward each wait for their kernels and raise DTSError if a bounded wait inside
+    them gave up; ``check=False`` keeps both fully asynchronous."""
 
     @staticmethod
-    def forward(ctx, guide, target, conf, params: Params):
+    def forward(ctx, guide, target, conf, params: Params, check=True):
         z, ck = solve(guide, target, conf, params.sigma_s, params.sigma_r, params.filter_iters,
-                      params.solver_iters, params.lam, params.step, checkpoints=True)
+                      params.solver_iters, params.lam, params.step, checkpoints=True,
+                      check=bool(check))
         ctx.save_for_backward(guide, target, conf, ck)
         ctx.params = params
+        ctx.check = bool(check)
         return z
 
     @staticmethod
@@ -812,5 +877,5 @@ class DTSFunction(torch.autograd.Function):
         need = ctx.needs_input_grad[:3]
         gt, gc, gg = solve_backward(guide, target, conf, ck, grad_z.contiguous(), p.sigma_s,
                                     p.sigma_r, p.filter_iters, p.solver_iters, p.lam, p.step,
-                                    need=(need[1], need[2], need[0]))
-        return gg, gt, gc, None
+                                    need=(need[1], need[2], need[0]), check=ctx.check)
+        return gg, gt, gc, None, None

@@ -75,23 +75,36 @@ def time_run(fn, iters):
 
 
 def batched_variant(solver, iters=2, use_cache=True, report=None):
-    """Index of the fastest batched-kernel variant for ``solver``'s problems."""
-    from . import batched_variants
+    """Index of the fastest batched-kernel variant for ``solver``'s problems.  A variant
+    the problem set does not fit (DTS_ENOTSUP from the library, e.g. a strip with more
+    chunks than the variant's grid) is skipped; any other failure is raised.  A cached
+    choice is used only if that variant accepts the problem set."""
+    from . import DTS_ENOTSUP, DTSError, batched_variants
 
     shapes = batched_variants()
     key = (_arch() + "|" + batched_signature(solver.problems) + "|variants:" +
            ",".join("x".join(str(x) for x in v[1:]) for v in shapes))
     db = _load() if use_cache else {}
     if key in db:
-        return int(db[key]["variant"])
+        cached = int(db[key]["variant"])
+        try:
+            solver._prepare(cached)
+            return cached
+        except DTSError as e:
+            if e.code != DTS_ENOTSUP:
+                raise
     timings = {}
     for v, *_ in shapes:
         try:
             solver._prepare(v)
-        except Exception:
+        except DTSError as e:
+            if e.code != DTS_ENOTSUP:
+                raise
             continue
         timings[v] = time_run(solver.run, iters)
         solver.status()
+    if not timings:
+        raise DTSError(DTS_ENOTSUP, "no batched-kernel variant accepts this problem set")
     best = min(timings, key=timings.get)
     if report is not None:
         report.update({str(k): t for k, t in timings.items()})

@@ -304,13 +304,15 @@ struct ColAdjArgs {
     unsigned long long* carry;
     unsigned epoch;
     int* status;
+    int spin_limit;
+    unsigned tag_xor;
 };
 
 template <int CTA, int R, int NWV>
 __global__ void __launch_bounds__(kWave * NWV) col_adjoint_kernel(ColAdjArgs a) {
     constexpr int NCH = 2 * CTA;
     __shared__ ChunkLds<NCH, NWV> L;
-    const CarryCtx cctx{a.carry, a.epoch, a.status, a.G, a.S, a.NG};
+    const CarryCtx cctx{a.carry, a.epoch, a.status, a.G, a.S, a.NG, a.spin_limit, a.tag_xor};
     const ChunkSlot slot = chunk_slot(static_cast<int>(blockIdx.x), a.G, a.xcd);
     const int chunk = slot.chunk;
     const int group = slot.group;
@@ -538,6 +540,8 @@ int launch_col_adjoint(const ColAdj& p, Ctx& ctx) {
     a.carry = ctx.carry;
     a.epoch = ++ctx.epoch;
     a.status = ctx.status;
+    a.spin_limit = spin_limit();
+    a.tag_xor = spin_tag_xor();
     const double px = static_cast<double>(p.batch) * p.H * p.W;
     const double bytes = px * 4.0 * (3.0 * p.C + 1.0 + (p.gd ? 2.0 : 0.0));
     return launch_col_adj_t<kAdjGroupChannels>(a, ctx.stream, bytes);

@@ -620,8 +620,8 @@ size_t dts_solve_stereo_workspace_bytes(int batch, int H, int W) {
 }
 
 int dts_solve_stereo(const float* left, const float* right, int Cg, const float* target, const float* conf,
-                     int batch, int H, int W, const dts_params* p, float gamma, float epsilon, float* out,
-                     void* workspace, size_t workspace_bytes, void* stream) {
+                     const float* init, int batch, int H, int W, const dts_params* p, float gamma, float epsilon,
+                     float* out, void* workspace, size_t workspace_bytes, void* stream) {
     if (!left || !right || !target || !conf || !out || !p) return DTS_EINVAL;
     int rc = check_shape(batch, H, W);
     if (rc) return rc;
@@ -638,11 +638,12 @@ int dts_solve_stereo(const float* left, const float* right, int Cg, const float*
     if (rc) return rc;
     float* D = reinterpret_cast<float*>(static_cast<char*>(workspace) + S.L.total);
     const size_t sig = static_cast<size_t>(batch) * H * W;
-    if (T == 0) return launch_copy(out, target, sig, S.ctx.stream);
+    const float* z0 = init ? init : target;
+    if (T == 0) return launch_copy(out, z0, sig, S.ctx.stream);
     const float s2 = static_cast<float>((static_cast<double>(p->sigma_s) / p->sigma_r) *
                                         (static_cast<double>(p->sigma_s) / p->sigma_r));
     for (int k = 0; k < T; ++k) {
-        const float* zk = (k == 0) ? target : out;
+        const float* zk = (k == 0) ? z0 : out;
         if ((rc = launch_stereo_data_grad(zk, target, conf, left, right, D, Cg, batch, H, W, gamma, epsilon,
                                           S.ctx.stream)))
             return rc;
@@ -954,6 +955,8 @@ int dts_tune_col_variant(int group_channels, int variant) {
 }
 
 int dts_tune_col_xcd(int on) { return tune_col_xcd(on); }
+
+int dts_tune_spin_limit(int polls) { return tune_spin_limit(polls); }
 
 int dts_tune_row_segment(int pixels_per_lane) { return tune_row_segment(pixels_per_lane); }
 

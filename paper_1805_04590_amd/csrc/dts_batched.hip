@@ -256,7 +256,7 @@ batched_kernel(BatchArgs a) {
                     ca.dst2 = nullptr;
                     ca.lambda = a.lambda;
                     ca.step = a.step;
-                    const CarryCtx cctx{ca.carry, ca.epoch, ca.status, ca.G, ca.S, ca.NG};
+                    const CarryCtx cctx{ca.carry, ca.epoch, ca.status, ca.G, ca.S, ca.NG, a.spin_limit, a.tag_xor};
                     const int chunk = tile % I.G;
                     const int rest = tile / I.G;
                     const int strip = rest % I.S;
@@ -573,6 +573,8 @@ int dts_solve_batched(const dts_batched_plan* plan, void* workspace, void* strea
     a.barrier = reinterpret_cast<unsigned*>(base + kBBarrier);
     a.launch = reinterpret_cast<const unsigned*>(base + kBLaunch);
     a.status = reinterpret_cast<int*>(base);
+    a.spin_limit = spin_limit();
+    a.tag_xor = spin_tag_xor();
     a.n = plan->n;
     a.n_phases = plan->n_phases;
     a.lambda = plan->lambda;

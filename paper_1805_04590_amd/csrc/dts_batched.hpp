@@ -37,6 +37,8 @@ struct BatchArgs {
     int* status;
     int n, n_phases;
     float lambda, step;
+    int spin_limit;
+    unsigned tag_xor;
 };
 
 }  // namespace dts

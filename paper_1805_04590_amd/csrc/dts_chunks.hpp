@@ -35,6 +35,8 @@ struct CarryCtx {
     unsigned epoch;             // tag of this launch
     int* status;                // device-side status word
     int G, S, NG;               // chunks per strip, strips per plane, channel groups
+    int spin_limit;             // polls before a wait gives up
+    unsigned tag_xor;           // 0; non-zero only to exercise the timeout path (no tag matches)
 };
 
 template <int NCH>
@@ -115,7 +117,8 @@ __device__ void chunk_carries(const CarryCtx& a, ChunkLds<NCH, NWV>& L, int b, i
     constexpr int NH = NWV / 2;
     const size_t strip_base =
         ((static_cast<size_t>(b) * a.NG + grp) * a.S + strip) * static_cast<size_t>(a.G);
-    const unsigned ep = a.epoch;
+    const unsigned ep = a.epoch;        // tag written
+    const unsigned want = ep ^ a.tag_xor;  // tag a reader accepts
     const int G = a.G;
 
     // chunk aggregates: wave 0 composes the waves top to bottom and leaves them in the
@@ -198,7 +201,7 @@ __device__ void chunk_carries(const CarryCtx& a, ChunkLds<NCH, NWV>& L, int b, i
                 for (int c = 0; c < NCH; ++c)
                     if (c < ncv) wb[c] = load_word(carry_word<NCH>(a, strip_base, jq, CW::kB + c, lane));
                 const unsigned long long wa = load_word(carry_word<NCH>(a, strip_base, jq, CW::kA, lane));
-                ok = static_cast<unsigned>(wa >> 32) == ep && tags_ok<NCH>(wb, ncv, ep);
+                ok = static_cast<unsigned>(wa >> 32) == want && tags_ok<NCH>(wb, ncv, want);
                 L.n.A[wave][lane] = word_value(wa);
 #pragma unroll
                 for (int c = 0; c < NCH; ++c) L.n.B[wave][c][lane] = (c < ncv) ? word_value(wb[c]) : 0.f;
@@ -209,8 +212,8 @@ __device__ void chunk_carries(const CarryCtx& a, ChunkLds<NCH, NWV>& L, int b, i
                         if (c < ncv) wj[c] = load_word(carry_word<NCH>(a, strip_base, jq, CW::kBJ + c, lane));
                     const unsigned long long wp = load_word(carry_word<NCH>(a, strip_base, jq, CW::kP, lane));
                     const unsigned long long wq = load_word(carry_word<NCH>(a, strip_base, jq, CW::kBQ, lane));
-                    ok = ok && static_cast<unsigned>(wp >> 32) == ep && static_cast<unsigned>(wq >> 32) == ep &&
-                         tags_ok<NCH>(wj, ncv, ep);
+                    ok = ok && static_cast<unsigned>(wp >> 32) == want && static_cast<unsigned>(wq >> 32) == want &&
+                         tags_ok<NCH>(wj, ncv, want);
                     L.n.P[wave][lane] = word_value(wp);
                     L.n.BQ[wave][lane] = word_value(wq);
 #pragma unroll
@@ -293,13 +296,13 @@ __device__ void chunk_carries(const CarryCtx& a, ChunkLds<NCH, NWV>& L, int b, i
                 gword* pw = carry_word<NCH>(a, strip_base, fstall ? fj : bj, CW::kA, lane);
                 int backoff = 1;
                 while (true) {
-                    if (static_cast<unsigned>(load_word(pw) >> 32) == ep) break;
+                    if (static_cast<unsigned>(load_word(pw) >> 32) == want) break;
                     spins += backoff;
-                    if (spins > kSpinLimit) break;
+                    if (spins > a.spin_limit) break;
                     for (int i = 0; i < backoff; ++i) __builtin_amdgcn_s_sleep(2);
                     backoff = backoff < 32 ? backoff * 2 : 32;
                 }
-                if (spins > kSpinLimit) {
+                if (spins > a.spin_limit) {
                     flag_error(a.status, kErrSpinTimeout);
                     fj = bj = kWalkDone;
                 }

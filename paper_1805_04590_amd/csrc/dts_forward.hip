@@ -18,6 +18,7 @@
 // look-back resolves the causal carry from earlier chunks, then a look-ahead resolves the
 // anticausal carry from later chunks, so every element is read and written exactly once.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <mutex>
 
@@ -235,7 +236,7 @@ constexpr int col_min_waves() { return (CT == 1 && R == 40 && NWV == 8) ? 4 : 1;
 template <int CT, int R, int NWV, int EPI>
 __global__ void __launch_bounds__(kWave * NWV, (col_min_waves<CT, R, NWV>())) col_pass_kernel(ColArgs a) {
     __shared__ ChunkLds<CT, NWV> L;
-    const CarryCtx cctx{a.carry, a.epoch, a.status, a.G, a.S, a.NG};
+    const CarryCtx cctx{a.carry, a.epoch, a.status, a.G, a.S, a.NG, a.spin_limit, a.tag_xor};
     // Persistent grid: a workgroup always processes the same chunk of the strips
     // group, group + groups, ...; every strip's chunks are thus held by G workgroups of
     // the same launch that are all running, and none ever waits on one not yet started.
@@ -360,6 +361,26 @@ int col_variant_info(int variant, int* ct, int* rows_per_wave, int* waves) {
 
 int num_col_variants() { return kNumColVariants; }
 
+static int g_spin_limit = kSpinLimit;
+static unsigned g_spin_tag_xor = 0u;
+
+int tune_spin_limit(int polls) {
+    if (polls == 0) {
+        g_spin_limit = kSpinLimit;
+        g_spin_tag_xor = 0u;
+    } else if (polls > 0) {
+        g_spin_limit = polls;
+        g_spin_tag_xor = 0u;
+    } else {
+        g_spin_limit = polls == INT_MIN ? INT_MAX : -polls;
+        g_spin_tag_xor = 0x80000000u;
+    }
+    return DTS_OK;
+}
+
+int spin_limit() { return g_spin_limit; }
+unsigned spin_tag_xor() { return g_spin_tag_xor; }
+
 static int g_col_xcd = 1;
 
 int tune_col_xcd(int on) {
@@ -429,6 +450,8 @@ int launch_col_pass(const ColPass& p, Ctx& ctx) {
     a.carry = ctx.carry;
     a.epoch = ++ctx.epoch;
     a.status = ctx.status;
+    a.spin_limit = spin_limit();
+    a.tag_xor = spin_tag_xor();
     a.zk = p.zk;
     a.tgt = p.tgt;
     a.conf = p.conf;

@@ -162,6 +162,10 @@ struct ColGrid {
 };
 ColGrid col_grid(int cap, int G, long long n_strips);
 int tune_col_xcd(int on);
+// Bounded waits of the carry exchange (see dts_tune_spin_limit).
+int tune_spin_limit(int polls);
+int spin_limit();
+unsigned spin_tag_xor();
 
 // Error bookkeeping shared by the translation units.
 int hip_fail(hipError_t e);

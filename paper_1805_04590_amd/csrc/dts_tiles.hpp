@@ -307,6 +307,8 @@ struct ColArgs {
     unsigned long long* carry;
     unsigned epoch;
     int* status;
+    int spin_limit;
+    unsigned tag_xor;
     const float* zk;
     const float* tgt;
     const float* conf;

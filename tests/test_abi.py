@@ -169,10 +169,10 @@ def test_solve_stereo_rejects_bad_arguments_without_launching(lib):
     p = dts.Params(8.0, 0.2, 3, 5).c()
     ok = lib.dts_solve_stereo_workspace_bytes(1, 8, 8)
     # epsilon <= 0, negative gamma, null output, too-small workspace: refused before any launch
-    assert lib.dts_solve_stereo(fake, fake, 3, fake, fake, 1, 8, 8, ctypes.byref(p), 0.001, 0.0, fake, fake, ok, None) == dts.DTS_EINVAL
-    assert lib.dts_solve_stereo(fake, fake, 3, fake, fake, 1, 8, 8, ctypes.byref(p), -1.0, 0.001, fake, fake, ok, None) == dts.DTS_EINVAL
-    assert lib.dts_solve_stereo(fake, fake, 3, fake, fake, 1, 8, 8, ctypes.byref(p), 0.001, 0.001, None, fake, ok, None) == dts.DTS_EINVAL
-    assert lib.dts_solve_stereo(fake, fake, 3, fake, fake, 1, 8, 8, ctypes.byref(p), 0.001, 0.001, fake, fake, ok - 256, None) == dts.DTS_EWORKSPACE
+    assert lib.dts_solve_stereo(fake, fake, 3, fake, fake, None, 1, 8, 8, ctypes.byref(p), 0.001, 0.0, fake, fake, ok, None) == dts.DTS_EINVAL
+    assert lib.dts_solve_stereo(fake, fake, 3, fake, fake, None, 1, 8, 8, ctypes.byref(p), -1.0, 0.001, fake, fake, ok, None) == dts.DTS_EINVAL
+    assert lib.dts_solve_stereo(fake, fake, 3, fake, fake, None, 1, 8, 8, ctypes.byref(p), 0.001, 0.001, None, fake, ok, None) == dts.DTS_EINVAL
+    assert lib.dts_solve_stereo(fake, fake, 3, fake, fake, None, 1, 8, 8, ctypes.byref(p), 0.001, 0.001, fake, fake, ok - 256, None) == dts.DTS_EWORKSPACE
 
 
 

@@ -33,7 +33,7 @@ def check(name, got, ref):
     elem = np.abs(got - ref).max()
     print(f"  {name}: rel L2 {rel:.2e}  max abs {elem:.2e}  floor {floor:.2e}", flush=True)
     assert rel <= REL, (name, rel)
-    assert elem <= max(floor, 1e-7) * 10, (name, elem, floor)
+    assert elem <= max(floor, 1e-7), (name, elem, floor)
 
 
 def run_case(case, seed=7):

@@ -9,10 +9,12 @@ The multispectral 10240 x 10240 solve (16-band guide, T = 10) is checked three w
   confidence is a fixed point.
 The 8 x 1024^2 batch (T = 15) runs whole on the GPU; two of its images are compared with
 the oracle's forward solve.
-The 8 x 1024^2 forward + backward (T = 15) is checked by directional derivatives of its
-loss sum((z - r)^2).  The solve is linear in the target, so along a target direction the
-loss is quadratic and a central difference is exact up to rounding; along a confidence
-direction a small step bounds the truncation error.
+The 8 x 1024^2 forward + backward (T = 15) is checked two ways: all three gradients of
+one full image against the oracle's FP64 adjoint, element by element; and directional
+derivatives of the loss sum((z - r)^2) over the whole batch.  The solve is linear in the
+target, so along a target direction the loss is quadratic and a central difference is
+exact up to rounding; along confidence and guide directions a small step bounds the
+truncation error (the distances are smooth in the guide since d >= 1).
 """
 import numpy as np
 import pytest
@@ -101,7 +103,7 @@ def test_rgb_batch_8x1024_gradients_match_directional_derivatives():
     g, t, cf, r = (torch.from_numpy(c[k]).cuda() for k in ("guide", "target", "conf", "ref"))
     ss, sr, N, T = c["sigma_s"], c["sigma_r"], c["filter_iters"], c["solver_iters"]
     z, ck = dts.solve(g, t, cf, ss, sr, N, T, checkpoints=True)
-    gt, gc, _ = dts.solve_backward(g, t, cf, ck, (2.0 * (z - r)).contiguous(), ss, sr, N, T)
+    gt, gc, gg = dts.solve_backward(g, t, cf, ck, (2.0 * (z - r)).contiguous(), ss, sr, N, T)
     gen = torch.Generator(device="cuda").manual_seed(5)
     # target: exact central difference (the loss is quadratic in t)
     v = torch.randn(t.shape, generator=gen, device="cuda")
@@ -112,10 +114,46 @@ def test_rgb_batch_8x1024_gradients_match_directional_derivatives():
     note("target: adjoint", an, "central difference", fd)
     assert abs(an - fd) <= 1e-3 * abs(fd)
     # confidence: a small step keeps c inside [0.1, 1] and the truncation error small
+    # (measured at this step: 4e-5 relative; smaller steps are dominated by the fp32
+    # rounding of the forward solves)
     v = torch.rand(cf.shape, generator=gen, device="cuda") - 0.5
-    eps = 1e-3
+    eps = 3e-3
     fd = (_loss(dts.solve(g, t, cf + eps * v, ss, sr, N, T), r)
           - _loss(dts.solve(g, t, cf - eps * v, ss, sr, N, T), r)) / (2 * eps)
     an = float((gc.double() * v.double()).sum())
     note("confidence: adjoint", an, "central difference", fd)
-    assert abs(an - fd) <= 1e-2 * abs(fd)
+    assert abs(an - fd) <= 1e-3 * abs(fd)
+    # guide: the loss is smooth in the guide (d >= 1).  Truncation grows above this step
+    # and the forward's fp32 rounding below it, so the best central difference agrees to
+    # about 9e-4 (measured); the element-wise FP64 comparison above is the 1e-3 check.
+    v = torch.rand(g.shape, generator=gen, device="cuda") - 0.5
+    eps = 1e-3
+    fd = (_loss(dts.solve(g + eps * v, t, cf, ss, sr, N, T), r)
+          - _loss(dts.solve(g - eps * v, t, cf, ss, sr, N, T), r)) / (2 * eps)
+    an = float((gg.double() * v.double()).sum())
+    note("guide: adjoint", an, "central difference", fd)
+    assert abs(an - fd) <= 2e-3 * abs(fd)
+
+
+def test_rgb_batch_8x1024_gradients_match_oracle_on_one_image():
+    c = dts_inputs.rgb_batch_8x1024()
+    ss, sr, N, T = c["sigma_s"], c["sigma_r"], c["filter_iters"], c["solver_iters"]
+    note("8 x 1024^2 forward + backward on the GPU")
+    g, t, cf, r = (torch.from_numpy(c[k]).cuda() for k in ("guide", "target", "conf", "ref"))
+    z, ck = dts.solve(g, t, cf, ss, sr, N, T, checkpoints=True)
+    gt, gc, gg = dts.solve_backward(g, t, cf, ck, (2.0 * (z - r)).contiguous(), ss, sr, N, T)
+    got = {k: v[3].double().cpu().numpy() for k, v in (("target", gt), ("conf", gc), ("guide", gg))}
+    del z, ck, gt, gc, gg
+    b = 3
+    note("oracle forward + adjoint of image", b, "(about a minute)")
+    zr = oracle.solve(c["guide"][b], c["target"][b], c["conf"][b], ss, sr, N, T)
+    rt, rc, rg = oracle.solve_backward(c["guide"][b], c["target"][b], c["conf"][b], ss, sr,
+                                       2.0 * (zr - c["ref"][b]), N, T)
+    for name, ref in (("target", rt), ("conf", rc), ("guide", rg)):
+        err = got[name] - ref
+        rel = float(np.linalg.norm(err) / np.linalg.norm(ref))
+        elem = float(np.abs(err).max())
+        floor = 1e-3 * float(np.abs(ref).max())
+        note(name, "rel L2", rel, "max abs", elem, "floor", floor)
+        assert rel <= 1e-3, (name, rel)
+        assert elem <= floor, (name, elem, floor)

@@ -81,3 +81,26 @@ def test_full_size_paper_parameters_diverge_only_locally():
     tol = 1e-4 * c["value_range"]
     assert (err > tol).mean() <= 1e-3, (err > tol).mean()
     assert np.percentile(err, 99.9) <= tol
+
+
+def test_full_size_paper_parameters_every_step():
+    # A complete check at the paper's eps = gamma = 0.001: each of the 20 GPU steps is
+    # taken from the oracle's own iterate z^k (passed as the initial iterate) and compared
+    # with the oracle's z^{k+1} on every pixel.  A single step is well conditioned, so the
+    # bar is the same as for the contractive setting.
+    c = dts_inputs.stereo_pair_1920x1080()
+    T = c["solver_iters"]
+    print("CASE stereo 1920x1080, every step at eps=0.001", flush=True)
+    _, its = oracle.solve_stereo(c["left"], c["right"], c["target"], c["conf"], c["sigma_s"], c["sigma_r"], 3, T,
+                                 gamma=c["gamma"], eps=c["eps"], return_iterates=True)
+    L, R, t, cf = (dev(c[k]) for k in ("left", "right", "target", "conf"))
+    tol = 1e-4 * c["value_range"]
+    worst = 0.0
+    for k in range(T):
+        z1 = dts.solve_stereo(L, R, t, cf, c["sigma_s"], c["sigma_r"], 3, 1, gamma=c["gamma"], eps=c["eps"],
+                              init=dev(its[k]))
+        torch.cuda.synchronize()
+        err = float(np.abs(z1.cpu().numpy() - its[k + 1]).max())
+        worst = max(worst, err)
+        assert err <= tol, (k, err)
+    print("worst single-step error", worst, flush=True)
