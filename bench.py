@@ -86,6 +86,26 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# GPU outputs of the other workloads kept on the host for the CPU leg, which compares them
+# with the oracle: {name: (inputs, gpu output)}
+SAMPLES = {}
+BATCHED_SAMPLE_INSTANCES = (42, 57, 26)  # Cg, Ct = (8, 1), (16, 3), (1, 3): small instances
+
+
+def host_info():
+    """Logical CPUs and the CPU model of this host."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return os.cpu_count(), model
+
+
 def cpu_baseline(rows):
     """Time the FP64 oracle on a full-width band of the workload (same generator)."""
     import dts_inputs
@@ -116,12 +136,22 @@ def cpu_baseline(rows):
         threads = max(p.get("num_threads", 1) for p in threadpoolctl.threadpool_info()) or 1
     except Exception:
         threads = 1
+    # the other workloads' GPU outputs against the oracle (max abs error over the
+    # sample, divided by the signal's value range where it is not 1)
+    errs = {}
+    for name, (inp, got) in SAMPLES.items():
+        ref = oracle.solve(inp["guide"], inp["target"], inp["conf"], inp["sigma_s"], inp["sigma_r"],
+                           inp["filter_iters"], inp["solver_iters"])
+        errs[name] = float(np.abs(got - ref).max()) / inp.get("value_range", 1.0)
+        log(f"  oracle vs GPU, {name}: {errs[name]:.3e}")
+    ncpu, model = host_info()
     return dict(value=px / dt / 1e6, unit="Mpixel/s", cores=1, kind="oracle",
                 sample=(f"rows 0-{rows} x all {case['target'].shape[2]} columns of the same "
                         f"workload, full solve (T={case['solver_iters']}), FP64 NumPy; "
                         f"{dt:.1f} s; elementwise NumPy runs on one core "
                         f"(BLAS pool {threads} threads unused)"),
-                gpu_max_abs_err=err, seconds=dt)
+                host_logical_cpus=ncpu, host_cpu_model=model,
+                gpu_max_abs_err=err, gpu_max_abs_err_by_workload=errs, seconds=dt)
 
 
 def timed(fn, steps, warmup):
@@ -177,6 +207,10 @@ def batched_leg(steps, warmup, graph=True, variant=None, sequential=True):
 
     ms_s = timed(seq, steps, warmup)
     err = max((o - b).abs().max().item() for o, b in zip(outs, bs.outputs))
+    for i in BATCHED_SAMPLE_INSTANCES:
+        c = cases[i]
+        SAMPLES[f"uneven_batch_64 instance {i} (batched kernel)"] = (
+            dict(c, filter_iters=3, solver_iters=10), bs.outputs[i].cpu().numpy())
     return dict(workload="64 uneven solves 320-1920 x 240-1080, Cg in {1,3,8,16}, Ct 1-3, T=10",
                 pixels=px, variant=bs.variant, launch="hip graph replay" if graph else "direct", batched_ms=round(ms_b, 3),
                 batched_mpix_s=round(px / ms_b / 1e3, 1), sequential_ms=round(ms_s, 3),
@@ -223,11 +257,28 @@ def fwd_bwd_leg(steps, warmup):
 
     ms_f = timed(fwd, steps, warmup)
     ms_fb = timed(fwd_bwd, steps, warmup)
+    dts.workspace_status(ws)
+    dts.workspace_status(wsb)
+    SAMPLES["rgb_batch_8x1024 image 0 forward"] = (
+        dict(guide=c["guide"][0], target=c["target"][0], conf=c["conf"][0], sigma_s=c["sigma_s"],
+             sigma_r=c["sigma_r"], filter_iters=3, solver_iters=T), state["z"][0].cpu().numpy())
     px = B * H * W
+    # algorithmic bytes of every launch of one forward + backward, from the library's own
+    # per-launch records (forward passes with checkpoints, recomputed passes, adjoint passes)
+    kernels, stats = kernel_table(fwd_bwd, 2)
+    fb_bytes = sum(s["bytes_per_launch"] * s["launches"] for s in stats.values()) / 2
+    kern = {k: dict(launches_per_step=round(v["launches_per_step"], 2), avg_us=round(v["avg_us"], 2),
+                    share=round(v["share"], 4), algorithmic_GBps=round(v["algorithmic_GBps"], 1),
+                    hbm_frac=round(v["algorithmic_GBps"] / HBM_PEAK_GBPS, 4))
+            for k, v in kernels.items()}
     return dict(workload="8 x 1024x1024 RGB -> 3 channels, T=15, loss sum((z-r)^2)", pixels=px,
                 fwd_ms=round(ms_f, 3), fwd_mpix_s=round(px / ms_f / 1e3, 1),
                 fwd_bwd_ms=round(ms_fb, 3), fwd_bwd_mpix_s=round(px / ms_fb / 1e3, 1),
-                fwd_bwd_over_fwd=round(ms_fb / ms_f, 3))
+                fwd_bwd_over_fwd=round(ms_fb / ms_f, 3),
+                fwd_bwd_algorithmic_bytes=fb_bytes,
+                algorithmic_GBps=round(fb_bytes / (ms_fb / 1e3) / 1e9, 1),
+                hbm_frac=round(fb_bytes / (ms_fb / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
+                kernels=kern)
 
 
 def kernel_table(step, steps):
@@ -318,6 +369,17 @@ def solve_leg(args, dev):
                         unit="GB/s", frac=round(achieved / HBM_PEAK_GBPS, 4),
                         traffic=recorded_traffic(dom),
                         bytes_per_launch=s["bytes_per_launch"], avg_us=round(s["avg_ms"] * 1e3, 2))
+        # every filter-pass kernel of the solve, and their time-weighted aggregate: the
+        # dominant kernel alone does not show the slower ones
+        tot_b = sum(v["bytes_per_launch"] * v["launches"] for v in stats.values())
+        tot_s = sum(v["total_ms"] for v in stats.values()) / 1e3
+        roofline["filter_passes"] = dict(
+            achieved=round(tot_b / tot_s / 1e9, 1), frac=round(tot_b / tot_s / 1e9 / HBM_PEAK_GBPS, 4),
+            per_kernel={k: dict(avg_us=round(v["avg_ms"] * 1e3, 2),
+                                achieved=round(v["bytes_per_launch"] / (v["avg_ms"] / 1e3) / 1e9, 1),
+                                frac=round(v["bytes_per_launch"] / (v["avg_ms"] / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),
+                                traffic=recorded_traffic(k))
+                        for k, v in stats.items()})
         log("  " + json.dumps(kernels))
 
     # Eq. (7): confidence from the edge-aware variance of the target, same guide
@@ -515,6 +577,7 @@ def graph_leg(steps, warmup):
         ms_e = timed(lambda: dts.solve(sg.guide, sg.target, sg.conf, *args, out=sg.out, workspace=sg.workspace),
                      steps * 4, warmup)
         ms_g = timed(sg.replay, steps * 4, warmup)
+        SAMPLES[name.replace("_T", " T=") + " (graph replay)"] = (c, sg.out[0].cpu().numpy())
         px = t.shape[-1] * t.shape[-2]
         res[name] = dict(eager_ms=round(ms_e, 4), graph_ms=round(ms_g, 4), eager_mpix_s=round(px / ms_e / 1e3, 1),
                          graph_mpix_s=round(px / ms_g / 1e3, 1), speedup=round(ms_e / ms_g, 3))
