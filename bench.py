@@ -23,37 +23,42 @@ sys.path.insert(0, ROOT)
 METRIC = "DTS solve Mpixel/s & % of HBM peak; batched and fwd+bwd vs plain fwd"
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "solve_10240x10240_hbm_traffic.md")
+FWD_BWD_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "fwd_bwd_8x1024_hbm_traffic.md")
 
 
-def sources_digest():
-    """SHA-256 over the library's sources: hardware-counter traffic recorded for one
-    digest is reported only while the kernels are unchanged."""
+def sources_digest(names=None):
+    """SHA-256 over library sources (`names`: file names under csrc/ plus dts.h; None: all
+    of them): hardware-counter traffic recorded for one digest is reported only while the
+    sources its kernels are built from are unchanged."""
     import hashlib
 
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1805_04590_amd", "csrc")
     files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc) if f.endswith((".hip", ".hpp")))
-    for path in files + [os.path.join(ROOT, "include", "dts.h")]:
+    files += [os.path.join(ROOT, "include", "dts.h")]
+    if names is not None:
+        files = [f for f in files if os.path.basename(f) in set(names)]
+    for path in files:
         h.update(os.path.basename(path).encode())
         with open(path, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def recorded_traffic(kernel):
+def recorded_traffic(kernel, profile=TRAFFIC_PROFILE):
     """HBM bytes per launch of `kernel` measured with rocprofv3 FETCH_SIZE / WRITE_SIZE
     (scaled by a plain copy of known size), or None when no record matches these sources."""
     import re
 
     try:
-        text = open(TRAFFIC_PROFILE).read()
+        text = open(profile).read()
     except OSError:
         return None
     m = re.search(r"<!-- traffic: (\{.*?\}) -->", text, flags=re.S)
     if not m:
         return None
     rec = json.loads(m.group(1))
-    if rec.get("sources_sha256") != sources_digest():
+    if rec.get("sources_sha256") != sources_digest(rec.get("sources")):
         return None
     k = rec.get("kernels", {}).get(kernel)
     return None if k is None else k.get("traffic_bytes")
@@ -76,6 +81,8 @@ def parse():
     ap.add_argument("--batched-only", type=int, default=None, metavar="VARIANT",
                     help="profiling mode: only the 64 uneven solves, batched kernel variant VARIANT, "
                          "direct launches, no one-by-one comparison")
+    ap.add_argument("--fwd-bwd-only", action="store_true",
+                    help="profiling mode: only the 8 x 1024^2 forward + backward leg")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first fill and copy a MIB-sized float32 buffer with torch: kernels of "
                          "known traffic that calibrate the hardware byte counters")
@@ -269,7 +276,8 @@ def fwd_bwd_leg(steps, warmup):
     fb_bytes = sum(s["bytes_per_launch"] * s["launches"] for s in stats.values()) / 2
     kern = {k: dict(launches_per_step=round(v["launches_per_step"], 2), avg_us=round(v["avg_us"], 2),
                     share=round(v["share"], 4), algorithmic_GBps=round(v["algorithmic_GBps"], 1),
-                    hbm_frac=round(v["algorithmic_GBps"] / HBM_PEAK_GBPS, 4))
+                    hbm_frac=round(v["algorithmic_GBps"] / HBM_PEAK_GBPS, 4),
+                    traffic=recorded_traffic(k, FWD_BWD_TRAFFIC_PROFILE))
             for k, v in kernels.items()}
     return dict(workload="8 x 1024x1024 RGB -> 3 channels, T=15, loss sum((z-r)^2)", pixels=px,
                 fwd_ms=round(ms_f, 3), fwd_mpix_s=round(px / ms_f / 1e3, 1),
@@ -608,6 +616,10 @@ def main():
         log(f"calibration: fill and 3 copies of {4 * n} bytes")
         del a, b
         torch.cuda.empty_cache()
+    if args.fwd_bwd_only:
+        log("forward+backward leg only (profiling mode) ...")
+        log("  " + json.dumps(fwd_bwd_leg(args.steps, args.warmup)))
+        return
     if args.batched_only is not None:
         log("batched solves only (profiling mode) ...")
         b = batched_leg(args.steps, args.warmup, graph=False, variant=args.batched_only, sequential=False)

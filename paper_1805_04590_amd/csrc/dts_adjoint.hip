@@ -401,6 +401,19 @@ __global__ void __launch_bounds__(kWave * NWV) col_adjoint_kernel(ColAdjArgs a) 
             L.B[wave][c][lane] = Xl[c];
             L.BJ[wave][c][lane] = BJ[c];
         }
+        // The distance-gradient accumulator is read here so that its loads are in flight
+        // during the carry exchange; it is updated and written back at the end.
+        float gacc[R];
+        const auto gdrs = plane_rsrc(a.gd ? a.gd + (static_cast<size_t>(grp) * a.batch + b) * plane : a.d,
+                                     a.gd ? pbytes : 0);
+        {
+            unsigned vo = voff;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                gacc[r] = bload(gdrs, vo, 0);
+                vo = opaque_vadd(vo, rowb);
+            }
+        }
         __syncthreads();
         chunk_carries<NCH, NWV>(cctx, L, b, grp, strip, chunk, lane, wave, valid, 2 * ncv);
         __syncthreads();
@@ -421,9 +434,6 @@ __global__ void __launch_bounds__(kWave * NWV) col_adjoint_kernel(ColAdjArgs a) 
             }
         }
         // backward sweep: K and sigma, then dL/df and dL/dw per row
-        float gdacc[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) gdacc[r] = 0.f;
 #pragma unroll
         for (int c = 0; c < CTA; ++c) {
             if (c < ncv) {
@@ -441,24 +451,16 @@ __global__ void __launch_bounds__(kWave * NWV) col_adjoint_kernel(ColAdjArgs a) 
                     const float jm = (r == 0) ? Xin[2 * c] : X[2 * c][r > 0 ? r - 1 : 0];
                     const float rm = (r == 0) ? Xin[2 * c + 1] : X[2 * c + 1][r > 0 ? r - 1 : 0];
                     const float gw = fmaf(ss, jm - f[c][r], rm * (kk - jm));
-                    gdacc[r] = fmaf(gw * w[r], a.ln_a, gdacc[r]);
+                    gacc[r] = fmaf(gw * w[r], a.ln_a, gacc[r]);
                     vo = opaque_vadd(vo, 0u - rowb);
                 }
             }
         }
         if (a.gd) {
-            const auto grs = plane_rsrc(a.gd + (static_cast<size_t>(grp) * a.batch + b) * plane, pbytes);
             unsigned vo = voff;
-            float cur[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                cur[r] = bload(grs, vo, 0);
-                vo = opaque_vadd(vo, rowb);
-            }
-            vo = voff;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                bstore(grs, vo, 0, cur[r] + gdacc[r]);
+                bstore(gdrs, vo, 0, gacc[r]);
                 vo = opaque_vadd(vo, rowb);
             }
         }
