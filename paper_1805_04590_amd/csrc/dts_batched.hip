@@ -374,10 +374,11 @@ static Geo geometry(const dts_problem& q, const BatchVariant& v) {
         g.row_S = q.W <= 512 ? 8 : 16;
         g.row_gw = 1;
     } else {
-        g.row_S = 16;
-        const int waves = (q.W + kBatchSoloWidth - 1) / kBatchSoloWidth;
-        g.row_gw = 1;
-        while (g.row_gw < waves) g.row_gw *= 2;
+        // wider rows: the whole workgroup on one row at a time, 8 pixels per lane up to
+        // 2048 (measured on the 64 uneven solves: 529 against 600 us per row phase for
+        // two rows side by side at 16 pixels per lane), 16 beyond
+        g.row_S = q.W <= 2 * kBatchSoloWidth ? 8 : 16;
+        g.row_gw = kBatchWaves;
     }
     const int side = kBatchWaves / g.row_gw;  // rows processed side by side
     const long long per_round = static_cast<long long>(q.W) * q.Ct * side;
