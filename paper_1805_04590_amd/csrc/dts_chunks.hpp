@@ -19,8 +19,10 @@
 //
 // Every weight is a^d with a < 1 and d >= 1 (Eq. (8)-(9)), so a carry fades by at least a
 // factor a per row.  A walk stops once the product of the factors still to be applied
-// falls below 2^-40: what it leaves out is below 2^-40 of the largest magnitude on the
-// line, far under one fp32 rounding of the result.  Where the product does not fall that
+// falls below 2^-40: what it leaves out is below 2^-40 of the largest magnitude the
+// recurrence takes on the line (for a filter pass, of the largest input; for an adjoint
+// pass at most 1 / (1 - a) times the largest input gradient), far under one fp32
+// rounding of the result.  Where the product does not fall that
 // far, the walk runs to the first or last chunk and is exact.  Which neighbours a chunk
 // composes, and in which order, depends on the data only, so a given launch shape gives
 // bitwise-identical results on every run.
@@ -87,7 +89,7 @@ struct ChunkLds {
 
 constexpr int kWalkDone = -0x40000000;
 
-// True when all `ncv` tagged words of channel block k carry the launch's epoch.
+// True when the first `ncv` of the tagged words carry the tag `ep`.
 template <int NCH>
 __device__ __forceinline__ bool tags_ok(const unsigned long long (&w)[NCH], int ncv, unsigned ep) {
     bool ok = true;
