@@ -335,3 +335,29 @@ def test_multi_chunk_solve_is_bitwise_reproducible(H, W, Ct):
         assert np.array_equal(host(dts.solve(g, t, c, 24.0, 0.2, 3, 3)), first), rep
     if H <= 2600:
         assert np.abs(first - oracle_solve(case)).max() <= SOLVE_TOL
+
+
+def test_column_chunk_placement_does_not_change_results():
+    # Chunks of a strip kept on one XCD (the default) or dealt round-robin: the carries a
+    # chunk composes are the same, so the column pass and the adjoint agree bit for bit.
+    H, W = 2600, 300
+    announce("column chunk placement", H, W)
+    case = dts_inputs.random_case(8300, H, W, 3, 2, Cc=2, sigma_s=20.0, sigma_r=0.2, T=2)
+    rdx, rdy = oracle.distances(case["guide"], 20.0, 0.2)
+    x, dy = dev(case["target"]), dev(rdy.astype(np.float32)[None])
+    g, t, c = dev(case["guide"]), dev(case["target"]), dev(case["conf"])
+    got = {}
+    try:
+        for on in (0, 1):
+            dts.tune_col_xcd(on)
+            z, ck = dts.solve(g, t, c, 20.0, 0.2, 3, 2, checkpoints=True)
+            grads = dts.solve_backward(g, t, c, ck, z, 20.0, 0.2, 3, 2)
+            got[on] = [host(dts.col_pass(x, dy, 20.0, 1, 3)), host(z)] + [host(q) for q in grads]
+    finally:
+        dts.tune_col_xcd(1)
+    for a, b in zip(got[0], got[1]):
+        assert np.array_equal(a, b)
+    a = oracle.feedback_coefficients(20.0, 3)[0]
+    ref = np.moveaxis(oracle.rf1d_lines(np.moveaxis(case["target"].astype(np.float64), -2, 0),
+                                        (a ** rdy)[:, None, :]), 0, -2)
+    assert np.abs(got[1][0][0] - ref).max() <= FILTER_TOL
