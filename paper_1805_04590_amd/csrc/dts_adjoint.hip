@@ -50,36 +50,6 @@ struct RowAdjArgs {
 
 constexpr int kMaxRowWavesAdj = 16;
 
-template <int S>
-__device__ __forceinline__ void seg_load(const float* row, int n0, int W, bool vec, float (&v)[S]) {
-    if (vec && n0 + S <= W) {
-#pragma unroll
-        for (int e = 0; e < S; e += 4) {
-            const float4 q = *reinterpret_cast<const float4*>(row + n0 + e);
-            v[e] = q.x;
-            v[e + 1] = q.y;
-            v[e + 2] = q.z;
-            v[e + 3] = q.w;
-        }
-    } else {
-#pragma unroll
-        for (int e = 0; e < S; ++e) v[e] = (n0 + e < W) ? row[n0 + e] : 0.f;
-    }
-}
-
-template <int S>
-__device__ __forceinline__ void seg_store(float* row, int n0, int W, bool vec, const float (&v)[S]) {
-    if (vec && n0 + S <= W) {
-#pragma unroll
-        for (int e = 0; e < S; e += 4)
-            *reinterpret_cast<float4*>(row + n0 + e) = make_float4(v[e], v[e + 1], v[e + 2], v[e + 3]);
-    } else {
-#pragma unroll
-        for (int e = 0; e < S; ++e)
-            if (n0 + e < W) row[n0 + e] = v[e];
-    }
-}
-
 template <int S, bool EPI>
 __global__ void __launch_bounds__(1024) row_adjoint_kernel(RowAdjArgs a) {
     __shared__ float fag[kMaxRowWavesAdj][3];
@@ -94,13 +64,12 @@ __global__ void __launch_bounds__(1024) row_adjoint_kernel(RowAdjArgs a) {
     const int H = a.H, W = a.W;
     const size_t plane = static_cast<size_t>(H) * W;
     const int n0 = (wave * kWave + lane) * S;
-    const bool vec = (W & 3) == 0;
     const size_t prow = static_cast<size_t>(b) * plane + static_cast<size_t>(y) * W;
 
     float w[S];
     {
         float dv[S];
-        seg_load<S>(a.d + prow, n0, W, vec, dv);
+        load_seg<S>(a.d + prow, n0, W, 0.f, dv);
 #pragma unroll
         for (int e = 0; e < S; ++e) {
             const int n = n0 + e;
@@ -120,8 +89,8 @@ __global__ void __launch_bounds__(1024) row_adjoint_kernel(RowAdjArgs a) {
     for (int c = 0; c < a.C; ++c) {
         const size_t roff = (static_cast<size_t>(b) * a.C + c) * plane + static_cast<size_t>(y) * W;
         float f[S], g[S];
-        seg_load<S>(a.f + roff, n0, W, vec, f);
-        seg_load<S>(a.gk + roff, n0, W, vec, g);
+        load_seg<S>(a.f + roff, n0, W, 0.f, f);
+        load_seg<S>(a.gk + roff, n0, W, 0.f, g);
 #pragma unroll
         for (int e = 0; e < S; ++e) g[e] *= a.gk_scale;
 
@@ -202,15 +171,15 @@ __global__ void __launch_bounds__(1024) row_adjoint_kernel(RowAdjArgs a) {
             const int cc = (a.Cc == 1) ? 0 : c;
             const size_t coff = (static_cast<size_t>(b) * a.Cc + cc) * plane + static_cast<size_t>(y) * W;
             float zk[S];
-            seg_load<S>(a.f + roff, n0, W, vec, zk);
+            load_seg<S>(a.f + roff, n0, W, 0.f, zk);
 #pragma unroll
             for (int e0 = 0; e0 < S; e0 += 4) {
                 float gzo[4], tt[4], cf[4], gto[4] = {0.f, 0.f, 0.f, 0.f}, gco[4] = {0.f, 0.f, 0.f, 0.f};
-                seg_load<4>(a.gz + roff, n0 + e0, W, vec, gzo);
-                seg_load<4>(a.tgt + roff, n0 + e0, W, vec, tt);
-                seg_load<4>(a.conf + coff, n0 + e0, W, vec, cf);
-                if (a.gt) seg_load<4>(a.gt + roff, n0 + e0, W, vec, gto);
-                if (a.gc) seg_load<4>(a.gc + coff, n0 + e0, W, vec, gco);
+                load_seg<4>(a.gz + roff, n0 + e0, W, 0.f, gzo);
+                load_seg<4>(a.tgt + roff, n0 + e0, W, 0.f, tt);
+                load_seg<4>(a.conf + coff, n0 + e0, W, 0.f, cf);
+                if (a.gt) load_seg<4>(a.gt + roff, n0 + e0, W, 0.f, gto);
+                if (a.gc) load_seg<4>(a.gc + coff, n0 + e0, W, 0.f, gco);
                 float gzn[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
@@ -220,21 +189,21 @@ __global__ void __launch_bounds__(1024) row_adjoint_kernel(RowAdjArgs a) {
                     if (a.last) gto[q] += gzn[q];
                     gco[q] = fmaf(a.step * (tt[q] - zk[e0 + q]), gzo[q], gco[q]);
                 }
-                seg_store<4>(a.gz + roff, n0 + e0, W, vec, gzn);
-                if (a.gt) seg_store<4>(a.gt + roff, n0 + e0, W, vec, gto);
-                if (a.gc) seg_store<4>(a.gc + coff, n0 + e0, W, vec, gco);
+                store_seg<4>(a.gz + roff, n0 + e0, W, gzn);
+                if (a.gt) store_seg<4>(a.gt + roff, n0 + e0, W, gto);
+                if (a.gc) store_seg<4>(a.gc + coff, n0 + e0, W, gco);
             }
         } else {
-            seg_store<S>(a.gout + roff, n0, W, vec, f);
+            store_seg<S>(a.gout + roff, n0, W, f);
         }
         __syncthreads();  // fag / bag reused by the next channel
     }
     if (a.gd) {
         float cur[S];
-        seg_load<S>(a.gd + prow, n0, W, vec, cur);
+        load_seg<S>(a.gd + prow, n0, W, 0.f, cur);
 #pragma unroll
         for (int e = 0; e < S; ++e) cur[e] += gdacc[e];
-        seg_store<S>(a.gd + prow, n0, W, vec, cur);
+        store_seg<S>(a.gd + prow, n0, W, cur);
     }
 }
 

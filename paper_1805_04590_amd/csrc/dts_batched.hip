@@ -120,6 +120,144 @@ __device__ __forceinline__ void row_band(const RowArgs& ra, int y0, int y1, int 
     }
 }
 
+// Rows of kBatchSoloWidth < W <= 2 kBatchSoloWidth pixels, each filtered by one wave alone
+// in two sections of kBatchSoloWidth pixels (lane l owns pixels 16 l + [0, 16) of each):
+// the causal recurrence runs through section 0 and on through section 1 from J at the
+// section boundary, the anticausal one back through section 1 and on through section 0
+// from K there.  Section 0's weights and causal output wait in the wave's LDS stash while
+// section 1 is in registers, so the wave never holds more than one section and, as for
+// rows of at most kBatchSoloWidth pixels, the waves of a workgroup filter their rows
+// independently, with no workgroup barrier.
+constexpr int kWideS = kBatchSoloWidth / kWave;  // pixels per lane and section
+constexpr int kWideQ = kWideS / 4;               // float4 per lane and section
+typedef float wide4 __attribute__((ext_vector_type(4)));
+struct WideStash {
+    wide4 w[kWideQ][kWave];  // section 0 weights
+    wide4 j[kWideQ][kWave];  // section 0 causal output of the current channel
+};
+
+__device__ __forceinline__ void stash_put(wide4 (&s)[kWideQ][kWave], const float (&v)[kWideS], int lane) {
+#pragma unroll
+    for (int q = 0; q < kWideQ; ++q) s[q][lane] = wide4{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
+}
+
+__device__ __forceinline__ void stash_get(const wide4 (&s)[kWideQ][kWave], float (&v)[kWideS], int lane) {
+#pragma unroll
+    for (int q = 0; q < kWideQ; ++q) {
+        const wide4 x = s[q][lane];
+        v[4 * q] = x[0];
+        v[4 * q + 1] = x[1];
+        v[4 * q + 2] = x[2];
+        v[4 * q + 3] = x[3];
+    }
+}
+
+// causal sweep of one section: f (the signal) becomes J, starting from J = jin before the
+// section's first pixel
+__device__ __forceinline__ void wide_causal(const float (&w)[kWideS], float (&f)[kWideS], float jin, int lane) {
+    float la = 1.f, lb = 0.f;
+#pragma unroll
+    for (int e = 0; e < kWideS; ++e) {
+        lb = fmaf(w[e], lb - f[e], f[e]);
+        la *= w[e];
+    }
+    scan_up_dpp(la, lb, lane);
+    const float xa = __shfl_up(la, 1), xb = __shfl_up(lb, 1);
+    float j = (lane == 0) ? jin : fmaf(xa, jin, xb);
+#pragma unroll
+    for (int e = 0; e < kWideS; ++e) {
+        j = fmaf(w[e], j - f[e], f[e]);
+        f[e] = j;
+    }
+}
+
+// anticausal sweep of one section: f (J) becomes K, starting from K = kin after the
+// section's last pixel, which links to it with weight wl on lane 63 (each lane's wl is
+// the weight of the pixel after its last)
+__device__ __forceinline__ void wide_anticausal(const float (&w)[kWideS], float wl, float (&f)[kWideS], float kin,
+                                                int lane) {
+    float la = 1.f, lb = 0.f;
+#pragma unroll
+    for (int e = kWideS - 1; e >= 0; --e) {
+        const float wn = (e == kWideS - 1) ? wl : w[e < kWideS - 1 ? e + 1 : e];
+        lb = fmaf(wn, lb - f[e], f[e]);
+        la *= wn;
+    }
+    scan_down_dpp(la, lb, lane);
+    const float xa = __shfl_down(la, 1), xb = __shfl_down(lb, 1);
+    float k = (lane == kWave - 1) ? kin : fmaf(xa, kin, xb);
+#pragma unroll
+    for (int e = kWideS - 1; e >= 0; --e) {
+        const float wn = (e == kWideS - 1) ? wl : w[e < kWideS - 1 ? e + 1 : e];
+        k = fmaf(wn, k - f[e], f[e]);
+        f[e] = k;
+    }
+}
+
+__device__ __forceinline__ void row_line_wide(const RowArgs& a, int y, WideStash& st) {
+    constexpr int S = kWideS;
+    const int lane = lane_id();
+    const int W = a.W;
+    const size_t plane = static_cast<size_t>(a.H) * W;
+    const unsigned rowoff = static_cast<unsigned>(y) * static_cast<unsigned>(W) * 4u;
+    const int n0 = lane * S, n1 = kBatchSoloWidth + lane * S;
+    const auto rs = [&](const float* base, int c) {
+        return plane_rsrc(base + static_cast<size_t>(c) * plane, plane * sizeof(float));
+    };
+    float w[S], w1[S], f0[S], f1[S];
+    bload_seg<S>(rs(a.d, 0), rowoff, n0, W, w);
+    if (a.C > 0) bload_seg<S>(rs(a.src, 0), rowoff, n0, W, f0);
+    bload_seg<S>(rs(a.d, 0), rowoff, n1, W, w1);
+    if (a.C > 0) bload_seg<S>(rs(a.src, 0), rowoff, n1, W, f1);
+#pragma unroll
+    for (int e = 0; e < S; ++e) {
+        w[e] = (n0 + e > 0) ? weight(w[e], a.log2a) : 0.f;  // section 0 lies inside the row
+        w1[e] = (n1 + e < W) ? weight(w1[e], a.log2a) : 0.f;
+    }
+    // weight of the pixel after each lane's last: section 0's lane 63 links to section 1's
+    // first pixel, section 1's lane 63 to nothing
+    const float wsec = readlane_f(w1[0], 0);
+    float wl0 = __shfl_down(w[0], 1), wl1 = __shfl_down(w1[0], 1);
+    if (lane == kWave - 1) {
+        wl0 = wsec;
+        wl1 = 0.f;
+    }
+    stash_put(st.w, w, lane);
+    for (int c = 0; c < a.C; ++c) {
+        // the weights come back from LDS for every channel, so they hold no registers while
+        // section 1 is filtered
+        __asm__ volatile("" ::: "memory");
+        stash_get(st.w, w, lane);
+        wide_causal(w, f0, 0.f, lane);
+        const float jsec = readlane_f(f0[S - 1], kWave - 1);  // J at the last pixel of section 0
+        stash_put(st.j, f0, lane);
+        if (c + 1 < a.C) bload_seg<S>(rs(a.src, c + 1), rowoff, n0, W, f0);
+        wide_causal(w1, f1, jsec, lane);
+        wide_anticausal(w1, wl1, f1, 0.f, lane);
+        const float ksec = readlane_f(f1[0], 0);  // K at the first pixel of section 1
+        bstore_seg<S>(rs(a.dst, c), rowoff, n1, W, f1);
+        __asm__ volatile("" ::: "memory");
+        stash_get(st.j, f1, lane);
+        stash_get(st.w, w, lane);
+        wide_anticausal(w, wl0, f1, ksec, lane);
+        bstore_seg<S>(rs(a.dst, c), rowoff, n0, W, f1);
+        if (c + 1 < a.C) bload_seg<S>(rs(a.src, c + 1), rowoff, n1, W, f1);
+    }
+}
+
+// Rows y0 + v, y0 + v + kBatchWaves, ... of [y0, y1), each filtered by wave v alone in two
+// sections (row_line_wide).
+__device__ __forceinline__ void row_band_wide(const RowArgs& ra, int y0, int y1, WideStash (&st)[kBatchWaves]) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int y = y0 + wave; y < y1; y += kBatchWaves) row_line_wide(ra, y, st[wave]);
+}
+
+template <int CTM>
+union BatchLds {
+    ChunkLds<CTM, kBatchWaves> chunk;  // column tiles
+    WideStash wide[kBatchWaves];       // rows of two sections, one stash per wave
+};
+
 // Transformed distances (Eq. (8)-(9)) of rows [y0, y1): one pixel per thread, guide bands
 // four at a time (their loads in flight together, the sums in band order); at x = 0
 // (y = 0) the missing neighbour is the pixel itself, so the distance is 1.  Consecutive
@@ -179,7 +317,7 @@ __device__ __forceinline__ void dist_band(const BInst& I, int y0, int y1) {
 template <int R, int CTM, int OCC>
 __global__ void __launch_bounds__(kWave * kBatchWaves) __attribute__((amdgpu_waves_per_eu(OCC, 8)))
 batched_kernel(BatchArgs a) {
-    __shared__ ChunkLds<CTM, kBatchWaves> L;
+    __shared__ BatchLds<CTM> U;
     __shared__ RowLds RL;
     __shared__ int s_pre[kBatchMaxProblems + 1];
     __shared__ unsigned s_t;
@@ -229,7 +367,8 @@ batched_kernel(BatchArgs a) {
                     const int y0 = tile * I.row_rows;
                     const int y1 = min(I.H, y0 + I.row_rows);
                     if (I.row_S == 8) row_band<8>(ra, y0, y1, I.row_gw, RL);
-                    else row_band<16>(ra, y0, y1, I.row_gw, RL);
+                    else if (I.row_S == 16) row_band<16>(ra, y0, y1, I.row_gw, RL);
+                    else row_band_wide(ra, y0, y1, U.wide);
                     __syncthreads();  // every wave has read s_t
                 } else {
                     ColArgs ca;
@@ -264,8 +403,8 @@ batched_kernel(BatchArgs a) {
                     auto take_next = [&]() {
                         if (threadIdx.x == 0) nxt = atomicAdd(tickets, 1u);
                     };
-                    if (epi) col_tile<CTM, R, kBatchWaves, 1>(ca, cctx, L, chunk, strip, grp, 0, take_next);
-                    else col_tile<CTM, R, kBatchWaves, 0>(ca, cctx, L, chunk, strip, grp, 0, take_next);
+                    if (epi) col_tile<CTM, R, kBatchWaves, 1>(ca, cctx, U.chunk, chunk, strip, grp, 0, take_next);
+                    else col_tile<CTM, R, kBatchWaves, 0>(ca, cctx, U.chunk, chunk, strip, grp, 0, take_next);
                 }
             }
             // every wave has read s_t (a barrier of the tile lies in between)
@@ -375,11 +514,13 @@ static Geo geometry(const dts_problem& q, const BatchVariant& v) {
     if (q.W <= kBatchSoloWidth) {
         g.row_S = q.W <= 512 ? 8 : 16;
         g.row_gw = 1;
+    } else if (q.W <= 2 * kBatchSoloWidth) {
+        // one wave per row in two sections (row_line_wide)
+        g.row_S = kBatchWideS;
+        g.row_gw = 1;
     } else {
-        // wider rows: the whole workgroup on one row at a time, 8 pixels per lane up to
-        // 2048 (measured on the 64 uneven solves: 529 against 600 us per row phase for
-        // two rows side by side at 16 pixels per lane), 16 beyond
-        g.row_S = q.W <= 2 * kBatchSoloWidth ? 8 : 16;
+        // wider rows: the whole workgroup on one row at a time, 16 pixels per lane
+        g.row_S = 16;
         g.row_gw = kBatchWaves;
     }
     const int side = kBatchWaves / g.row_gw;  // rows processed side by side

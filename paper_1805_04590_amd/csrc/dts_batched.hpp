@@ -7,6 +7,7 @@ constexpr int kBatchMaxN = 8;          // filter iterations per instance
 constexpr int kBatchWaves = 4;         // waves per workgroup of the batched kernel
 constexpr int kBatchSoloWidth = 64 * 16;              // widest row one wave filters alone
 constexpr int kBatchMaxWidth = kBatchWaves * kBatchSoloWidth;
+constexpr int kBatchWideS = 32;  // row_S code of the two-section rows
 constexpr int kBatchMaxProblems = 1024;
 
 struct BInst {
@@ -19,8 +20,9 @@ struct BInst {
     float* tmp;
     unsigned long long* carry;
     int H, W, Cg, Ct, Cc, N, T;
-    int row_S;       // pixels per lane of a row (8 or 16)
-    int row_gw;      // waves per row (1, 2 or 4); kBatchWaves / row_gw rows side by side
+    int row_S;       // pixels per lane of a row: 8 or 16, or kBatchWideS for rows of one
+                     // wave in two sections of kBatchSoloWidth pixels (16 per lane each)
+    int row_gw;      // waves per row (1 or kBatchWaves); kBatchWaves / row_gw rows side by side
     int row_rows;    // rows per row tile (a multiple of kBatchWaves / row_gw)
     int dist_rows;   // rows per tile of the distance phase
     int G, S, NG;    // column chunks per strip, strips, channel groups

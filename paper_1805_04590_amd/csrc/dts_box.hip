@@ -70,19 +70,19 @@ __global__ void __launch_bounds__(256) box_codes_kernel(const float* __restrict_
     const size_t plane = static_cast<size_t>(H) * W;
     const size_t i0 = static_cast<size_t>(y) * W + x0;
     const float* g = guide + static_cast<size_t>(b) * Cg * plane + i0;
-    const bool vec = (W % kCodePx) == 0;  // then x0 + 3 < W and every row is 16-byte aligned
+    const bool whole = x0 + kCodePx <= W;  // the lane's pixels all lie inside the row
     float ax[kCodePx], ay[kCodePx];
 #pragma unroll
     for (int e = 0; e < kCodePx; ++e) ax[e] = ay[e] = 0.0f;
     for (int k = 0; k < Cg; ++k) {
         const float* gk = g + static_cast<size_t>(k) * plane;
         float v[kCodePx], u[kCodePx];
-        if (vec) {
-            const float4 a = *reinterpret_cast<const float4*>(gk);
-            v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        if (whole) {
+            const float4_a4 a = *reinterpret_cast<const float4_a4*>(gk);
+            v[0] = a[0]; v[1] = a[1]; v[2] = a[2]; v[3] = a[3];
             if (y > 0) {
-                const float4 c = *reinterpret_cast<const float4*>(gk - W);
-                u[0] = c.x; u[1] = c.y; u[2] = c.z; u[3] = c.w;
+                const float4_a4 c = *reinterpret_cast<const float4_a4*>(gk - W);
+                u[0] = c[0]; u[1] = c[1]; u[2] = c[2]; u[3] = c[3];
             }
         } else {
 #pragma unroll

@@ -157,27 +157,45 @@ __device__ __forceinline__ void flag_error(int* status, int code) {
     __hip_atomic_fetch_or(status, code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Row loads of 4 consecutive elements starting at n0 (a multiple of 4); elements at or
-// beyond W read as `fill`.  `vec` is true when every row starts 16-byte aligned.
-__device__ __forceinline__ float4 load4(const float* row, int n0, int W, bool vec, float fill) {
-    if (vec && n0 + 3 < W) return *reinterpret_cast<const float4*>(row + n0);
-    float4 v;
-    v.x = (n0 + 0 < W) ? row[n0 + 0] : fill;
-    v.y = (n0 + 1 < W) ? row[n0 + 1] : fill;
-    v.z = (n0 + 2 < W) ? row[n0 + 2] : fill;
-    v.w = (n0 + 3 < W) ? row[n0 + 3] : fill;
-    return v;
+// Four floats at a 4-byte aligned address, moved as one 16-byte access: dword alignment is
+// all that multi-dword global and buffer accesses need, so rows whose length is not a
+// multiple of 4 (and whose starts are therefore not 16-byte aligned) still move 16 bytes
+// per lane and instruction instead of 4.
+typedef float float4_a4 __attribute__((ext_vector_type(4), aligned(4)));
+
+// S (a multiple of 4) consecutive row elements starting at n0 (a multiple of S); elements
+// at or beyond W read as `fill`, and store_seg writes only those below W.
+template <int S>
+__device__ __forceinline__ void load_seg(const float* row, int n0, int W, float fill, float (&v)[S]) {
+    static_assert(S % 4 == 0, "segments are whole groups of 4");
+    if (n0 + S <= W) {
+#pragma unroll
+        for (int e = 0; e < S; e += 4) {
+            const float4_a4 q = *reinterpret_cast<const float4_a4*>(row + n0 + e);
+            v[e] = q[0];
+            v[e + 1] = q[1];
+            v[e + 2] = q[2];
+            v[e + 3] = q[3];
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < S; ++e) v[e] = (n0 + e < W) ? row[n0 + e] : fill;
+    }
 }
 
-__device__ __forceinline__ void store4(float* row, int n0, int W, bool vec, float4 v) {
-    if (vec && n0 + 3 < W) {
-        *reinterpret_cast<float4*>(row + n0) = v;
-        return;
+template <int S>
+__device__ __forceinline__ void store_seg(float* row, int n0, int W, const float (&v)[S]) {
+    static_assert(S % 4 == 0, "segments are whole groups of 4");
+    if (n0 + S <= W) {
+        // element stores that the backend merges into 16-byte stores (a vector store here
+        // is scheduled with more registers live)
+#pragma unroll
+        for (int e = 0; e < S; ++e) row[n0 + e] = v[e];
+    } else {
+#pragma unroll
+        for (int e = 0; e < S; ++e)
+            if (n0 + e < W) row[n0 + e] = v[e];
     }
-    if (n0 + 0 < W) row[n0 + 0] = v.x;
-    if (n0 + 1 < W) row[n0 + 1] = v.y;
-    if (n0 + 2 < W) row[n0 + 2] = v.z;
-    if (n0 + 3 < W) row[n0 + 3] = v.w;
 }
 
 // Raw buffer access.  A resource covers one plane; lanes whose voffset is kInvalidOffset
@@ -201,49 +219,43 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned voff, 
 
 // S consecutive floats of a row through a buffer resource over the whole plane: lane
 // elements [n0, n0 + S) of the row at byte offset `row` (elements at or past `n` read 0
-// and are not written).  `vec`: the row is 16-byte aligned and n is a multiple of 4, so
-// every 4-float piece is wholly inside or wholly past the row end and moves as one
-// 128-bit access; otherwise element by element.  Buffer accesses count on the vector
-// memory counter only, so waiting for them never waits on LDS or scalar traffic (and
-// the reverse), unlike generic (flat) accesses through pointers loaded from memory.
+// and are not written), in 128-bit accesses at 4-byte aligned offsets.  Buffer accesses
+// count on the vector memory counter only, so waiting for them never waits on LDS or
+// scalar traffic (and the reverse), unlike generic (flat) accesses through pointers
+// loaded from memory.
 template <int S>
-__device__ __forceinline__ void bload_seg(__amdgpu_buffer_rsrc_t r, unsigned row, int n0, int n, bool vec,
-                                          float (&v)[S]) {
-    if (vec) {
+__device__ __forceinline__ void bload_seg(__amdgpu_buffer_rsrc_t r, unsigned row, int n0, int n, float (&v)[S]) {
+    static_assert(S % 4 == 0, "segments are whole groups of 4");
+    // 16-byte loads at 4-byte aligned offsets; a group that runs past n reads the next row
+    // (or, past the plane, zeros from the range check), which is replaced by 0
 #pragma unroll
-        for (int e = 0; e < S; e += 4) {
-            const unsigned o = (n0 + e < n) ? row + static_cast<unsigned>(n0 + e) * 4u : kInvalidOffset;
-            const auto q = __builtin_amdgcn_raw_buffer_load_b128(r, o, 0, 0);
-            v[e] = __uint_as_float(q[0]);
-            v[e + 1] = __uint_as_float(q[1]);
-            v[e + 2] = __uint_as_float(q[2]);
-            v[e + 3] = __uint_as_float(q[3]);
-        }
-    } else {
+    for (int e = 0; e < S; e += 4) {
+        const unsigned o = (n0 + e < n) ? row + static_cast<unsigned>(n0 + e) * 4u : kInvalidOffset;
+        const auto q = __builtin_amdgcn_raw_buffer_load_b128(r, o, 0, 0);
 #pragma unroll
-        for (int e = 0; e < S; ++e)
-            v[e] = bload(r, (n0 + e < n) ? row + static_cast<unsigned>(n0 + e) * 4u : kInvalidOffset, 0);
+        for (int k = 0; k < 4; ++k) v[e + k] = (n0 + e + k < n) ? __uint_as_float(q[k]) : 0.f;
     }
 }
 
 template <int S>
-__device__ __forceinline__ void bstore_seg(__amdgpu_buffer_rsrc_t r, unsigned row, int n0, int n, bool vec,
+__device__ __forceinline__ void bstore_seg(__amdgpu_buffer_rsrc_t r, unsigned row, int n0, int n,
                                            const float (&v)[S]) {
-    if (vec) {
+    static_assert(S % 4 == 0, "segments are whole groups of 4");
+    // whole groups as 16-byte stores at 4-byte aligned offsets, a group that reaches past n
+    // element by element
 #pragma unroll
-        for (int e = 0; e < S; e += 4) {
-            const unsigned o = (n0 + e < n) ? row + static_cast<unsigned>(n0 + e) * 4u : kInvalidOffset;
-            __amdgpu_buffer_rsrc_t rr = r;
-            const uint32_t q0 = __float_as_uint(v[e]), q1 = __float_as_uint(v[e + 1]);
-            const uint32_t q2 = __float_as_uint(v[e + 2]), q3 = __float_as_uint(v[e + 3]);
+    for (int e = 0; e < S; e += 4) {
+        if (n0 + e + 4 <= n) {
             typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-            const u32x4 q = {q0, q1, q2, q3};
-            __builtin_amdgcn_raw_buffer_store_b128(q, rr, o, 0, 0);
-        }
-    } else {
+            const u32x4 q = {__float_as_uint(v[e]), __float_as_uint(v[e + 1]), __float_as_uint(v[e + 2]),
+                             __float_as_uint(v[e + 3])};
+            __builtin_amdgcn_raw_buffer_store_b128(q, r, row + static_cast<unsigned>(n0 + e) * 4u, 0, 0);
+        } else {
 #pragma unroll
-        for (int e = 0; e < S; ++e)
-            bstore(r, (n0 + e < n) ? row + static_cast<unsigned>(n0 + e) * 4u : kInvalidOffset, 0, v[e]);
+            for (int k = 0; k < 4; ++k)
+                bstore(r, (n0 + e + k < n) ? row + static_cast<unsigned>(n0 + e + k) * 4u : kInvalidOffset, 0,
+                       v[e + k]);
+        }
     }
 }
 

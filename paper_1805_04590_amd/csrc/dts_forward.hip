@@ -58,12 +58,11 @@ __global__ void __launch_bounds__(1024) row_pass_stream_kernel(RowArgs a, int ro
     const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int W = a.W;
     const int n0 = (wave * kWave + lane) * S;
-    const bool vec = (W & 3) == 0;
     float fN[S], dN[S];
     int r = blockIdx.x;
     if (r < rows) {
-        load_seg<S>(a.src + static_cast<size_t>(r) * W, n0, W, vec, 0.f, fN);
-        load_seg<S>(a.d + static_cast<size_t>(r) * W, n0, W, vec, 1.f, dN);
+        load_seg<S>(a.src + static_cast<size_t>(r) * W, n0, W, 0.f, fN);
+        load_seg<S>(a.d + static_cast<size_t>(r) * W, n0, W, 1.f, dN);
     }
     for (; r < rows; r += gridDim.x) {
         float f[S], w[S];
@@ -75,8 +74,8 @@ __global__ void __launch_bounds__(1024) row_pass_stream_kernel(RowArgs a, int ro
         }
         const int rn = r + gridDim.x;
         if (rn < rows) {
-            load_seg<S>(a.src + static_cast<size_t>(rn) * W, n0, W, vec, 0.f, fN);
-            load_seg<S>(a.d + static_cast<size_t>(rn) * W, n0, W, vec, 1.f, dN);
+            load_seg<S>(a.src + static_cast<size_t>(rn) * W, n0, W, 0.f, fN);
+            load_seg<S>(a.d + static_cast<size_t>(rn) * W, n0, W, 1.f, dN);
         }
         float wlast = __shfl_down(w[0], 1);
         if (lane == 0) wfirst[wave] = w[0];
@@ -129,7 +128,7 @@ __global__ void __launch_bounds__(1024) row_pass_stream_kernel(RowArgs a, int ro
             k = fmaf(wn, k - f[e], f[e]);
             f[e] = k;
         }
-        store_seg<S>(a.dst + static_cast<size_t>(r) * W, n0, W, vec, f);
+        store_seg<S>(a.dst + static_cast<size_t>(r) * W, n0, W, f);
     }
 }
 

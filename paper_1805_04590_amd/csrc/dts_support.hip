@@ -46,12 +46,11 @@ __global__ void __launch_bounds__(1024) support_row_kernel(const float* __restri
     const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const size_t off = (static_cast<size_t>(b) * H + y) * W;
     const int n0 = (wave * kWave + lane) * S;
-    const bool vec = (W & 3) == 0;
 
     float w[S], x[S];
     {
         float dv[S];
-        load_seg<S>(dx + off, n0, W, vec, 1.f, dv);
+        load_seg<S>(dx + off, n0, W, 1.f, dv);
 #pragma unroll
         for (int e = 0; e < S; ++e) {
             const int n = n0 + e;
@@ -59,7 +58,7 @@ __global__ void __launch_bounds__(1024) support_row_kernel(const float* __restri
         }
     }
     if (src) {
-        load_seg<S>(src + off, n0, W, vec, 0.f, x);
+        load_seg<S>(src + off, n0, W, 0.f, x);
     } else {
 #pragma unroll
         for (int e = 0; e < S; ++e) x[e] = (n0 + e < W) ? 1.f : 0.f;
@@ -123,7 +122,7 @@ __global__ void __launch_bounds__(1024) support_row_kernel(const float* __restri
         k = fmaf(wn, k, x[e]);
         yv[e] = m * (yv[e] + k - x[e]);
     }
-    store_seg<S>(dst + off, n0, W, vec, yv);
+    store_seg<S>(dst + off, n0, W, yv);
 }
 
 // ---------------------------------------------------------------------------------------

@@ -34,37 +34,6 @@ struct RowArgs {
 
 constexpr int kMaxRowWaves = 16;
 
-template <int S>
-__device__ __forceinline__ void load_seg(const float* row, int n0, int W, bool vec, float fill,
-                                         float (&v)[S]) {
-    if (vec && n0 + S <= W) {
-#pragma unroll
-        for (int e = 0; e < S; e += 4) {
-            const float4 q = *reinterpret_cast<const float4*>(row + n0 + e);
-            v[e] = q.x;
-            v[e + 1] = q.y;
-            v[e + 2] = q.z;
-            v[e + 3] = q.w;
-        }
-    } else {
-#pragma unroll
-        for (int e = 0; e < S; ++e) v[e] = (n0 + e < W) ? row[n0 + e] : fill;
-    }
-}
-
-template <int S>
-__device__ __forceinline__ void store_seg(float* row, int n0, int W, bool vec, const float (&v)[S]) {
-    if (vec && n0 + S <= W) {
-#pragma unroll
-        for (int e = 0; e < S; e += 4)
-            *reinterpret_cast<float4*>(row + n0 + e) = make_float4(v[e], v[e + 1], v[e + 2], v[e + 3]);
-    } else {
-#pragma unroll
-        for (int e = 0; e < S; ++e)
-            if (n0 + e < W) row[n0 + e] = v[e];
-    }
-}
-
 // Both directions of the recurrence over one row held by one wave (lane l owns pixels
 // [l S, (l+1) S)), in registers: w[e] links pixel e to the one before it, wlast links
 // the lane's last pixel to the next lane's first (0 for lane 63).  f is replaced by K.
@@ -128,7 +97,6 @@ __device__ __forceinline__ void row_line(const RowArgs& a, int y, int b, int wav
     const int We = live ? W : 0;  // pixels of the row this group touches
     const size_t plane = static_cast<size_t>(H) * W;
     const int n0 = (wave * kWave + lane) * S;
-    const bool vec = (W & 3) == 0;
 
     // BUF: each channel's row is loaded one channel ahead (channel 0 with the distances),
     // so its loads are in flight while the previous channel is scanned: a row then costs
@@ -137,7 +105,7 @@ __device__ __forceinline__ void row_line(const RowArgs& a, int y, int b, int wav
     [[maybe_unused]] const unsigned rowoff = static_cast<unsigned>(y) * static_cast<unsigned>(W) * 4u;
     [[maybe_unused]] const auto load_ch = [&](int c, float (&v)[S]) {
         const size_t pl = static_cast<size_t>(b) * cin + (SQ ? c >> 1 : c);
-        bload_seg<S>(plane_rsrc(a.src + pl * plane, plane * sizeof(float)), rowoff, n0, We, vec, v);
+        bload_seg<S>(plane_rsrc(a.src + pl * plane, plane * sizeof(float)), rowoff, n0, We, v);
     };
     float f[S];
 
@@ -151,8 +119,8 @@ __device__ __forceinline__ void row_line(const RowArgs& a, int y, int b, int wav
                              static_cast<size_t>(y) * W;
             const float* gu = (y > 0) ? g - W : g;
             float v[S], u[S];
-            load_seg<S>(g, n0, We, vec, 0.f, v);
-            load_seg<S>(gu, n0, We, vec, 0.f, u);
+            load_seg<S>(g, n0, We, 0.f, v);
+            load_seg<S>(gu, n0, We, 0.f, u);
             float prev = __shfl_up(v[S - 1], 1);
             if (lane == 0) prev = (n0 > 0 && n0 <= We) ? g[n0 - 1] : v[0];
 #pragma unroll
@@ -170,8 +138,8 @@ __device__ __forceinline__ void row_line(const RowArgs& a, int y, int b, int wav
             ax[e] = sqrtf(fmaf(a.s2, ax[e], 1.f));
             ay[e] = sqrtf(fmaf(a.s2, ay[e], 1.f));
         }
-        store_seg<S>(dxr, n0, We, vec, ax);
-        store_seg<S>(dyr, n0, We, vec, ay);
+        store_seg<S>(dxr, n0, We, ax);
+        store_seg<S>(dyr, n0, We, ay);
 #pragma unroll
         for (int e = 0; e < S; ++e) {
             const int n = n0 + e;
@@ -181,11 +149,11 @@ __device__ __forceinline__ void row_line(const RowArgs& a, int y, int b, int wav
         float dv[S];
         if constexpr (BUF) {
             bload_seg<S>(plane_rsrc(a.d + static_cast<size_t>(b) * plane, plane * sizeof(float)), rowoff, n0,
-                         We, vec, dv);
+                         We, dv);
             if (a.C > 0) load_ch(0, f);
         } else {
             const float* dr = a.d + static_cast<size_t>(b) * plane + static_cast<size_t>(y) * W;
-            load_seg<S>(dr, n0, We, vec, 1.f, dv);
+            load_seg<S>(dr, n0, We, 1.f, dv);
         }
 #pragma unroll
         for (int e = 0; e < S; ++e) {
@@ -212,7 +180,7 @@ __device__ __forceinline__ void row_line(const RowArgs& a, int y, int b, int wav
         } else {
             const size_t soff =
                 (static_cast<size_t>(b) * cin + (SQ ? c >> 1 : c)) * plane + static_cast<size_t>(y) * W;
-            load_seg<S>(a.src + soff, n0, We, vec, 0.f, f);
+            load_seg<S>(a.src + soff, n0, We, 0.f, f);
         }
         if (SQ && (c & 1)) {
 #pragma unroll
@@ -274,13 +242,13 @@ __device__ __forceinline__ void row_line(const RowArgs& a, int y, int b, int wav
         }
         if constexpr (BUF) {
             bstore_seg<S>(plane_rsrc(a.dst + (roff - static_cast<size_t>(y) * W), plane * sizeof(float)), rowoff,
-                          n0, We, vec, f);
+                          n0, We, f);
             if (c + 1 < a.C) {
 #pragma unroll
                 for (int e = 0; e < S; ++e) f[e] = fn[e];
             }
         } else {
-            store_seg<S>(a.dst + roff, n0, We, vec, f);
+            store_seg<S>(a.dst + roff, n0, We, f);
         }
     }
 }

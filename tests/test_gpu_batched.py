@@ -62,10 +62,13 @@ def test_batched_matches_oracle_and_single(variant):
 
 @pytest.mark.parametrize("variant", range(N_BATCH_VARIANTS))
 def test_batched_wide_rows(variant):
-    """Rows filtered by one wave and rows split over 2 and 4 waves, the widest accepted
-    row, a 1-row and a 1-column image, next to each other in one launch."""
+    """Rows filtered by one wave, by one wave in two sections (1024 < W <= 2048, widths
+    that are and are not multiples of 4, one to three channels), by all four waves of a
+    workgroup, the widest accepted row, a 1-row and a 1-column image, next to each other in
+    one launch."""
     shapes = [(9, 1100, 3, 1), (6, 2500, 1, 2), (5, 4096, 8, 1), (3, 2048, 2, 1), (1, 300, 3, 1),
-              (70, 1, 1, 2), (33, 100, 16, 3), (12, 1024, 1, 1), (7, 513, 3, 2)]
+              (70, 1, 1, 2), (33, 100, 16, 3), (12, 1024, 1, 1), (7, 513, 3, 2), (5, 1025, 2, 3),
+              (11, 1999, 3, 2), (2, 2049, 1, 1), (6, 1536, 16, 3)]
     cases = [dts_inputs.random_case(1200 + k, H, W, Cg, Ct, Cc=1, sigma_s=12.0, sigma_r=0.2, T=2)
              for k, (H, W, Cg, Ct) in enumerate(shapes)]
     print("CASE batched wide rows", variant, shapes, flush=True)
