@@ -66,6 +66,7 @@ SHAPES = [
     (45, 130, 2, 3, 1, 2),
     (300, 67, 1, 2, 2, 2),
     (130, 257, 8, 1, 1, 2),
+    (6, 5001, 2, 2, 1, 2),  # a width that is not a multiple of 4, 8 pixels per lane
 ]
 
 

@@ -49,6 +49,10 @@ STEP_SHAPES = [
     (4099, 3, 1, 1),
     (1500, 130, 3, 3),
     (700, 200, 2, 4),
+    # widths not a multiple of 4 at 8 and 16 pixels per lane: rows start off 16-byte
+    # alignment and still move as 16-byte accesses
+    (5, 6001, 2, 2),
+    (3, 9999, 1, 1),
 ]
 
 
@@ -95,6 +99,8 @@ FILTER_SHAPES = [
     (129, 1025, 3, 1),
     (65, 4100, 3, 1),
     (97, 63, 8, 4),
+    (9, 6001, 3, 2),
+    (4, 10001, 2, 1),
 ]
 
 

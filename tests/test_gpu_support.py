@@ -26,6 +26,7 @@ CASES = [
     (37, 1500, 1, 3, 1, 20.0, 0.3),
     (1500, 37, 3, 3, 1, 32.0, 0.1),
     (65, 4500, 3, 3, 1, 32.0, 0.2),
+    (9, 9001, 2, 3, 1, 16.0, 0.2),
 ]
 
 
