@@ -224,8 +224,8 @@ __device__ __forceinline__ void row_line_wide(const RowArgs& a, int y, WideStash
     }
     stash_put(st.w, w, lane);
     for (int c = 0; c < a.C; ++c) {
-        // the weights come back from LDS for every channel, so they hold no registers while
-        // section 1 is filtered
+        // section 0's weights come back from LDS for every channel, so they hold no
+        // registers while section 1 is filtered
         __asm__ volatile("" ::: "memory");
         stash_get(st.w, w, lane);
         wide_causal(w, f0, 0.f, lane);

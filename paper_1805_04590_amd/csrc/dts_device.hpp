@@ -226,8 +226,9 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned voff, 
 template <int S>
 __device__ __forceinline__ void bload_seg(__amdgpu_buffer_rsrc_t r, unsigned row, int n0, int n, float (&v)[S]) {
     static_assert(S % 4 == 0, "segments are whole groups of 4");
-    // 16-byte loads at 4-byte aligned offsets; a group that runs past n reads the next row
-    // (or, past the plane, zeros from the range check), which is replaced by 0
+    // 16-byte loads at 4-byte aligned offsets; a group that runs past n reads the first
+    // elements of the next row, or past the end of the plane zeros (the range check applies
+    // to each dword of the access), and those elements are replaced by 0
 #pragma unroll
     for (int e = 0; e < S; e += 4) {
         const unsigned o = (n0 + e < n) ? row + static_cast<unsigned>(n0 + e) * 4u : kInvalidOffset;
