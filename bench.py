@@ -422,6 +422,7 @@ def solve_leg(args, dev):
         dts.support(guide, ss, sr, N, conf=conf, out=sup, conf_out=confs, workspace=wss)
 
     ms_s = timed(sstep, args.steps, args.warmup)
+    dts.workspace_status(wss)
     # distances (guide in, dx and dy out); pass 1: rows of ones (dx in, plane out), columns
     # (plane and dy in, plane out); N - 1 more row and column passes over the support
     # plane; the last column pass also reads and writes the Cc confidence planes

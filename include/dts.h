@@ -202,7 +202,9 @@ size_t dts_support_workspace_bytes(int batch, int H, int W);
  * (1 - a_i) / (1 + a_i), so s is 1 deep inside a flat region and lies in (0, 1].
  * support [batch][H][W].  conf [batch][Cc][H][W] (1 <= Cc <= 16) and conf_out (same shape)
  * may be NULL together; conf_out may alias conf but neither may alias support.  The
- * support depends on the guide only: compute it once per guide.  Errors as dts_filter. */
+ * support depends on the guide only: compute it once per guide.  Errors as dts_filter;
+ * its column passes use the filter's chunked carry exchange, so a bounded wait that
+ * gives up flags the workspace status (dts_workspace_status). */
 int dts_support(const float* guide, int Cg, int batch, int H, int W, float sigma_s, float sigma_r,
                 int filter_iters, float* support, const float* conf, int Cc, float* conf_out, void* workspace,
                 size_t workspace_bytes, void* stream);

@@ -714,11 +714,12 @@ def solve_box(guide, target, conf, sigma_s, sigma_r, filter_iters=3, solver_iter
 
 
 def support(guide, sigma_s, sigma_r, filter_iters=3, conf=None, out=None, conf_out=None,
-            workspace=None):
+            workspace=None, check=None):
     """Support of the edge-aware kernel relative to a flat region, s in (0, 1] per pixel
     ([B][H][W], or [H][W] for a 3-D guide).  With ``conf`` ([B][Cc][H][W]) also returns the
     support-weighted confidence conf / s (Sec. 3.1, after Eq. (6)) as (s, conf / s);
-    ``conf_out`` may be ``conf``."""
+    ``conf_out`` may be ``conf``.  ``check``: read the workspace's device status afterwards
+    (default: only when the workspace is allocated here)."""
     g = _as4d(guide, "guide")
     B, Cg, H, W = g.shape
     lib = library()
@@ -738,7 +739,8 @@ def support(guide, sigma_s, sigma_r, filter_iters=3, conf=None, out=None, conf_o
         co = torch.empty_like(c) if conf_out is None else _as4d(conf_out, "conf_out")
         if co.shape != c.shape:
             raise ValueError("conf_out must have the shape of conf")
-    if workspace is None:
+    internal = workspace is None
+    if internal:
         nbytes = lib.dts_support_workspace_bytes(B, H, W)
         if nbytes == 0:
             raise DTSError(DTS_EINVAL, "dts_support_workspace_bytes")
@@ -747,6 +749,7 @@ def support(guide, sigma_s, sigma_r, filter_iters=3, conf=None, out=None, conf_o
                          _ptr(s_out), _ptr(c), Cc, _ptr(co), _ptr(workspace), workspace.numel(),
                          _stream())
     _check(rc, "dts_support")
+    _finish(workspace, internal, check, "dts_support")
     sv = s_out.reshape(B, H, W) if guide.dim() == 4 else s_out.reshape(H, W)
     if c is None:
         return sv

@@ -123,13 +123,12 @@ static double feedback(double sigma_s, int i, int N) {
 
 // Support workspace: [header | dx | dy | tmp | chunk aggregates (float4) | carries (float2)]
 struct SupportLayout {
-    size_t dx, dy, tmp, agg, carry, total;
+    size_t dx, dy, tmp, carry, carry_bytes, total;
 };
 
 static SupportLayout make_support_layout(int batch, int H, int W) {
     SupportLayout L;
     const size_t plane = static_cast<size_t>(batch) * H * W * sizeof(float);
-    const size_t chunks = static_cast<size_t>(batch) * support_chunks(H) * W;
     size_t off = kHeaderBytes;
     L.dx = off;
     off = align_up(off + plane);
@@ -137,10 +136,9 @@ static SupportLayout make_support_layout(int batch, int H, int W) {
     off = align_up(off + plane);
     L.tmp = off;
     off = align_up(off + plane);
-    L.agg = off;
-    off = align_up(off + chunks * 16);
     L.carry = off;
-    off = align_up(off + chunks * 8);
+    L.carry_bytes = align_up(support_carry_words(batch, H, W) * sizeof(unsigned long long));
+    off += L.carry_bytes;
     L.total = off;
     return L;
 }
@@ -829,8 +827,13 @@ int dts_support(const float* guide, int Cg, int batch, int H, int W, float sigma
     float* tmp = reinterpret_cast<float*>(base + L.tmp);
     Ctx ctx;
     ctx.stream = static_cast<hipStream_t>(stream);
-    // no kernel of the support path reports a device-side failure: start from a clean status
+    ctx.status = reinterpret_cast<int*>(base);
+    ctx.carry = reinterpret_cast<unsigned long long*>(base + L.carry);
+    ctx.carry_words = L.carry_bytes / sizeof(unsigned long long);
+    // status and carry words start from zero: the status read back afterwards describes
+    // this call (a bounded wait of the column passes that gave up)
     if ((rc = launch_zero(base, kHeaderBytes, ctx.stream))) return rc;
+    if ((rc = launch_zero(base + L.carry, L.carry_bytes, ctx.stream))) return rc;
     RowPass rp{};
     rp.guide = guide;
     rp.dx_out = dx;
@@ -850,8 +853,8 @@ int dts_support(const float* guide, int Cg, int batch, int H, int W, float sigma
         if ((rc = launch_support_row(i == 1 ? nullptr : support, dx, tmp, batch, H, W, l2a, m, ctx.stream)))
             return rc;
         const bool last = i == filter_iters;
-        if ((rc = launch_support_col(tmp, dy, support, base + L.agg, base + L.carry, last ? conf : nullptr, Cc,
-                                     last ? conf_out : nullptr, batch, H, W, l2a, m, ctx.stream)))
+        if ((rc = launch_support_col(tmp, dy, support, last ? conf : nullptr, Cc, last ? conf_out : nullptr, batch,
+                                     H, W, l2a, m, ctx)))
             return rc;
     }
     return DTS_OK;

@@ -132,11 +132,11 @@ int launch_box_col_prefixed(const float* src, float* P, float* dst, const unsign
 int launch_box_col(const float* src, float* dst, const unsigned short* bounds, int C, int batch, int H, int W, int h,
                    const float* zk, const float* tgt, const float* conf, int Cc, float lambda, float step,
                    hipStream_t s);
-size_t support_chunks(int H);
+size_t support_carry_words(int batch, int H, int W);
 int launch_support_row(const float* src, const float* dx, float* dst, int batch, int H, int W, float log2a,
                        float m, hipStream_t s);
-int launch_support_col(const float* src, const float* dy, float* dst, void* agg, void* carry, const float* conf,
-                       int Cc, float* conf_out, int batch, int H, int W, float log2a, float m, hipStream_t s);
+int launch_support_col(const float* src, const float* dy, float* dst, const float* conf, int Cc, float* conf_out,
+                       int batch, int H, int W, float log2a, float m, Ctx& ctx);
 
 // RAII launch timer: records a start event on construction and a stop event on
 // destruction (both on `s`) when timing is enabled; a no-op otherwise.

@@ -13,22 +13,28 @@
 // Row pass: one workgroup per row, lane l of wave v owning S consecutive pixels, both
 // directions as 64-lane affine-map scans with a cross-wave exchange through LDS (the
 // layout of the filter's row pass).
-// Column pass: reduce, carry, apply.  Each chunk of kChunk rows of every column first
-// reduces to its two affine aggregates, one thread per column per chunk; one thread per
-// column then composes them down and up the column into every chunk's carries; the apply
-// kernel reruns both recurrences of the chunk from its carries and writes the scaled sum.
-// Every launch is independent of the others' scheduling: no waits, no flags.
+// Column pass: the filter's persistent chunked column pass (dts_chunks.hpp), each chunk of
+// a 64-column strip in registers, one column per lane.  A wave's rows reduce to the
+// aggregates of both recurrences (y: factor A, value B at the last row from a zero carry;
+// v: factor P, value BJ at the first row from a zero carry; the two do not feed each
+// other, so BQ = 0), the chunk engine resolves every wave's carry-ins from the
+// neighbouring chunks' aggregates, and the wave reruns both recurrences from them and
+// writes the scaled sum: every plane is read once.
 #include <algorithm>
 
+#include <mutex>
+
 #include "../../include/dts.h"
+#include "dts_chunks.hpp"
 #include "dts_device.hpp"
 #include "dts_internal.hpp"
 #include "dts_tiles.hpp"
 
 namespace dts {
 
-constexpr int kSupChunk = 32;       // rows per column chunk
-constexpr int kSupColThreads = 256;  // columns per workgroup of the column kernels
+constexpr int kSupRows = 24;   // rows per wave of a column chunk
+constexpr int kSupWaves = 8;   // waves per workgroup: chunks of 192 rows
+constexpr int kSupChunkRows = kSupRows * kSupWaves;
 
 // ---------------------------------------------------------------------------------------
 // Row pass: dst = m * (y + v - x) along every row; x = src, or ones when src is null.
@@ -126,134 +132,151 @@ __global__ void __launch_bounds__(1024) support_row_kernel(const float* __restri
 }
 
 // ---------------------------------------------------------------------------------------
-// Column pass.  Chunk g of a column covers rows [s, e], s = g kChunk.  Its aggregates:
-//   forward   y[e] = Af y[s-1] + Bf,   Af = prod_{n=s..e} w[n]       (w[0] = 0)
-//   backward  v[s] = Ab v[e+1] + Bb,   Ab = prod_{n=s+1..e+1} w[n]   (w[H] = 0)
-// with Bf, Bb the chunk's own recurrences from zero carries.
+// Column pass: dst = m * (y + v - x) along every column, and, when conf is set,
+// conf_out = conf / dst.
 // ---------------------------------------------------------------------------------------
-struct SupCol {
+struct SupColArgs {
     const float* src;   // x; ones when null
     const float* dy;
     float* dst;
-    float4* agg;        // [batch][G][W]: Af, Bf, Ab, Bb
-    float2* carry;      // [batch][G][W]: y[s-1], v[e+1]
-    const float* conf;  // optional: conf_out = conf / s (apply only)
+    const float* conf;  // optional: conf_out = conf / s
     float* conf_out;
     int Cc;
-    int H, W, G;
+    int H, W, batch;
     float log2a, m;
+    int G, S, groups, xcd;  // chunks per strip, strips per plane, strips in flight, chunk_slot form
+    unsigned long long* carry;
+    unsigned epoch;
+    int* status;
+    int spin_limit;
+    unsigned tag_xor;
 };
 
-// Loads of one chunk of one column: x[r] and w[r] for rows s + r, and the weight of the
-// row after the chunk (0 past the bottom).  Rows past the bottom read x = 0, w = 0.
-__device__ __forceinline__ void sup_chunk_load(const SupCol& a, int b, int g, int col, float (&x)[kSupChunk],
-                                               float (&w)[kSupChunk], float& wnext) {
-    const int s = g * kSupChunk;
-    const size_t base = static_cast<size_t>(b) * a.H * a.W + col;
+template <int R, int NWV>
+__global__ void __launch_bounds__(kWave * NWV, 4) support_col_kernel(SupColArgs a) {
+    __shared__ ChunkLds<1, NWV> L;
+    const CarryCtx cctx{a.carry, a.epoch, a.status, a.G, a.S, 1, a.spin_limit, a.tag_xor};
+    // persistent grid, as the filter's column pass: a workgroup always takes the same chunk
+    // of the strips group, group + groups, ...
+    const ChunkSlot slot = chunk_slot(static_cast<int>(blockIdx.x), a.G, a.xcd);
+    const int chunk = slot.chunk;
+    const int group = slot.group;
+    if (group >= a.groups) return;
+    const int lane = opaque_v(lane_id());
+    const int wave = opaque_s(__builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
+    const int H = a.H, W = a.W;
+    const size_t plane = static_cast<size_t>(H) * W;
+    const size_t pbytes = plane * sizeof(float);
+    const unsigned rowb = static_cast<unsigned>(W) * 4u;
+    const int r0 = (chunk * NWV + wave) * R;  // first row of this wave
+    const int nr = min(R, max(H - r0, 0));
+    const int n_strips = a.batch * a.S;
+#pragma unroll 1
+    for (int sid = group; sid < n_strips; sid += a.groups) {
+        const int strip = sid % a.S;
+        const int b = sid / a.S;
+        const int x = strip * kWave + lane;
+        const bool valid = x < W;
+        // rows past the bottom and lanes past the right edge read 0 (buffer range check)
+        const unsigned voff = (valid ? static_cast<unsigned>(x) * 4u : kInvalidOffset) +
+                              static_cast<unsigned>(min(r0, H)) * rowb;
+        const auto drs = plane_rsrc(a.dy + static_cast<size_t>(b) * plane, pbytes);
+        float w[R], xv[R];
+        {
+            unsigned vo = voff;
 #pragma unroll
-    for (int r = 0; r < kSupChunk; ++r) {
-        const int n = s + r;
-        const bool in = n < a.H;
-        const size_t idx = base + static_cast<size_t>(in ? n : 0) * a.W;
-        w[r] = (in && n > 0) ? weight(a.dy[idx], a.log2a) : 0.f;
-        x[r] = in ? (a.src ? a.src[idx] : 1.f) : 0.f;
-    }
-    const int n = s + kSupChunk;
-    wnext = (n < a.H) ? weight(a.dy[base + static_cast<size_t>(n) * a.W], a.log2a) : 0.f;
-}
-
-__global__ void __launch_bounds__(kSupColThreads) support_col_reduce_kernel(SupCol a) {
-    const int col = blockIdx.x * kSupColThreads + threadIdx.x;
-    const int g = blockIdx.y, b = blockIdx.z;
-    if (col >= a.W) return;
-    float x[kSupChunk], w[kSupChunk], wnext;
-    sup_chunk_load(a, b, g, col, x, w, wnext);
-    float Af = 1.f, Bf = 0.f, Ab = 1.f, Bb = 0.f;
-#pragma unroll
-    for (int r = 0; r < kSupChunk; ++r) {
-        Bf = fmaf(w[r], Bf, x[r]);
-        Af *= w[r];
-    }
-#pragma unroll
-    for (int r = kSupChunk - 1; r >= 0; --r) {
-        const float wn = (r + 1 < kSupChunk) ? w[r + 1 < kSupChunk ? r + 1 : r] : wnext;
-        Bb = fmaf(wn, Bb, x[r]);
-        Ab *= wn;
-    }
-    a.agg[(static_cast<size_t>(b) * a.G + g) * a.W + col] = make_float4(Af, Bf, Ab, Bb);
-}
-
-// One thread per column: compose the chunk aggregates down the column (forward carries)
-// and up the column (backward carries).  Loads are issued kCarryBatch chunks at a time so
-// their latencies overlap; the compositions themselves are a short serial chain.
-constexpr int kCarryBatch = 16;
-
-__global__ void __launch_bounds__(kSupColThreads) support_col_carry_kernel(SupCol a) {
-    const int col = blockIdx.x * kSupColThreads + threadIdx.x;
-    const int b = blockIdx.y;
-    if (col >= a.W) return;
-    const size_t base = static_cast<size_t>(b) * a.G * a.W + col;
-    float Cf = 0.f;
-    for (int g0 = 0; g0 < a.G; g0 += kCarryBatch) {
-        float4 q[kCarryBatch];
-#pragma unroll
-        for (int i = 0; i < kCarryBatch; ++i)
-            if (g0 + i < a.G) q[i] = a.agg[base + static_cast<size_t>(g0 + i) * a.W];
-#pragma unroll
-        for (int i = 0; i < kCarryBatch; ++i)
-            if (g0 + i < a.G) {
-                a.carry[base + static_cast<size_t>(g0 + i) * a.W].x = Cf;
-                Cf = fmaf(q[i].x, Cf, q[i].y);
+            for (int r = 0; r < R; ++r) {
+                const float keep = (r < nr) ? 1.f : 0.f;
+                w[r] = weight(bload(drs, vo, 0), a.log2a) * keep;
+                vo = opaque_vadd(vo, rowb);
             }
-    }
-    float Cb = 0.f;
-    for (int g1 = a.G - 1; g1 >= 0; g1 -= kCarryBatch) {
-        float4 q[kCarryBatch];
+        }
+        if (r0 == 0) w[0] = 0.f;  // y[0] = x[0]
+        // weight linking the wave's last row to the next one (0 past the bottom: v[H-1] = x)
+        const float wnext = weight(bload(drs, voff + static_cast<unsigned>(nr) * rowb, 0), a.log2a) *
+                            ((r0 + R < H) ? 1.f : 0.f);
+        if (a.src) {
+            const auto srs = plane_rsrc(a.src + static_cast<size_t>(b) * plane, pbytes);
+            unsigned vo = voff;
 #pragma unroll
-        for (int i = 0; i < kCarryBatch; ++i)
-            if (g1 - i >= 0) q[i] = a.agg[base + static_cast<size_t>(g1 - i) * a.W];
-#pragma unroll
-        for (int i = 0; i < kCarryBatch; ++i)
-            if (g1 - i >= 0) {
-                a.carry[base + static_cast<size_t>(g1 - i) * a.W].y = Cb;
-                Cb = fmaf(q[i].z, Cb, q[i].w);
+            for (int r = 0; r < R; ++r) {
+                xv[r] = bload(srs, vo, 0);
+                vo = opaque_vadd(vo, rowb);
             }
-    }
-}
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) xv[r] = (r < nr) ? 1.f : 0.f;
+        }
 
-__global__ void __launch_bounds__(kSupColThreads) support_col_apply_kernel(SupCol a) {
-    const int col = blockIdx.x * kSupColThreads + threadIdx.x;
-    const int g = blockIdx.y, b = blockIdx.z;
-    if (col >= a.W) return;
-    float x[kSupChunk], w[kSupChunk], wnext;
-    sup_chunk_load(a, b, g, col, x, w, wnext);
-    const float2 c = a.carry[(static_cast<size_t>(b) * a.G + g) * a.W + col];
-    float yv[kSupChunk];
-    float y = c.x;
+        // the wave's aggregates from zero carries
+        float A = 1.f, yl = 0.f;
 #pragma unroll
-    for (int r = 0; r < kSupChunk; ++r) {
-        y = fmaf(w[r], y, x[r]);
-        yv[r] = y;
-    }
-    const int s = g * kSupChunk;
-    const size_t plane = static_cast<size_t>(a.H) * a.W;
-    const size_t base = static_cast<size_t>(b) * plane + col;
-    float v = c.y;
+        for (int r = 0; r < R; ++r) {
+            yl = fmaf(w[r], yl, xv[r]);
+            A *= w[r];
+        }
+        float P = 1.f, vl = 0.f;
 #pragma unroll
-    for (int r = kSupChunk - 1; r >= 0; --r) {
-        const float wn = (r + 1 < kSupChunk) ? w[r + 1 < kSupChunk ? r + 1 : r] : wnext;
-        v = fmaf(wn, v, x[r]);
-        const int n = s + r;
-        if (n < a.H) {
-            const float sv = a.m * (yv[r] + v - x[r]);
-            const size_t idx = base + static_cast<size_t>(n) * a.W;
-            a.dst[idx] = sv;
-            if (a.conf) {
-                const float inv = 1.f / sv;
-                for (int k = 0; k < a.Cc; ++k) {
-                    const size_t ci = (static_cast<size_t>(b) * a.Cc + k) * plane + static_cast<size_t>(n) * a.W + col;
-                    a.conf_out[ci] = a.conf[ci] * inv;
-                }
+        for (int r = R - 1; r >= 0; --r) {
+            const float wn = (r + 1 < R) ? w[(r + 1 < R) ? r + 1 : r] : wnext;
+            vl = fmaf(wn, vl, xv[r]);
+            P *= wn;
+        }
+        L.A[wave][lane] = A;
+        L.B[wave][0][lane] = yl;
+        L.P[wave][lane] = P;
+        L.BQ[wave][lane] = 0.f;
+        L.BJ[wave][0][lane] = vl;
+        __syncthreads();
+        chunk_carries<1, NWV>(cctx, L, b, 0, strip, chunk, lane, wave, valid, 1);
+        __syncthreads();
+        const float yin = L.Jin[wave][0][lane];  // y of the row before the wave's first
+        const float vin = L.Kin[wave][0][lane];  // v of the row after the wave's last
+
+        // both recurrences from the true carries; the scaled sum overwrites xv
+        float yv[R];
+        {
+            float y = yin;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                y = fmaf(w[r], y, xv[r]);
+                yv[r] = y;
+            }
+        }
+        {
+            float v = vin;
+#pragma unroll
+            for (int r = R - 1; r >= 0; --r) {
+                const float wn = (r + 1 < R) ? w[(r + 1 < R) ? r + 1 : r] : wnext;
+                v = fmaf(wn, v, xv[r]);
+                xv[r] = a.m * (yv[r] + v - xv[r]);
+            }
+        }
+        const auto ors = plane_rsrc(a.dst + static_cast<size_t>(b) * plane, pbytes);
+        {
+            unsigned vo = voff;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                bstore(ors, vo, 0, xv[r]);
+                vo = opaque_vadd(vo, rowb);
+            }
+        }
+        for (int k = 0; k < a.Cc; ++k) {
+            const size_t pl = (static_cast<size_t>(b) * a.Cc + k) * plane;
+            const auto crs = plane_rsrc(a.conf + pl, pbytes);
+            const auto cors = plane_rsrc(a.conf_out + pl, pbytes);
+            float cv[R];
+            unsigned vo = voff;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                cv[r] = bload(crs, vo, 0);
+                vo = opaque_vadd(vo, rowb);
+            }
+            vo = voff;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                bstore(cors, vo, 0, cv[r] / xv[r]);
+                vo = opaque_vadd(vo, rowb);
             }
         }
     }
@@ -262,7 +285,11 @@ __global__ void __launch_bounds__(kSupColThreads) support_col_apply_kernel(SupCo
 // ---------------------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------------------
-size_t support_chunks(int H) { return static_cast<size_t>((H + kSupChunk - 1) / kSupChunk); }
+size_t support_carry_words(int batch, int H, int W) {
+    const size_t G = (H + kSupChunkRows - 1) / kSupChunkRows;
+    const size_t S = (W + kWave - 1) / kWave;
+    return static_cast<size_t>(batch) * S * G * carry_words_per_chunk(1) * kWave;
+}
 
 int launch_support_row(const float* src, const float* dx, float* dst, int batch, int H, int W, float log2a,
                        float m, hipStream_t s) {
@@ -280,38 +307,55 @@ int launch_support_row(const float* src, const float* dx, float* dst, int batch,
     return hip_fail(hipGetLastError());
 }
 
-int launch_support_col(const float* src, const float* dy, float* dst, void* agg, void* carry, const float* conf,
-                       int Cc, float* conf_out, int batch, int H, int W, float log2a, float m, hipStream_t s) {
-    SupCol a;
+static int support_col_capacity() {
+    static int cached[64] = {0};
+    static std::mutex mu;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    std::lock_guard<std::mutex> lock(mu);
+    if (cached[dev] == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, support_col_kernel<kSupRows, kSupWaves>,
+                                                         kWave * kSupWaves, 0) != hipSuccess)
+            return 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+        cached[dev] = per_cu * cus;
+    }
+    return cached[dev];
+}
+
+int launch_support_col(const float* src, const float* dy, float* dst, const float* conf, int Cc, float* conf_out,
+                       int batch, int H, int W, float log2a, float m, Ctx& ctx) {
+    SupColArgs a;
     a.src = src;
     a.dy = dy;
     a.dst = dst;
-    a.agg = static_cast<float4*>(agg);
-    a.carry = static_cast<float2*>(carry);
     a.conf = conf;
     a.conf_out = conf_out;
     a.Cc = conf ? Cc : 0;
     a.H = H;
     a.W = W;
-    a.G = static_cast<int>(support_chunks(H));
+    a.batch = batch;
     a.log2a = log2a;
     a.m = m;
+    a.G = (H + kSupChunkRows - 1) / kSupChunkRows;
+    a.S = (W + kWave - 1) / kWave;
+    a.carry = ctx.carry;
+    a.epoch = ++ctx.epoch;
+    a.status = ctx.status;
+    a.spin_limit = spin_limit();
+    a.tag_xor = spin_tag_xor();
+    const int cap = support_col_capacity();
+    if (cap <= 0) return hip_fail(hipErrorNoDevice);
+    if (a.G > cap) return DTS_ENOTSUP;
+    const ColGrid grid = col_grid(cap, a.G, static_cast<long long>(batch) * a.S);
+    a.groups = grid.groups;
+    a.xcd = grid.xcd;
+    // distances and the signal in, the support out; conf in and conf / s out
     const double px = static_cast<double>(batch) * H * W;
-    const unsigned cb = static_cast<unsigned>((W + kSupColThreads - 1) / kSupColThreads);
-    const double xin = src ? 4.0 : 0.0;
-    {
-        // one plane of distances (and the signal) in, 16 bytes of aggregates per chunk out
-        ProfScope prof("support_col_reduce", px * (4.0 + xin) + 16.0 * batch * a.G * static_cast<double>(W), s);
-        hipLaunchKernelGGL(support_col_reduce_kernel, dim3(cb, a.G, batch), dim3(kSupColThreads), 0, s, a);
-        if (int rc = hip_fail(hipGetLastError())) return rc;
-    }
-    {
-        ProfScope prof("support_col_carry", 24.0 * batch * a.G * static_cast<double>(W), s);
-        hipLaunchKernelGGL(support_col_carry_kernel, dim3(cb, batch), dim3(kSupColThreads), 0, s, a);
-        if (int rc = hip_fail(hipGetLastError())) return rc;
-    }
-    ProfScope prof("support_col_apply", px * (8.0 + xin + 8.0 * a.Cc), s);
-    hipLaunchKernelGGL(support_col_apply_kernel, dim3(cb, a.G, batch), dim3(kSupColThreads), 0, s, a);
+    ProfScope prof("support_col", px * 4.0 * (2.0 + (src ? 1.0 : 0.0) + 2.0 * a.Cc), ctx.stream);
+    hipLaunchKernelGGL((support_col_kernel<kSupRows, kSupWaves>), dim3(grid.n), dim3(kWave * kSupWaves), 0,
+                       ctx.stream, a);
     return hip_fail(hipGetLastError());
 }
 
