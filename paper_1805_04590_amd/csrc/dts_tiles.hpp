@@ -321,6 +321,10 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, const CarryCtx& cctx,
     // and rows past the bottom edge get weight 0: that is the boundary J[0] = f[0] going
     // down and K[H-1] = J[H-1] going up, and it makes padded rows drop out of both
     // recurrences.
+    // The chunk's loads are issued at raised wave priority, so the issue of a workgroup
+    // starting its tile is not held back by the ALU work of the CU's other workgroups
+    // (10240^2 one-channel column pass 298 -> 293 us, 16-band solve 19.25 -> 19.10 ms).
+    __builtin_amdgcn_s_setprio(3);
     float w[R];
     const auto drs = plane_rsrc(a.d + static_cast<size_t>(b) * plane, pbytes);
     {
@@ -349,6 +353,7 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, const CarryCtx& cctx,
         }
     }
 
+    __builtin_amdgcn_s_setprio(0);
     // phase 1: causal scan of the wave's rows with zero carry-in, plus the anticausal
     // coefficients:  K[first] = BJ + BQ * J_carry + P * K_carry
     float Q = 1.f, pi = 1.f, BQ = 0.f;
