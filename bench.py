@@ -256,13 +256,24 @@ def fwd_bwd_leg(steps, warmup):
         state["z"], state["ck"] = dts.solve(g, t, cf, c["sigma_s"], c["sigma_r"], 3, T,
                                             checkpoints=True, out=out, workspace=ws)
 
-    def fwd_bwd():
+    def fwd_bwd_recompute():
         fwd()
         go = 2.0 * (state["z"] - r)
         dts.solve_backward(g, t, cf, state["ck"], go, c["sigma_s"], c["sigma_r"], 3, T,
                            workspace=wsb)
 
+    # the forward keeps every filter pass's output (2N - 1 signals per iteration) and the
+    # backward reads them instead of recomputing them (the tape comes from torch's caching
+    # allocator, reused call after call)
+    def fwd_bwd():
+        res = dts.solve(g, t, cf, c["sigma_s"], c["sigma_r"], 3, T, tape=True, out=out, workspace=ws)
+        z, ck, tp = res
+        state["z"] = z
+        go = 2.0 * (z - r)
+        dts.solve_backward(g, t, cf, ck, go, c["sigma_s"], c["sigma_r"], 3, T, workspace=wsb, tape=tp)
+
     ms_f = timed(fwd, steps, warmup)
+    ms_fbr = timed(fwd_bwd_recompute, steps, warmup)
     ms_fb = timed(fwd_bwd, steps, warmup)
     dts.workspace_status(ws)
     dts.workspace_status(wsb)
@@ -283,6 +294,9 @@ def fwd_bwd_leg(steps, warmup):
                 fwd_ms=round(ms_f, 3), fwd_mpix_s=round(px / ms_f / 1e3, 1),
                 fwd_bwd_ms=round(ms_fb, 3), fwd_bwd_mpix_s=round(px / ms_fb / 1e3, 1),
                 fwd_bwd_over_fwd=round(ms_fb / ms_f, 3),
+                fwd_bwd_mode=f"pass tape: the forward keeps 2N-1 = 5 pass outputs per iteration "
+                             f"({T * 5 * B * Ct * H * W * 4 / 1e9:.2f} GB) for the backward",
+                fwd_bwd_recompute_ms=round(ms_fbr, 3),
                 fwd_bwd_algorithmic_bytes=fb_bytes,
                 algorithmic_GBps=round(fb_bytes / (ms_fb / 1e3) / 1e9, 1),
                 hbm_frac=round(fb_bytes / (ms_fb / 1e3) / 1e9 / HBM_PEAK_GBPS, 4),

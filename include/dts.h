@@ -116,6 +116,24 @@ int dts_solve_backward(const float* guide, int Cg, const float* target, const fl
                        float* grad_conf, float* grad_guide, void* workspace,
                        size_t workspace_bytes, void* stream);
 
+/* dts_solve and dts_solve_backward trading memory for the backward's recomputation (the
+ * store-or-recompute choice of reverse mode; not in the paper).  dts_solve_tape is
+ * dts_solve that also keeps, for every iteration k < T, the outputs of the first 2N - 1
+ * of its 2N filter passes (N = filter_iters) in tape [T][2N-1][batch][Ct][H][W]; they go
+ * there instead of into the workspace, so the forward moves the same bytes.
+ * checkpoints and tape are required when T > 0 (DTS_EINVAL otherwise).
+ * dts_solve_backward_tape is dts_solve_backward reading those pass inputs from tape
+ * instead of recomputing them from the checkpoints (2N - 1 passes per iteration fewer);
+ * its gradients are bitwise those of dts_solve_backward.  Workspaces as for dts_solve and
+ * dts_solve_backward. */
+int dts_solve_tape(const float* guide, int Cg, const float* target, const float* conf, int Cc, int Ct,
+                   int batch, int H, int W, const dts_params* p, float* out, float* checkpoints, float* tape,
+                   void* workspace, size_t workspace_bytes, void* stream);
+int dts_solve_backward_tape(const float* guide, int Cg, const float* target, const float* conf, int Cc,
+                            int Ct, int batch, int H, int W, const dts_params* p, const float* checkpoints,
+                            const float* tape, const float* grad_out, float* grad_target, float* grad_conf,
+                            float* grad_guide, void* workspace, size_t workspace_bytes, void* stream);
+
 /* ---- Stereo refinement (Eq. (11), Sec. 3.3) ---- */
 
 /* Workspace for dts_solve_stereo (0 if the shape is invalid). */

@@ -70,6 +70,8 @@ EXPORTED_SYMBOLS = (
     "dts_filter",
     "dts_solve",
     "dts_solve_backward",
+    "dts_solve_tape",
+    "dts_solve_backward_tape",
     "dts_solve_noalloc",
     "dts_workspace_status",
     "dts_strerror",
@@ -211,6 +213,11 @@ def library():
     lib.dts_solve_backward.argtypes = [fp, i, fp, fp, i, i, i, i, i, P, fp, fp, fp, fp, fp,
                                        vp, sz, vp]
     lib.dts_solve_backward.restype = i
+    lib.dts_solve_tape.argtypes = [fp, i, fp, fp, i, i, i, i, i, P, fp, fp, fp, vp, sz, vp]
+    lib.dts_solve_tape.restype = i
+    lib.dts_solve_backward_tape.argtypes = [fp, i, fp, fp, i, i, i, i, i, P, fp, fp, fp, fp, fp, fp,
+                                            vp, sz, vp]
+    lib.dts_solve_backward_tape.restype = i
     lib.dts_solve_noalloc.argtypes = [fp, i, fp, fp, i, i, i, i, i, P, fp, fp, vp]
     lib.dts_solve_noalloc.restype = i
     lib.dts_solve_stereo_workspace_bytes.argtypes = [i, i, i]
@@ -757,14 +764,17 @@ def support(guide, sigma_s, sigma_r, filter_iters=3, conf=None, out=None, conf_o
 
 
 def solve(guide, target, conf, sigma_s, sigma_r, filter_iters=3, solver_iters=10, lam=0.99,
-          step=0.99, checkpoints=False, out=None, workspace=None, check=None):
+          step=0.99, checkpoints=False, out=None, workspace=None, check=None, tape=False):
     """z^T of the Eq. (3) gradient descent started at z^0 = target.
 
     With ``checkpoints=True`` also returns the [T][B][Ct][H][W] tensor of iterates
-    z^0..z^{T-1} that ``solve_backward`` consumes.  ``check``: wait for the solve and
-    read the workspace's device status (default: only when the workspace is allocated
-    here, since nobody else could read it); a caller passing ``workspace`` may read it
-    later with ``workspace_status``."""
+    z^0..z^{T-1} that ``solve_backward`` consumes.  With ``tape=True`` (implies
+    checkpoints) also returns the [T][2N-1][B][Ct][H][W] tensor of every iteration's
+    filter-pass outputs (``dts_solve_tape``), which ``solve_backward(tape=...)`` reads
+    instead of recomputing.  ``check``: wait for the solve and read the workspace's
+    device status (default: only when the workspace is allocated here, since nobody else
+    could read it); a caller passing ``workspace`` may read it later with
+    ``workspace_status``."""
     g = _as4d(guide, "guide")
     t = _as4d(target, "target")
     c = _as4d(conf, "conf")
@@ -774,19 +784,30 @@ def solve(guide, target, conf, sigma_s, sigma_r, filter_iters=3, solver_iters=10
     p = Params(sigma_s, sigma_r, filter_iters, solver_iters, lam, step).c()
     lib = library()
     out = torch.empty_like(t) if out is None else _out_like(out, t)
-    ck = None
-    if checkpoints:
-        ck = torch.empty((max(int(solver_iters), 0),) + tuple(t.shape), dtype=torch.float32,
+    ck = tp = None
+    T = max(int(solver_iters), 0)
+    if checkpoints or tape:
+        ck = torch.empty((T,) + tuple(t.shape), dtype=torch.float32, device=t.device)
+    if tape:
+        tp = torch.empty((T, 2 * int(filter_iters) - 1) + tuple(t.shape), dtype=torch.float32,
                          device=t.device)
     internal = workspace is None
     if internal:
         workspace = _workspace(lib.dts_solve_workspace_bytes(B, H, W, Ct, ctypes.byref(p)), t.device)
-    rc = lib.dts_solve(_ptr(g), g.shape[1], _ptr(t), _ptr(c), c.shape[1], Ct, B, H, W,
-                       ctypes.byref(p), _ptr(out), _ptr(ck) if ck is not None and ck.numel() else None,
-                       _ptr(workspace), workspace.numel(), _stream())
-    _check(rc, "dts_solve")
+    ckp = _ptr(ck) if ck is not None and ck.numel() else None
+    if tape:
+        rc = lib.dts_solve_tape(_ptr(g), g.shape[1], _ptr(t), _ptr(c), c.shape[1], Ct, B, H, W,
+                                ctypes.byref(p), _ptr(out), ckp, _ptr(tp) if tp.numel() else None,
+                                _ptr(workspace), workspace.numel(), _stream())
+        _check(rc, "dts_solve_tape")
+    else:
+        rc = lib.dts_solve(_ptr(g), g.shape[1], _ptr(t), _ptr(c), c.shape[1], Ct, B, H, W,
+                           ctypes.byref(p), _ptr(out), ckp, _ptr(workspace), workspace.numel(), _stream())
+        _check(rc, "dts_solve")
     _finish(workspace, internal, check, "dts_solve")
     res = out if target.dim() == 4 else out[0]
+    if tape:
+        return res, ck, tp
     if checkpoints:
         return res, ck
     return res
@@ -820,9 +841,10 @@ def solve_noalloc(guide, target, conf, out, sigma_s, sigma_r, filter_iters=3, so
 
 def solve_backward(guide, target, conf, checkpoints, grad_out, sigma_s, sigma_r, filter_iters=3,
                    solver_iters=10, lam=0.99, step=0.99, need=(True, True, True),
-                   workspace=None, check=None):
+                   workspace=None, check=None, tape=None):
     """(dL/dtarget, dL/dconf, dL/dguide) given dL/dz^T and the checkpoints of ``solve``.
-    ``check`` as for ``solve``."""
+    With ``tape`` (from ``solve(tape=True)``) the filter-pass inputs are read from it
+    instead of recomputed (``dts_solve_backward_tape``).  ``check`` as for ``solve``."""
     g = _as4d(guide, "guide")
     t = _as4d(target, "target")
     c = _as4d(conf, "conf")
@@ -836,6 +858,10 @@ def solve_backward(guide, target, conf, checkpoints, grad_out, sigma_s, sigma_r,
     if checkpoints.shape != (T,) + tuple(t.shape) or checkpoints.dtype != torch.float32 \
             or not checkpoints.is_contiguous() or checkpoints.device != t.device:
         raise ValueError("checkpoints must be the [T][B][Ct][H][W] float32 tensor from solve()")
+    if tape is not None and (tape.shape != (T, 2 * int(filter_iters) - 1) + tuple(t.shape)
+                             or tape.dtype != torch.float32 or not tape.is_contiguous()
+                             or tape.device != t.device):
+        raise ValueError("tape must be the [T][2N-1][B][Ct][H][W] float32 tensor from solve(tape=True)")
     p = Params(sigma_s, sigma_r, filter_iters, solver_iters, lam, step).c()
     lib = library()
     gt = torch.empty_like(t) if need[0] else None
@@ -845,11 +871,18 @@ def solve_backward(guide, target, conf, checkpoints, grad_out, sigma_s, sigma_r,
     if internal:
         workspace = _workspace(lib.dts_solve_backward_workspace_bytes(
             B, H, W, g.shape[1], Ct, ctypes.byref(p)), t.device)
-    rc = lib.dts_solve_backward(_ptr(g), g.shape[1], _ptr(t), _ptr(c), c.shape[1], Ct, B, H, W,
-                                ctypes.byref(p), _ptr(checkpoints) if T else None, _ptr(go),
-                                _ptr(gt), _ptr(gc), _ptr(gg), _ptr(workspace), workspace.numel(),
-                                _stream())
-    _check(rc, "dts_solve_backward")
+    if tape is not None:
+        rc = lib.dts_solve_backward_tape(_ptr(g), g.shape[1], _ptr(t), _ptr(c), c.shape[1], Ct, B, H, W,
+                                         ctypes.byref(p), _ptr(checkpoints) if T else None,
+                                         _ptr(tape) if T else None, _ptr(go), _ptr(gt), _ptr(gc), _ptr(gg),
+                                         _ptr(workspace), workspace.numel(), _stream())
+        _check(rc, "dts_solve_backward_tape")
+    else:
+        rc = lib.dts_solve_backward(_ptr(g), g.shape[1], _ptr(t), _ptr(c), c.shape[1], Ct, B, H, W,
+                                    ctypes.byref(p), _ptr(checkpoints) if T else None, _ptr(go),
+                                    _ptr(gt), _ptr(gc), _ptr(gg), _ptr(workspace), workspace.numel(),
+                                    _stream())
+        _check(rc, "dts_solve_backward")
     _finish(workspace, internal, check, "dts_solve_backward")
     squeeze = target.dim() == 3
     fix = (lambda x: x[0] if (x is not None and squeeze) else x)
@@ -859,26 +892,36 @@ def solve_backward(guide, target, conf, checkpoints, grad_out, sigma_s, sigma_r,
 class DTSFunction(torch.autograd.Function):
     """z^T = solve(guide, target, conf) with gradients for all three inputs through the
     hand-written adjoint (per-iteration checkpoints, recomputed filter passes).
-    ``apply(guide, target, conf, params, check=True)``: with ``check`` the forward and the
-    backward each wait for their kernels and raise DTSError if a bounded wait inside
-    them gave up; ``check=False`` keeps both fully asynchronous."""
+    ``apply(guide, target, conf, params, check=True, tape=False)``: with ``check`` the
+    forward and the backward each wait for their kernels and raise DTSError if a bounded
+    wait inside them gave up; ``check=False`` keeps both fully asynchronous.  With
+    ``tape`` the forward also keeps every filter pass's output (2N - 1 signals per
+    iteration) and the backward reads them instead of recomputing them."""
 
     @staticmethod
-    def forward(ctx, guide, target, conf, params: Params, check=True):
-        z, ck = solve(guide, target, conf, params.sigma_s, params.sigma_r, params.filter_iters,
-                      params.solver_iters, params.lam, params.step, checkpoints=True,
-                      check=bool(check))
-        ctx.save_for_backward(guide, target, conf, ck)
+    def forward(ctx, guide, target, conf, params: Params, check=True, tape=False):
+        res = solve(guide, target, conf, params.sigma_s, params.sigma_r, params.filter_iters,
+                    params.solver_iters, params.lam, params.step, checkpoints=True,
+                    check=bool(check), tape=bool(tape))
+        if tape:
+            z, ck, tp = res
+            ctx.save_for_backward(guide, target, conf, ck, tp)
+        else:
+            z, ck = res
+            ctx.save_for_backward(guide, target, conf, ck)
         ctx.params = params
         ctx.check = bool(check)
+        ctx.tape = bool(tape)
         return z
 
     @staticmethod
     def backward(ctx, grad_z):
-        guide, target, conf, ck = ctx.saved_tensors
+        saved = ctx.saved_tensors
+        guide, target, conf, ck = saved[:4]
+        tp = saved[4] if ctx.tape else None
         p = ctx.params
         need = ctx.needs_input_grad[:3]
         gt, gc, gg = solve_backward(guide, target, conf, ck, grad_z.contiguous(), p.sigma_s,
                                     p.sigma_r, p.filter_iters, p.solver_iters, p.lam, p.step,
-                                    need=(need[1], need[2], need[0]), check=ctx.check)
-        return gg, gt, gc, None, None
+                                    need=(need[1], need[2], need[0]), check=ctx.check, tape=tp)
+        return gg, gt, gc, None, None, None

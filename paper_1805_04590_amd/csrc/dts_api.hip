@@ -372,9 +372,13 @@ int dts_filter(const float* guide, int Cg, const float* src, float* dst, int Cs,
     return DTS_OK;
 }
 
-int dts_solve(const float* guide, int Cg, const float* target, const float* conf, int Cc, int Ct,
-              int batch, int H, int W, const dts_params* p, float* out, float* checkpoints,
-              void* workspace, size_t workspace_bytes, void* stream) {
+// The solve of Eq. (3).  With `tape` (T > 0 needs checkpoints too) the outputs of the
+// first 2N - 1 passes of every iteration go to tape[k][pass - 1] instead of the
+// workspace's pass buffer: the same bytes move, and dts_solve_backward_tape reads them
+// back instead of recomputing them.
+static int solve_impl(const float* guide, int Cg, const float* target, const float* conf, int Cc, int Ct,
+                      int batch, int H, int W, const dts_params* p, float* out, float* checkpoints, float* tape,
+                      void* workspace, size_t workspace_bytes, void* stream) {
     if (!guide || !target || !conf || !out || !p) return DTS_EINVAL;
     int rc = check_shape(batch, H, W);
     if (rc) return rc;
@@ -393,14 +397,18 @@ int dts_solve(const float* guide, int Cg, const float* target, const float* conf
     if (checkpoints && (rc = launch_copy(checkpoints, target, sig, S.ctx.stream))) return rc;
     const float s2 = static_cast<float>((static_cast<double>(p->sigma_s) / p->sigma_r) *
                                         (static_cast<double>(p->sigma_s) / p->sigma_r));
+    const int npass = 2 * N;
     for (int k = 0; k < T; ++k) {
         const float* zk = (k == 0) ? target : (checkpoints ? checkpoints + k * sig : out);
         float* znext = (k == T - 1) ? out : (checkpoints ? checkpoints + (k + 1) * sig : out);
+        // output of pass q (1 <= q < 2N) of this iteration
+        float* const tk = tape ? tape + static_cast<size_t>(k) * (npass - 1) * sig : nullptr;
+        const auto pass_out = [&](int q) -> float* { return tk ? tk + static_cast<size_t>(q - 1) * sig : S.tmp; };
         for (int i = 1; i <= N; ++i) {
             const float l2a = log2_feedback(p->sigma_s, i, N);
             RowPass rp{};
-            rp.src = (i == 1) ? zk : S.tmp;
-            rp.dst = S.tmp;
+            rp.src = (i == 1) ? zk : pass_out(2 * i - 2);
+            rp.dst = pass_out(2 * i - 1);
             rp.d = S.dx;
             rp.guide = (k == 0 && i == 1) ? guide : nullptr;
             rp.dx_out = S.dx;
@@ -414,8 +422,8 @@ int dts_solve(const float* guide, int Cg, const float* target, const float* conf
             rp.log2a = l2a;
             if ((rc = launch_row_pass(rp, S.ctx))) return rc;
             ColPass cp{};
-            cp.src = S.tmp;
-            cp.dst = (i == N) ? znext : S.tmp;
+            cp.src = pass_out(2 * i - 1);
+            cp.dst = (i == N) ? znext : pass_out(2 * i);
             cp.d = S.dy;
             cp.C = Ct;
             cp.H = H;
@@ -436,6 +444,22 @@ int dts_solve(const float* guide, int Cg, const float* target, const float* conf
     return DTS_OK;
 }
 
+int dts_solve(const float* guide, int Cg, const float* target, const float* conf, int Cc, int Ct,
+              int batch, int H, int W, const dts_params* p, float* out, float* checkpoints,
+              void* workspace, size_t workspace_bytes, void* stream) {
+    return solve_impl(guide, Cg, target, conf, Cc, Ct, batch, H, W, p, out, checkpoints, nullptr, workspace,
+                      workspace_bytes, stream);
+}
+
+int dts_solve_tape(const float* guide, int Cg, const float* target, const float* conf, int Cc, int Ct,
+                   int batch, int H, int W, const dts_params* p, float* out, float* checkpoints, float* tape,
+                   void* workspace, size_t workspace_bytes, void* stream) {
+    if (!p) return DTS_EINVAL;
+    if (p->solver_iters > 0 && (!checkpoints || !tape)) return DTS_EINVAL;
+    return solve_impl(guide, Cg, target, conf, Cc, Ct, batch, H, W, p, out, checkpoints, tape, workspace,
+                      workspace_bytes, stream);
+}
+
 int dts_solve_noalloc(const float* guide, int Cg, const float* target, const float* conf, int Cc, int Ct,
                       int batch, int H, int W, const dts_params* p, float* out, float* checkpoints,
                       void* stream) {
@@ -450,11 +474,13 @@ int dts_solve_noalloc(const float* guide, int Cg, const float* target, const flo
                      stream);
 }
 
-int dts_solve_backward(const float* guide, int Cg, const float* target, const float* conf, int Cc,
-                       int Ct, int batch, int H, int W, const dts_params* p,
-                       const float* checkpoints, const float* grad_out, float* grad_target,
-                       float* grad_conf, float* grad_guide, void* workspace,
-                       size_t workspace_bytes, void* stream) {
+// The adjoint of solve_impl.  With `tape_ext` (written by dts_solve_tape) the inputs of
+// every iteration's passes are read from it; without, they are recomputed from the
+// checkpoint into the workspace's tape.
+static int backward_impl(const float* guide, int Cg, const float* target, const float* conf, int Cc, int Ct,
+                         int batch, int H, int W, const dts_params* p, const float* checkpoints,
+                         const float* tape_ext, const float* grad_out, float* grad_target, float* grad_conf,
+                         float* grad_guide, void* workspace, size_t workspace_bytes, void* stream) {
     if (!guide || !target || !conf || !grad_out || !p) return DTS_EINVAL;
     int rc = check_shape(batch, H, W);
     if (rc) return rc;
@@ -466,6 +492,7 @@ int dts_solve_backward(const float* guide, int Cg, const float* target, const fl
     if (!isfinite(p->lambda) || !isfinite(p->step)) return DTS_EINVAL;
     const int T = p->solver_iters, N = p->filter_iters;
     if (T > 0 && !checkpoints) return DTS_EINVAL;
+    const float* const tape_in = tape_ext;
     const BwdLayout L = make_backward_layout(batch, H, W, Ct, N);
     if (!workspace || workspace_bytes < L.total || (reinterpret_cast<uintptr_t>(workspace) & 15u))
         return DTS_EWORKSPACE;
@@ -479,7 +506,7 @@ int dts_solve_backward(const float* guide, int Cg, const float* target, const fl
     float* dy = reinterpret_cast<float*>(base + L.dy);
     float* gdx = grad_guide ? reinterpret_cast<float*>(base + L.gdx) : nullptr;
     float* gdy = grad_guide ? reinterpret_cast<float*>(base + L.gdy) : nullptr;
-    float* tape = reinterpret_cast<float*>(base + L.tape);
+    float* ws_tape = reinterpret_cast<float*>(base + L.tape);
     float* gz = reinterpret_cast<float*>(base + L.gz);
     float* gab[2] = {reinterpret_cast<float*>(base + L.ga), reinterpret_cast<float*>(base + L.gb)};
     const size_t plane = static_cast<size_t>(batch) * H * W;
@@ -516,14 +543,16 @@ int dts_solve_backward(const float* guide, int Cg, const float* target, const fl
     const int npass = 2 * N;
     for (int k = T - 1; k >= 0; --k) {
         const float* zk = checkpoints + static_cast<size_t>(k) * sig;
-        // recompute the inputs of passes 2..2N of DT(z^k): pass p reads in(p), writes in(p+1)
+        // inputs of passes 2..2N of DT(z^k): pass p reads in(p) and writes in(p+1), kept by
+        // the forward in the caller's tape or recomputed here into the workspace's
+        const float* const tk = tape_in ? tape_in + static_cast<size_t>(k) * (npass - 1) * sig : ws_tape;
         auto in = [&](int pass) -> const float* {
-            return pass == 1 ? zk : tape + static_cast<size_t>(pass - 2) * sig;
+            return pass == 1 ? zk : tk + static_cast<size_t>(pass - 2) * sig;
         };
-        for (int pass = 1; pass < npass; ++pass) {
+        for (int pass = 1; pass < npass && !tape_in; ++pass) {
             const int i = (pass + 1) / 2;
             const float l2a = log2_feedback(p->sigma_s, i, N);
-            float* out = tape + static_cast<size_t>(pass - 1) * sig;
+            float* out = ws_tape + static_cast<size_t>(pass - 1) * sig;
             if (pass & 1) {
                 RowPass rp{};
                 rp.src = in(pass);
@@ -606,6 +635,25 @@ int dts_solve_backward(const float* guide, int Cg, const float* target, const fl
         if ((rc = launch_dist_adjoint(da, ctx))) return rc;
     }
     return DTS_OK;
+}
+
+int dts_solve_backward(const float* guide, int Cg, const float* target, const float* conf, int Cc,
+                       int Ct, int batch, int H, int W, const dts_params* p,
+                       const float* checkpoints, const float* grad_out, float* grad_target,
+                       float* grad_conf, float* grad_guide, void* workspace,
+                       size_t workspace_bytes, void* stream) {
+    return backward_impl(guide, Cg, target, conf, Cc, Ct, batch, H, W, p, checkpoints, nullptr, grad_out,
+                         grad_target, grad_conf, grad_guide, workspace, workspace_bytes, stream);
+}
+
+int dts_solve_backward_tape(const float* guide, int Cg, const float* target, const float* conf, int Cc,
+                            int Ct, int batch, int H, int W, const dts_params* p, const float* checkpoints,
+                            const float* tape, const float* grad_out, float* grad_target, float* grad_conf,
+                            float* grad_guide, void* workspace, size_t workspace_bytes, void* stream) {
+    if (!p) return DTS_EINVAL;
+    if (p->solver_iters > 0 && !tape) return DTS_EINVAL;
+    return backward_impl(guide, Cg, target, conf, Cc, Ct, batch, H, W, p, checkpoints, tape, grad_out,
+                         grad_target, grad_conf, grad_guide, workspace, workspace_bytes, stream);
 }
 
 static size_t stereo_workspace_bytes(int batch, int H, int W) {

@@ -104,6 +104,26 @@ def test_solve_rejects_bad_arguments_without_launching(lib):
     assert s(_fake(), 3, _fake(2), _fake(3), 1, 1, 1, 8, 8, None, _fake(4), None, ws, 0, None) == dts.DTS_EINVAL
 
 
+def test_tape_entry_points_reject_missing_buffers_without_launching(lib):
+    ws = ctypes.c_void_p(0)
+    good = P(8.0, 0.2, 3, 10, 0.99, 0.99)
+    st = lib.dts_solve_tape
+    # T > 0 needs both the checkpoints and the tape
+    assert st(_fake(), 3, _fake(2), _fake(3), 1, 1, 1, 8, 8, ctypes.byref(good), _fake(4), None, _fake(5),
+              ws, 0, None) == dts.DTS_EINVAL
+    assert st(_fake(), 3, _fake(2), _fake(3), 1, 1, 1, 8, 8, ctypes.byref(good), _fake(4), _fake(5), None,
+              ws, 0, None) == dts.DTS_EINVAL
+    assert st(_fake(), 3, _fake(2), _fake(3), 1, 1, 1, 8, 8, ctypes.byref(good), _fake(4), _fake(5), _fake(6),
+              ws, 0, None) == dts.DTS_EWORKSPACE
+    bt = lib.dts_solve_backward_tape
+    assert bt(_fake(), 3, _fake(2), _fake(3), 1, 1, 1, 8, 8, ctypes.byref(good), _fake(4), None, _fake(5),
+              None, None, None, ws, 0, None) == dts.DTS_EINVAL
+    assert bt(_fake(), 3, _fake(2), _fake(3), 1, 1, 1, 8, 8, ctypes.byref(good), _fake(4), _fake(6), _fake(5),
+              None, None, None, ws, 0, None) == dts.DTS_EWORKSPACE
+    assert st(_fake(), 3, _fake(2), _fake(3), 1, 1, 1, 8, 8, None, _fake(4), None, None, ws, 0, None) == \
+        dts.DTS_EINVAL
+
+
 def test_binding_refuses_cpu_tensors():
     import torch
     g = torch.zeros(3, 8, 8)

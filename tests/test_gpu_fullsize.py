@@ -135,6 +135,23 @@ def test_rgb_batch_8x1024_gradients_match_directional_derivatives():
     assert abs(an - fd) <= 2e-3 * abs(fd)
 
 
+def test_rgb_batch_8x1024_tape_path_matches_the_recomputing_one():
+    """The forward + backward the benchmark times (pass outputs kept in a tape, no
+    recomputation) against the recomputing path at full size, bit for bit; the
+    recomputing path is checked against the oracle below."""
+    c = dts_inputs.rgb_batch_8x1024()
+    ss, sr, N, T = c["sigma_s"], c["sigma_r"], c["filter_iters"], c["solver_iters"]
+    note("8 x 1024^2 forward + backward, tape against recomputation")
+    g, t, cf, r = (torch.from_numpy(c[k]).cuda() for k in ("guide", "target", "conf", "ref"))
+    z, ck, tp = dts.solve(g, t, cf, ss, sr, N, T, tape=True)
+    go = (2.0 * (z - r)).contiguous()
+    got = dts.solve_backward(g, t, cf, ck, go, ss, sr, N, T, tape=tp)
+    del tp
+    ref = dts.solve_backward(g, t, cf, ck, go, ss, sr, N, T)
+    for name, a, b in zip(("target", "conf", "guide"), got, ref):
+        assert torch.equal(a, b), name
+
+
 def test_rgb_batch_8x1024_gradients_match_oracle_on_one_image():
     c = dts_inputs.rgb_batch_8x1024()
     ss, sr, N, T = c["sigma_s"], c["sigma_r"], c["filter_iters"], c["solver_iters"]
