@@ -325,6 +325,12 @@ int dts_tune_spin_limit(int polls);
  * the row width.  Rows whose width needs more than 16 waves at this setting fall back to
  * the default. */
 int dts_tune_row_segment(int pixels_per_lane);
+/* Column passes of the box kernel (dts_filter_box, dts_solve_box): on != 0 (the default)
+ * runs a pass whose half-width h is at most 64 pixels as one kernel over a window of rows
+ * in LDS; 0 takes the kernels used for wider boxes (a block prefix in the workspace and a
+ * gather, or a ring down each column with the solver update) for every h.  Results agree
+ * to fp32 rounding. */
+int dts_tune_box_window(int on);
 
 /* ---- Kernel timing (HIP events around each launch, on the launch's own stream) ---- */
 

@@ -45,6 +45,7 @@ __all__ = [
     "col_variants",
     "tune_col_variant",
     "tune_row_segment",
+    "tune_box_window",
     "tune_col_xcd",
     "tune_spin_limit",
     "batched_variants",
@@ -96,6 +97,7 @@ EXPORTED_SYMBOLS = (
     "dts_col_variant_info",
     "dts_tune_col_variant",
     "dts_tune_row_segment",
+    "dts_tune_box_window",
     "dts_tune_col_xcd",
     "dts_tune_spin_limit",
     "dts_batched_variant_count",
@@ -257,6 +259,8 @@ def library():
     lib.dts_tune_col_variant.restype = i
     lib.dts_tune_row_segment.argtypes = [i]
     lib.dts_tune_row_segment.restype = i
+    lib.dts_tune_box_window.argtypes = [i]
+    lib.dts_tune_box_window.restype = i
     lib.dts_tune_col_xcd.argtypes = [i]
     lib.dts_tune_col_xcd.restype = i
     lib.dts_tune_spin_limit.argtypes = [i]
@@ -440,6 +444,12 @@ def tune_col_variant(group_channels, variant):
 
 def tune_row_segment(pixels_per_lane):
     _check(library().dts_tune_row_segment(int(pixels_per_lane)), "dts_tune_row_segment")
+
+
+def tune_box_window(on):
+    """Run the box kernel's column passes with h <= 64 as one windowed kernel (default) or
+    always through the wide-box kernels."""
+    _check(library().dts_tune_box_window(int(bool(on))), "dts_tune_box_window")
 
 
 def tune_col_xcd(on):

@@ -229,20 +229,28 @@ static int box_mean(const BoxCall& B, const float* src, float* dst, int C, int b
     const float* x = src;
     for (int i = 0; i < N; ++i) {
         const int h = static_cast<int>(B.R[i] >> 8);
-        // the row pass writes y (never the buffer it reads); a plain column pass builds its
-        // block prefix in the other buffer and writes its mean back over y
+        // the row pass writes y (never the buffer it reads).  The window column pass writes
+        // the other buffer (its halos are other tiles' rows of y); the wide-box passes build
+        // their block prefix in the other buffer and write the mean back over y, or run the
+        // ring kernel with the update.
         float* y = (x == B.t1) ? B.t2 : B.t1;
         float* other = (y == B.t1) ? B.t2 : B.t1;
         int rc = launch_box_row(x, y, B.bx + px * i, C, batch, H, W, h, st);
         if (rc) return rc;
         const bool last = i == N - 1;
-        if (last && zk) {
+        const bool upd = last && zk;
+        if (box_window_fits(h)) {
+            float* out = last ? dst : other;
+            rc = launch_box_col_window(y, out, B.by + px * i, C, batch, H, W, h, upd ? zk : nullptr, tgt, conf, Cc,
+                                       lambda, step, st);
+            x = out;
+        } else if (upd) {
             rc = launch_box_col(y, dst, B.by + px * i, C, batch, H, W, h, zk, tgt, conf, Cc, lambda, step, st);
         } else {
             rc = launch_box_col_prefixed(y, other, last ? dst : y, B.by + px * i, C, batch, H, W, st);
+            x = y;
         }
         if (rc) return rc;
-        x = y;
     }
     return DTS_OK;
 }
@@ -1010,6 +1018,7 @@ int dts_tune_col_xcd(int on) { return tune_col_xcd(on); }
 int dts_tune_spin_limit(int polls) { return tune_spin_limit(polls); }
 
 int dts_tune_row_segment(int pixels_per_lane) { return tune_row_segment(pixels_per_lane); }
+int dts_tune_box_window(int on) { return tune_box_window(on); }
 
 int dts_workspace_status(void* workspace, void* stream) {
     if (!workspace) return DTS_EINVAL;

@@ -18,12 +18,22 @@
 //                           (a row segment's prefix of codes in LDS, binary searches)
 //   box_transpose_kernel    the column bounds are the row bounds of the transposed
 //                           codes, transposed back (64 x 64 LDS tiles)
-//   box_row_kernel          one row pass: FP64 prefix of the segment and its halo in LDS,
-//                           mean = (P[hi + 1] - P[lo]) / (hi - lo + 1)
-//   box_col_kernel<EPI>     one column pass: one column per lane walking down its rows;
-//                           an LDS ring keeps the float32 prefix within 32-row blocks and
-//                           the FP64 prefix at block starts, so a box sum only carries the
-//                           rounding of its own additions.  EPI: the update of Eq. (3).
+//   box_rowwin_kernel       one row pass for h <= kWinMaxH: a wave per 512 outputs, the
+//                           FP64 prefix S of the segment and its halo in LDS,
+//                           mean = (S[hi + 1] - S[lo]) / (hi - lo + 1)
+//   box_colwin_kernel<EPI>  one column pass for h <= kWinMaxH: 64 columns x 128 output rows
+//                           per workgroup, the window's rows in LDS as float32 prefixes
+//                           within 32-row blocks plus FP64 block sums.  EPI: the update of
+//                           Eq. (3).
+//   box_row_kernel          row pass for wider boxes (h <= 255): FP64 prefix of a
+//                           1024-pixel segment and its halo in LDS
+//   box_col_kernel<EPI>     column pass with the update for wider boxes: one column per
+//                           lane walking down its rows; an LDS ring keeps the float32
+//                           prefix within 32-row blocks and the FP64 prefix at block
+//                           starts, so a box sum only carries the rounding of its own
+//                           additions
+//   box_colprefix_kernel,   plain column pass for wider boxes: the block prefix written
+//   box_colmean_kernel      out, then a gather of each box's ends and block totals
 // The bounds depend on the guide only and are computed once per call; every pass then
 // reads its signal and two bytes of bounds per pixel and writes its result.
 #include <algorithm>
@@ -41,6 +51,7 @@ constexpr int kBoxRowChunk = kBoxRowSpan / kBoxRowThreads;
 constexpr int kBoxLoad = 32;           // rows loaded per step of the column kernels
 constexpr int kBoxEmit = 8;            // outputs per block of the column pass
 constexpr unsigned kBoxCodeCap = 65536u;
+constexpr int kWinMaxH = 64;           // widest half-width of the window passes
 
 // ---------------------------------------------------------------------------------------
 // Integer codes of the arc-length increments
@@ -323,6 +334,96 @@ __global__ void __launch_bounds__(kBoxRowThreads) box_row_kernel(BoxPassArgs a) 
     }
 }
 
+// Row pass for half-widths h <= kWinMaxH (the same limit as the window column pass): one
+// wave per kRowWinSeg outputs of a row, many waves in flight per CU.  The wave loads its
+// window (the segment and h pixels on either side) with coalesced loads and stages it in
+// LDS; each lane takes the FP64 prefix of kRowWinPer consecutive samples, a wave scan adds
+// the lane totals before it, and the window's exclusive FP64 prefix S (S[0] = 0) goes back
+// to LDS over the staged samples.  mean = (S[hi + 1] - S[lo]) / (hi - lo + 1), the numbers
+// of box_row_kernel up to FP64 rounding.
+constexpr int kRowWinSeg = 512;
+constexpr int kRowWinSpan = kRowWinSeg + 2 * kWinMaxH;  // segment plus the widest halo
+constexpr int kRowWinPer = kRowWinSpan / kWave;    // samples per lane (loads per lane)
+constexpr int kRowWinOut = kRowWinSeg / kWave;     // outputs per lane
+static_assert(kRowWinSpan % kWave == 0 && kRowWinSeg % kWave == 0, "row window shape");
+
+__global__ void __launch_bounds__(kWave) box_rowwin_kernel(BoxPassArgs a, int segs) {
+    __shared__ double S[kRowWinSpan + 1];
+    float* stage = reinterpret_cast<float*>(S);  // the window's samples, before S is written
+    const int lane = threadIdx.x;
+    // units (row, segment) of one image in XCD-contiguous bands: a halo is then mostly
+    // the neighbouring segment's pixels, read on the same XCD
+    const int unit = xcd_band_index(static_cast<int>(blockIdx.x), segs * a.H);
+    const int y = unit / segs, sg = unit - y * segs;
+    const int b = blockIdx.z;
+    const int x0 = sg * kRowWinSeg;
+    const int s0 = max(x0 - a.h, 0);
+    const int n = min(x0 + kRowWinSeg + a.h, a.W) - s0;  // window pixels
+    const int oEnd = min(x0 + kRowWinSeg, a.W);
+    const size_t plane = static_cast<size_t>(a.H) * a.W;
+    const size_t yoff = static_cast<size_t>(y) * a.W;
+    const unsigned short* brow = a.bounds + static_cast<size_t>(b) * plane + yoff;
+    unsigned bd[kRowWinOut];
+#pragma unroll
+    for (int m = 0; m < kRowWinOut; ++m) {
+        const int x = x0 + lane + kWave * m;
+        bd[m] = (x < oEnd) ? brow[x] : 0u;
+    }
+    float v[kRowWinPer];
+    auto load = [&](int c) {
+        const float* row = a.src + (static_cast<size_t>(b) * a.C + c) * plane + yoff + s0;
+#pragma unroll
+        for (int m = 0; m < kRowWinPer; ++m) {
+            const int e = lane + kWave * m;
+            v[m] = (e < n) ? row[e] : 0.0f;
+        }
+    };
+    load(0);
+    for (int c = 0; c < a.C; ++c) {
+#pragma unroll
+        for (int m = 0; m < kRowWinPer; ++m) stage[lane + kWave * m] = v[m];
+        __syncthreads();
+        float w[kRowWinPer];
+#pragma unroll
+        for (int u = 0; u < kRowWinPer; ++u) w[u] = stage[lane * kRowWinPer + u];
+        __syncthreads();  // S is written over the staged samples
+        if (c + 1 < a.C) load(c + 1);
+        double run = 0.0;
+#pragma unroll
+        for (int u = 0; u < kRowWinPer; ++u) run += static_cast<double>(w[u]);
+        double incl = run;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const double t = __shfl_up(incl, o);
+            if (lane >= o) incl += t;
+        }
+        double base = __shfl_up(incl, 1);
+        if (lane == 0) base = 0.0;
+#pragma unroll
+        for (int u = 0; u < kRowWinPer; ++u) {
+            base += static_cast<double>(w[u]);
+            S[lane * kRowWinPer + u + 1] = base;
+        }
+        if (lane == 0) S[0] = 0.0;
+        __syncthreads();
+        float* drow = a.dst + (static_cast<size_t>(b) * a.C + c) * plane + yoff;
+#pragma unroll
+        for (int m = 0; m < kRowWinOut; ++m) {
+            const int x = x0 + lane + kWave * m;
+            if (x < oEnd) {
+                // a box never leaves the row or reaches beyond h, so it lies in the window;
+                // the clamps only keep the LDS reads inside it
+                const int li = x - s0;
+                const int lo = max(li - static_cast<int>(bd[m] & 255u), 0);
+                const int hi = min(li + static_cast<int>(bd[m] >> 8), n - 1);
+                drow[x] = static_cast<float>(S[hi + 1] - S[lo]) *
+                          __builtin_amdgcn_rcpf(static_cast<float>(hi - lo + 1));
+            }
+        }
+        __syncthreads();  // the next channel's samples are staged over S
+    }
+}
+
 template <int EPI>
 __global__ void __launch_bounds__(kWave) box_col_kernel(BoxPassArgs a) {
     extern __shared__ unsigned char box_smem[];
@@ -539,6 +640,142 @@ __global__ void __launch_bounds__(256) box_colmean_kernel(const float* __restric
 }
 
 // ---------------------------------------------------------------------------------------
+// Column pass in one kernel for half-widths h <= kWinMaxH: a workgroup owns 64 columns
+// (one per lane) and kWinRows output rows.  It loads its window, the output rows and h
+// rows on either side, as float32 prefixes within 32-row blocks (block k holds window
+// rows 32k .. 32k + 31), sums the block totals before each block in FP64, and reads a box
+// sum off the window as S(hi) - S(lo - 1) with S(j) = (FP64 total of the blocks before
+// j's) + (float32 prefix of j within its block): the rounding is that of the ring kernel.
+// Every output pixel costs one signal read and two bytes of bounds from HBM; the halo
+// rows are the neighbouring tiles' rows, and the tile order (a run of consecutive tiles
+// down a column strip per XCD) keeps both readers of a halo on one L2.  The operands of
+// the output rows are loaded up front and stay in flight across the two barriers, which
+// wait for LDS only.
+// ---------------------------------------------------------------------------------------
+constexpr int kWinRows = 128;
+constexpr int kWinWaves = 8;
+constexpr int kWinSpan = kWinRows + 2 * kWinMaxH;    // window rows
+constexpr int kWinBlocks = kWinSpan / 32;
+constexpr int kWinBlocksPerWave = (kWinBlocks + kWinWaves - 1) / kWinWaves;
+constexpr int kWinOutPerWave = kWinRows / kWinWaves;
+static_assert(kWinSpan % 32 == 0 && kWinRows % kWinWaves == 0, "window shape");
+
+struct BoxWinArgs {
+    BoxPassArgs p;
+    int tiles_x, tiles_y;   // 64-column strips, kWinRows-row tiles per strip
+    int tiles;              // tiles_x * tiles_y * batch * C, one workgroup each
+};
+
+template <int EPI>
+__global__ void __launch_bounds__(kWinWaves* kWave) box_colwin_kernel(BoxWinArgs w) {
+    __shared__ float pf[kWinSpan * kWave];      // [row][lane]
+    __shared__ float btot[kWinBlocks * kWave];  // block totals (float32 prefix at the block's end)
+    __shared__ double bpre[kWinBlocks * kWave]; // FP64 sum of the totals of the blocks before
+    const BoxPassArgs& a = w.p;
+    // workgroups are dealt to the 8 XCDs in turn; each XCD takes a contiguous band of tiles
+    const unsigned T = static_cast<unsigned>(xcd_band_index(static_cast<int>(blockIdx.x), w.tiles));
+    const int ty = static_cast<int>(T % static_cast<unsigned>(w.tiles_y));
+    const unsigned rest = T / static_cast<unsigned>(w.tiles_y);
+    const int tx = static_cast<int>(rest % static_cast<unsigned>(w.tiles_x));
+    const int bc = static_cast<int>(rest / static_cast<unsigned>(w.tiles_x));  // image * C + channel
+    const int b = bc / a.C, c = bc - b * a.C;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int col = tx * kWave + lane;
+    const bool valid = col < a.W;
+    const int cx = valid ? col : 0;
+    const size_t plane = static_cast<size_t>(a.H) * a.W;
+    const int y0 = ty * kWinRows;
+    const int s0 = max(y0 - a.h, 0);
+    const int n = min(y0 + kWinRows + a.h, a.H) - s0;  // window rows
+    const int nb = (n + 31) >> 5;
+    const int oEnd = min(y0 + kWinRows, a.H);
+    const float* sc = a.src + static_cast<size_t>(bc) * plane + cx;
+    float* dc = a.dst + static_cast<size_t>(bc) * plane + cx;
+    const unsigned short* bdc = a.bounds + static_cast<size_t>(b) * plane + cx;
+
+    float v[kWinBlocksPerWave][32];
+#pragma unroll
+    for (int i = 0; i < kWinBlocksPerWave; ++i) {
+        const int k = wave + kWinWaves * i;
+#pragma unroll
+        for (int u = 0; u < 32; ++u) {
+            const int r = 32 * k + u;
+            v[i][u] = (valid && r < n) ? sc[static_cast<size_t>(s0 + r) * a.W] : 0.0f;
+        }
+    }
+    unsigned bd[kWinOutPerWave];
+    [[maybe_unused]] float zv[EPI ? kWinOutPerWave : 1], tv[EPI ? kWinOutPerWave : 1],
+        cv[EPI ? kWinOutPerWave : 1];
+#pragma unroll
+    for (int q = 0; q < kWinOutPerWave; ++q) {
+        const int o = y0 + wave + kWinWaves * q;
+        const bool in = valid && o < oEnd;
+        const size_t po = static_cast<size_t>(in ? o : 0) * a.W;
+        bd[q] = in ? bdc[po] : 0u;
+        if constexpr (EPI) {
+            const float* zc = a.zk + static_cast<size_t>(bc) * plane + cx;
+            const float* tc = a.tgt + static_cast<size_t>(bc) * plane + cx;
+            const float* cc = a.conf + (static_cast<size_t>(b) * a.Cc + (a.Cc == 1 ? 0 : c)) * plane + cx;
+            zv[q] = in ? zc[po] : 0.0f;
+            tv[q] = in ? tc[po] : 0.0f;
+            cv[q] = in ? cc[po] : 0.0f;
+        }
+    }
+
+    // float32 prefixes within the wave's blocks
+#pragma unroll
+    for (int i = 0; i < kWinBlocksPerWave; ++i) {
+        const int k = wave + kWinWaves * i;
+        if (k < nb) {
+            float run = 0.0f;
+#pragma unroll
+            for (int u = 0; u < 32; ++u) {
+                run += v[i][u];
+                pf[(32 * k + u) * kWave + lane] = run;
+            }
+            btot[k * kWave + lane] = run;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kWinBlocksPerWave; ++i) {
+        const int k = wave + kWinWaves * i;
+        if (k < nb) {
+            double acc = 0.0;
+            for (int j = 0; j < k; ++j) acc += static_cast<double>(btot[j * kWave + lane]);
+            bpre[k * kWave + lane] = acc;
+        }
+    }
+    __syncthreads();
+
+#pragma unroll
+    for (int q = 0; q < kWinOutPerWave; ++q) {
+        const int o = y0 + wave + kWinWaves * q;
+        if (o < oEnd) {
+            const int lo_off = static_cast<int>(bd[q] & 255u), hi_off = static_cast<int>(bd[q] >> 8);
+            // a box never leaves the image or reaches beyond h, so it lies in the window;
+            // the clamps only keep the LDS reads inside it
+            const int jh = min(o - s0 + hi_off, n - 1);
+            const int jl = max(o - s0 - lo_off - 1, -1);
+            const double ph = bpre[(jh >> 5) * kWave + lane] + static_cast<double>(pf[jh * kWave + lane]);
+            const double pl =
+                (jl < 0) ? 0.0 : bpre[(jl >> 5) * kWave + lane] + static_cast<double>(pf[jl * kWave + lane]);
+            const float mean =
+                static_cast<float>(ph - pl) * __builtin_amdgcn_rcpf(static_cast<float>(lo_off + hi_off + 1));
+            if (valid) {
+                const size_t po = static_cast<size_t>(o) * a.W;
+                if constexpr (EPI) {
+                    const float upd = fmaf(a.lambda, zv[q] - mean, cv[q] * (zv[q] - tv[q]));
+                    dc[po] = fmaf(-a.step, upd, zv[q]);
+                } else {
+                    dc[po] = mean;
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------------------
 static int max_lds_per_block() {
@@ -638,6 +875,14 @@ int launch_box_row(const float* src, float* dst, const unsigned short* bounds, i
     a.W = W;
     a.h = h;
     const double px = static_cast<double>(batch) * H * W;
+    if (box_window_fits(h)) {
+        const int segs = (W + kRowWinSeg - 1) / kRowWinSeg;
+        if (static_cast<long long>(segs) * H > 0x7fffffffLL) return DTS_ENOTSUP;
+        ProfScope prof("box_row_window", px * (8.0 * C + 2.0), s);
+        hipLaunchKernelGGL(box_rowwin_kernel, dim3(static_cast<unsigned>(segs * H), 1, batch), dim3(kWave), 0, s, a,
+                           segs);
+        return hip_fail(hipGetLastError());
+    }
     ProfScope prof("box_row", px * (8.0 * C + 2.0), s);
     hipLaunchKernelGGL(box_row_kernel, dim3((W + kBoxSeg - 1) / kBoxSeg, H, batch), dim3(kBoxRowThreads), 0, s, a);
     return hip_fail(hipGetLastError());
@@ -657,6 +902,53 @@ int launch_box_col_prefixed(const float* src, float* P, float* dst, const unsign
     ProfScope prof("box_col_mean", px * 10.0 * C, s);
     hipLaunchKernelGGL(box_colmean_kernel, dim3(gx, (H + kBoxMeanRows - 1) / kBoxMeanRows, batch * C), dim3(256), 0,
                        s, P, bounds, dst, C, H, W);
+    return hip_fail(hipGetLastError());
+}
+
+static bool g_box_window = true;
+
+int tune_box_window(int on) {
+    g_box_window = on != 0;
+    return DTS_OK;
+}
+
+bool box_window_fits(int h) { return g_box_window && h >= 0 && h <= kWinMaxH; }
+
+int launch_box_col_window(const float* src, float* dst, const unsigned short* bounds, int C, int batch, int H, int W,
+                          int h, const float* zk, const float* tgt, const float* conf, int Cc, float lambda,
+                          float step, hipStream_t s) {
+    if (h < 0 || h > kWinMaxH) return DTS_EINVAL;
+    BoxWinArgs w{};
+    BoxPassArgs& a = w.p;
+    a.src = src;
+    a.dst = dst;
+    a.bounds = bounds;
+    a.C = C;
+    a.H = H;
+    a.W = W;
+    a.h = h;
+    a.zk = zk;
+    a.tgt = tgt;
+    a.conf = conf;
+    a.Cc = Cc;
+    a.lambda = lambda;
+    a.step = step;
+    w.tiles_x = (W + kWave - 1) / kWave;
+    w.tiles_y = (H + kWinRows - 1) / kWinRows;
+    const unsigned long long tiles =
+        static_cast<unsigned long long>(w.tiles_x) * static_cast<unsigned long long>(w.tiles_y) * batch * C;
+    if (tiles == 0) return DTS_OK;
+    if (tiles > 0x7fffffffull) return DTS_ENOTSUP;
+    w.tiles = static_cast<int>(tiles);
+    const dim3 grid(static_cast<unsigned>(w.tiles));
+    const double px = static_cast<double>(batch) * H * W;
+    if (zk) {
+        ProfScope prof("box_col_window_update", px * (18.0 * C + 4.0 * Cc), s);
+        hipLaunchKernelGGL(box_colwin_kernel<1>, grid, dim3(kWinWaves * kWave), 0, s, w);
+    } else {
+        ProfScope prof("box_col_window", px * 10.0 * C, s);
+        hipLaunchKernelGGL(box_colwin_kernel<0>, grid, dim3(kWinWaves * kWave), 0, s, w);
+    }
     return hip_fail(hipGetLastError());
 }
 

@@ -132,6 +132,14 @@ int launch_box_col_prefixed(const float* src, float* P, float* dst, const unsign
 int launch_box_col(const float* src, float* dst, const unsigned short* bounds, int C, int batch, int H, int W, int h,
                    const float* zk, const float* tgt, const float* conf, int Cc, float lambda, float step,
                    hipStream_t s);
+// One-kernel column pass over a window of rows in LDS, for half-widths up to a limit
+// (box_window_fits); wider boxes take launch_box_col / launch_box_col_prefixed.  Writes a
+// buffer other than the one it reads.
+bool box_window_fits(int h);
+int tune_box_window(int on);
+int launch_box_col_window(const float* src, float* dst, const unsigned short* bounds, int C, int batch, int H, int W,
+                          int h, const float* zk, const float* tgt, const float* conf, int Cc, float lambda,
+                          float step, hipStream_t s);
 size_t support_carry_words(int batch, int H, int W);
 int launch_support_row(const float* src, const float* dx, float* dst, int batch, int H, int W, float log2a,
                        float m, hipStream_t s);

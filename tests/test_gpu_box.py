@@ -79,6 +79,57 @@ def test_filter_box_matches_oracle(case):
         assert np.abs(got[b] - ref).max() <= FILTER_TOL, (case, b, float(np.abs(got[b] - ref).max()))
 
 
+# Column passes with h <= 64 run as one kernel over a window of rows in LDS (128 output
+# rows per tile, 64 columns); wider ones take the block-prefix and ring kernels.  These
+# shapes sit on the window's edges, and each runs both ways against the oracle.
+WINDOW_CASES = [
+    # H, W, Cg, C, N, batch, sigma_s, sigma_r
+    (1000, 70, 3, 1, 1, 1, 37.0, 0.2),     # h = 64, the widest window; ragged tiles and strip
+    (100, 130, 3, 2, 3, 2, 20.0, 0.15),    # one tile per strip, shorter than its halo span
+    (50, 1, 1, 1, 3, 1, 30.0, 0.2),        # one column (63 idle lanes), image shorter than h
+    (300, 200, 3, 1, 1, 1, 0.5, 0.2),      # h = 0: one-pixel boxes
+    (257, 64, 16, 1, 3, 1, 37.0, 0.1),     # a last tile of one row
+    (400, 90, 3, 1, 1, 1, 37.6, 0.2),      # h = 65: the wide-box kernels either way
+]
+
+
+@pytest.mark.parametrize("window", [1, 0], ids=["window", "wide"])
+@pytest.mark.parametrize("case", WINDOW_CASES, ids=[f"{c[0]}x{c[1]}_C{c[3]}_N{c[4]}_s{c[6]}" for c in WINDOW_CASES])
+def test_filter_box_column_kernels_match_oracle(case, window):
+    H, W, Cg, C, N, B, ss, sr = case
+    print("CASE box window", case, window, flush=True)
+    rng = np.random.default_rng(H * 613 + W * 17 + C)
+    cs = [dts_inputs.random_case(int(rng.integers(1 << 30)), H, W, Cg, C, sigma_s=ss, sigma_r=sr, T=1)
+          for _ in range(B)]
+    g = np.stack([c["guide"] for c in cs])
+    x = np.stack([c["target"] for c in cs])
+    dts.tune_box_window(window)
+    try:
+        got = dts.filter_box(dev(g), dev(x), ss, sr, N).cpu().numpy()
+    finally:
+        dts.tune_box_window(1)
+    for b in range(B):
+        qx, qy = oracle.box_codes(g[b], ss, sr)
+        ref = oracle.box_filter(x[b], qx, qy, ss, N)
+        assert np.abs(got[b] - ref).max() <= FILTER_TOL, (case, b, float(np.abs(got[b] - ref).max()))
+
+
+@pytest.mark.parametrize("window", [1, 0], ids=["window", "wide"])
+def test_solve_box_column_kernels_match_oracle(window):
+    # the update epilogue of the last column pass, in place over z^k after the first step
+    H, W, Cg, Ct, Cc, N, T, ss, sr = 300, 150, 3, 2, 1, 3, 3, 30.0, 0.2
+    print("CASE box window solve", window, flush=True)
+    c = dts_inputs.random_case(77, H, W, Cg, Ct, Cc=Cc, sigma_s=ss, sigma_r=sr, T=T)
+    dts.tune_box_window(window)
+    try:
+        got = dts.solve_box(dev(c["guide"])[None], dev(c["target"])[None], dev(c["conf"])[None], ss, sr, N,
+                            T).cpu().numpy()[0]
+    finally:
+        dts.tune_box_window(1)
+    ref = oracle.solve_box(c["guide"], c["target"], c["conf"], ss, sr, N, T)
+    assert np.abs(got - ref).max() <= SOLVE_TOL, float(np.abs(got - ref).max())
+
+
 SOLVE_CASES = [
     # H, W, Cg, Ct, Cc, N, T, batch, sigma_s, sigma_r
     (1, 1, 1, 1, 1, 3, 3, 1, 8.0, 0.2),
