@@ -37,6 +37,7 @@
 // The bounds depend on the guide only and are computed once per call; every pass then
 // reads its signal and two bytes of bounds per pixel and writes its result.
 #include <algorithm>
+#include <mutex>
 
 #include "../../include/dts.h"
 #include "dts_device.hpp"
@@ -663,115 +664,193 @@ static_assert(kWinSpan % 32 == 0 && kWinRows % kWinWaves == 0, "window shape");
 struct BoxWinArgs {
     BoxPassArgs p;
     int tiles_x, tiles_y;   // 64-column strips, kWinRows-row tiles per strip
-    int tiles;              // tiles_x * tiles_y * batch * C, one workgroup each
+    int tiles;              // tiles_x * tiles_y * batch * C
+    int per_xcd;            // workgroups per XCD (the grid is 8 per_xcd)
 };
 
-template <int EPI>
-__global__ void __launch_bounds__(kWinWaves* kWave) box_colwin_kernel(BoxWinArgs w) {
-    __shared__ float pf[kWinSpan * kWave];      // [row][lane]
-    __shared__ float btot[kWinBlocks * kWave];  // block totals (float32 prefix at the block's end)
-    __shared__ double bpre[kWinBlocks * kWave]; // FP64 sum of the totals of the blocks before
-    const BoxPassArgs& a = w.p;
-    // workgroups are dealt to the 8 XCDs in turn; each XCD takes a contiguous band of tiles
-    const unsigned T = static_cast<unsigned>(xcd_band_index(static_cast<int>(blockIdx.x), w.tiles));
-    const int ty = static_cast<int>(T % static_cast<unsigned>(w.tiles_y));
-    const unsigned rest = T / static_cast<unsigned>(w.tiles_y);
-    const int tx = static_cast<int>(rest % static_cast<unsigned>(w.tiles_x));
-    const int bc = static_cast<int>(rest / static_cast<unsigned>(w.tiles_x));  // image * C + channel
-    const int b = bc / a.C, c = bc - b * a.C;
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    const int col = tx * kWave + lane;
-    const bool valid = col < a.W;
-    const int cx = valid ? col : 0;
-    const size_t plane = static_cast<size_t>(a.H) * a.W;
-    const int y0 = ty * kWinRows;
-    const int s0 = max(y0 - a.h, 0);
-    const int n = min(y0 + kWinRows + a.h, a.H) - s0;  // window rows
-    const int nb = (n + 31) >> 5;
-    const int oEnd = min(y0 + kWinRows, a.H);
-    const float* sc = a.src + static_cast<size_t>(bc) * plane + cx;
-    float* dc = a.dst + static_cast<size_t>(bc) * plane + cx;
-    const unsigned short* bdc = a.bounds + static_cast<size_t>(b) * plane + cx;
+// Geometry of tile T: strip-major, tiles down a strip consecutive.
+struct WinTile {
+    int bc, b, c;          // image * C + channel, image, channel
+    int cx;                // the lane's column (0 for lanes beyond the image)
+    int valid;             // the lane's column lies in the image (0 or 1)
+    int y0, s0, n, nb;     // first output row, first window row, window rows, 32-row blocks
+    int oEnd;              // one past the last output row
+};
 
-    float v[kWinBlocksPerWave][32];
+__device__ __forceinline__ WinTile win_tile(const BoxWinArgs& w, int T, int lane) {
+    const BoxPassArgs& a = w.p;
+    WinTile t;
+    const int ty = T % w.tiles_y;
+    const int rest = T / w.tiles_y;
+    const int tx = rest % w.tiles_x;
+    t.bc = rest / w.tiles_x;
+    t.b = t.bc / a.C;
+    t.c = t.bc - t.b * a.C;
+    const int col = tx * kWave + lane;
+    t.valid = col < a.W;
+    t.cx = t.valid ? col : 0;
+    t.y0 = ty * kWinRows;
+    t.s0 = max(t.y0 - a.h, 0);
+    t.n = min(t.y0 + kWinRows + a.h, a.H) - t.s0;
+    t.nb = (t.n + 31) >> 5;
+    t.oEnd = min(t.y0 + kWinRows, a.H);
+    return t;
+}
+
+// Operands of one tile through raw buffer resources over its planes: a lane's column is a
+// per-lane byte offset (kInvalidOffset beyond the image), a row a uniform (scalar) offset,
+// and rows outside the window or the tile read 0 through an invalid lane offset.
+struct WinRes {
+    __amdgpu_buffer_rsrc_t sig, bnd, dst;
+    unsigned lv4, lv2;  // the lane's byte offset in a float plane and in the bounds plane
+};
+
+__device__ __forceinline__ WinRes win_res(const BoxPassArgs& a, const WinTile& t) {
+    const size_t plane = static_cast<size_t>(a.H) * a.W;
+    WinRes r;
+    r.sig = plane_rsrc(a.src + static_cast<size_t>(t.bc) * plane, plane * 4);
+    r.dst = plane_rsrc(a.dst + static_cast<size_t>(t.bc) * plane, plane * 4);
+    r.bnd = plane_rsrc(a.bounds + static_cast<size_t>(t.b) * plane, plane * 2);
+    r.lv4 = t.valid ? static_cast<unsigned>(t.cx) * 4u : kInvalidOffset;
+    r.lv2 = t.valid ? static_cast<unsigned>(t.cx) * 2u : kInvalidOffset;
+    return r;
+}
+
+// The wave's 32-row blocks of the window (block k = wave + kWinWaves i).
+__device__ __forceinline__ void win_load_signal(const BoxPassArgs& a, const WinTile& t, const WinRes& rs, int wave,
+                                                float (&v)[kWinBlocksPerWave][32]) {
+    const unsigned pitch = static_cast<unsigned>(a.W) * 4u;
 #pragma unroll
     for (int i = 0; i < kWinBlocksPerWave; ++i) {
         const int k = wave + kWinWaves * i;
 #pragma unroll
         for (int u = 0; u < 32; ++u) {
             const int r = 32 * k + u;
-            v[i][u] = (valid && r < n) ? sc[static_cast<size_t>(s0 + r) * a.W] : 0.0f;
+            const unsigned row = static_cast<unsigned>(t.s0 + min(r, t.n - 1)) * pitch;
+            v[i][u] = bload(rs.sig, (r < t.n) ? rs.lv4 : kInvalidOffset, row);
         }
     }
+}
+
+// Bounds of the wave's output rows (row y0 + wave + kWinWaves q).
+__device__ __forceinline__ void win_load_bounds(const BoxPassArgs& a, const WinTile& t, const WinRes& rs, int wave,
+                                                unsigned (&bd)[kWinOutPerWave]) {
+    const unsigned pitch = static_cast<unsigned>(a.W) * 2u;
+#pragma unroll
+    for (int q = 0; q < kWinOutPerWave; ++q) {
+        const int o = t.y0 + wave + kWinWaves * q;
+        const unsigned row = static_cast<unsigned>(min(o, t.oEnd - 1)) * pitch;
+        bd[q] = __builtin_amdgcn_raw_buffer_load_b16(rs.bnd, (o < t.oEnd) ? rs.lv2 : kInvalidOffset, row, 0);
+    }
+}
+
+// Persistent over tiles: XCD x owns a contiguous band of tiles and its per_xcd workgroups
+// take every per_xcd-th of them, so the tiles in flight on one XCD are neighbours down a
+// strip.  While a tile's block sums and outputs are computed, the next tile's window and
+// bounds are already in flight (registers; the barriers wait for LDS only).
+template <int EPI>
+__global__ void __launch_bounds__(kWinWaves* kWave) box_colwin_kernel(BoxWinArgs w) {
+    __shared__ float pf[kWinSpan * kWave];      // [row][lane]
+    __shared__ float btot[kWinBlocks * kWave];  // block totals (float32 prefix at the block's end)
+    __shared__ double bpre[kWinBlocks * kWave]; // FP64 sum of the totals of the blocks before
+    const BoxPassArgs& a = w.p;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int x = static_cast<int>(blockIdx.x % kXcds), j = static_cast<int>(blockIdx.x / kXcds);
+    const int q8 = w.tiles / kXcds, r8 = w.tiles % kXcds;
+    const int t_end = x * q8 + min(x, r8) + q8 + (x < r8 ? 1 : 0);
+    int T = x * q8 + min(x, r8) + j;
+    if (T >= t_end) return;
+    const size_t plane = static_cast<size_t>(a.H) * a.W;
+    const unsigned pitch = static_cast<unsigned>(a.W) * 4u;
+
+    WinTile t = win_tile(w, T, lane);
+    WinRes rs = win_res(a, t);
+    float v[kWinBlocksPerWave][32];
     unsigned bd[kWinOutPerWave];
-    [[maybe_unused]] float zv[EPI ? kWinOutPerWave : 1], tv[EPI ? kWinOutPerWave : 1],
-        cv[EPI ? kWinOutPerWave : 1];
-#pragma unroll
-    for (int q = 0; q < kWinOutPerWave; ++q) {
-        const int o = y0 + wave + kWinWaves * q;
-        const bool in = valid && o < oEnd;
-        const size_t po = static_cast<size_t>(in ? o : 0) * a.W;
-        bd[q] = in ? bdc[po] : 0u;
+    win_load_signal(a, t, rs, wave, v);
+    win_load_bounds(a, t, rs, wave, bd);
+    for (;;) {
+        [[maybe_unused]] float zv[kWinOutPerWave], tv[kWinOutPerWave], cv[kWinOutPerWave];
         if constexpr (EPI) {
-            const float* zc = a.zk + static_cast<size_t>(bc) * plane + cx;
-            const float* tc = a.tgt + static_cast<size_t>(bc) * plane + cx;
-            const float* cc = a.conf + (static_cast<size_t>(b) * a.Cc + (a.Cc == 1 ? 0 : c)) * plane + cx;
-            zv[q] = in ? zc[po] : 0.0f;
-            tv[q] = in ? tc[po] : 0.0f;
-            cv[q] = in ? cc[po] : 0.0f;
-        }
-    }
-
-    // float32 prefixes within the wave's blocks
+            const auto zr = plane_rsrc(a.zk + static_cast<size_t>(t.bc) * plane, plane * 4);
+            const auto tr = plane_rsrc(a.tgt + static_cast<size_t>(t.bc) * plane, plane * 4);
+            const auto cr = plane_rsrc(a.conf + (static_cast<size_t>(t.b) * a.Cc + (a.Cc == 1 ? 0 : t.c)) * plane,
+                                       plane * 4);
 #pragma unroll
-    for (int i = 0; i < kWinBlocksPerWave; ++i) {
-        const int k = wave + kWinWaves * i;
-        if (k < nb) {
-            float run = 0.0f;
-#pragma unroll
-            for (int u = 0; u < 32; ++u) {
-                run += v[i][u];
-                pf[(32 * k + u) * kWave + lane] = run;
+            for (int q = 0; q < kWinOutPerWave; ++q) {
+                const int o = t.y0 + wave + kWinWaves * q;
+                const unsigned row = static_cast<unsigned>(min(o, t.oEnd - 1)) * pitch;
+                const unsigned lv = (o < t.oEnd) ? rs.lv4 : kInvalidOffset;
+                zv[q] = bload(zr, lv, row);
+                tv[q] = bload(tr, lv, row);
+                cv[q] = bload(cr, lv, row);
             }
-            btot[k * kWave + lane] = run;
         }
-    }
-    __syncthreads();
+        // float32 prefixes within the wave's blocks
 #pragma unroll
-    for (int i = 0; i < kWinBlocksPerWave; ++i) {
-        const int k = wave + kWinWaves * i;
-        if (k < nb) {
-            double acc = 0.0;
-            for (int j = 0; j < k; ++j) acc += static_cast<double>(btot[j * kWave + lane]);
-            bpre[k * kWave + lane] = acc;
-        }
-    }
-    __syncthreads();
-
+        for (int i = 0; i < kWinBlocksPerWave; ++i) {
+            const int k = wave + kWinWaves * i;
+            if (k < t.nb) {
+                float run = 0.0f;
 #pragma unroll
-    for (int q = 0; q < kWinOutPerWave; ++q) {
-        const int o = y0 + wave + kWinWaves * q;
-        if (o < oEnd) {
-            const int lo_off = static_cast<int>(bd[q] & 255u), hi_off = static_cast<int>(bd[q] >> 8);
-            // a box never leaves the image or reaches beyond h, so it lies in the window;
-            // the clamps only keep the LDS reads inside it
-            const int jh = min(o - s0 + hi_off, n - 1);
-            const int jl = max(o - s0 - lo_off - 1, -1);
-            const double ph = bpre[(jh >> 5) * kWave + lane] + static_cast<double>(pf[jh * kWave + lane]);
-            const double pl =
-                (jl < 0) ? 0.0 : bpre[(jl >> 5) * kWave + lane] + static_cast<double>(pf[jl * kWave + lane]);
-            const float mean =
-                static_cast<float>(ph - pl) * __builtin_amdgcn_rcpf(static_cast<float>(lo_off + hi_off + 1));
-            if (valid) {
-                const size_t po = static_cast<size_t>(o) * a.W;
-                if constexpr (EPI) {
-                    const float upd = fmaf(a.lambda, zv[q] - mean, cv[q] * (zv[q] - tv[q]));
-                    dc[po] = fmaf(-a.step, upd, zv[q]);
-                } else {
-                    dc[po] = mean;
+                for (int u = 0; u < 32; ++u) {
+                    run += v[i][u];
+                    pf[(32 * k + u) * kWave + lane] = run;
                 }
+                btot[k * kWave + lane] = run;
             }
         }
+        // the next tile's operands, in flight during this tile's block sums and outputs
+        // (the update's operands leave no registers for them: that kernel takes one tile
+        // per workgroup)
+        const int Tn = T + w.per_xcd;
+        const bool more = !EPI && Tn < t_end;
+        WinTile tn = t;
+        WinRes rn = rs;
+        unsigned bdn[kWinOutPerWave];
+        if (more) {
+            tn = win_tile(w, Tn, lane);
+            rn = win_res(a, tn);
+            win_load_signal(a, tn, rn, wave, v);
+            win_load_bounds(a, tn, rn, wave, bdn);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kWinBlocksPerWave; ++i) {
+            const int k = wave + kWinWaves * i;
+            if (k < t.nb) {
+                double acc = 0.0;
+                for (int jb = 0; jb < k; ++jb) acc += static_cast<double>(btot[jb * kWave + lane]);
+                bpre[k * kWave + lane] = acc;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kWinOutPerWave; ++q) {
+            const int o = t.y0 + wave + kWinWaves * q;
+            if (o < t.oEnd) {
+                const int lo_off = static_cast<int>(bd[q] & 255u), hi_off = static_cast<int>(bd[q] >> 8);
+                // a box never leaves the image or reaches beyond h, so it lies in the
+                // window; the clamps only keep the LDS reads inside it
+                const int jh = min(o - t.s0 + hi_off, t.n - 1);
+                const int jl = max(o - t.s0 - lo_off - 1, -1);
+                const double ph = bpre[(jh >> 5) * kWave + lane] + static_cast<double>(pf[jh * kWave + lane]);
+                const double pl =
+                    (jl < 0) ? 0.0 : bpre[(jl >> 5) * kWave + lane] + static_cast<double>(pf[jl * kWave + lane]);
+                const float mean =
+                    static_cast<float>(ph - pl) * __builtin_amdgcn_rcpf(static_cast<float>(lo_off + hi_off + 1));
+                float res = mean;
+                if constexpr (EPI) res = fmaf(-a.step, fmaf(a.lambda, zv[q] - mean, cv[q] * (zv[q] - tv[q])), zv[q]);
+                bstore(rs.dst, rs.lv4, static_cast<unsigned>(o) * pitch, res);
+            }
+        }
+        if (!more) break;
+        __syncthreads();  // the LDS window is rebuilt for the next tile
+        T = Tn;
+        t = tn;
+        rs = rn;
+#pragma unroll
+        for (int q = 0; q < kWinOutPerWave; ++q) bd[q] = bdn[q];
     }
 }
 
@@ -905,6 +984,25 @@ int launch_box_col_prefixed(const float* src, float* P, float* dst, const unsign
     return hip_fail(hipGetLastError());
 }
 
+// Co-resident workgroups of the window column kernel on the current device (0 if unknown).
+template <int EPI>
+static int box_win_slots() {
+    static std::mutex mu;
+    static int cached[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    std::lock_guard<std::mutex> lock(mu);
+    if (cached[dev] == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, box_colwin_kernel<EPI>, kWinWaves * kWave, 0) !=
+                hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return 0;
+        cached[dev] = std::max(1, per_cu * cus);
+    }
+    return cached[dev];
+}
+
 static bool g_box_window = true;
 
 int tune_box_window(int on) {
@@ -940,7 +1038,11 @@ int launch_box_col_window(const float* src, float* dst, const unsigned short* bo
     if (tiles == 0) return DTS_OK;
     if (tiles > 0x7fffffffull) return DTS_ENOTSUP;
     w.tiles = static_cast<int>(tiles);
-    const dim3 grid(static_cast<unsigned>(w.tiles));
+    // the plain pass runs persistent (as many workgroups as fit, each taking a run of tiles
+    // with the next one prefetched); the pass with the update takes one tile per workgroup
+    w.per_xcd = (w.tiles + kXcds - 1) / kXcds;
+    if (!zk) w.per_xcd = std::max(1, std::min(w.per_xcd, box_win_slots<0>() / kXcds));
+    const dim3 grid(static_cast<unsigned>(kXcds * w.per_xcd));
     const double px = static_cast<double>(batch) * H * W;
     if (zk) {
         ProfScope prof("box_col_window_update", px * (18.0 * C + 4.0 * Cc), s);
