@@ -152,25 +152,44 @@ __device__ __forceinline__ int ring_slot(int slot, int rel, int RB) {
     return v;
 }
 
-// Offsets of the box of local index li among the prefix coordinates Q[0..n): the first j
-// in [li - h, li] with Q[li] - Q[j] <= R and the last j in [li, li + h] with
-// Q[j] - Q[li] <= R.  Q is strictly increasing (every code >= 1).
-template <typename Get>
-__device__ __forceinline__ unsigned box_offsets(Get Q, int li, int first, int last, unsigned R, int h) {
-    const unsigned qi = Q(li);
-    int a = max(li - h, first), b = li;
-    while (a < b) {
-        const int m = (a + b) >> 1;
-        if (qi - Q(m) <= R) b = m; else a = m + 1;
+// Offsets of the boxes of K local indexes li among the prefix coordinates Q[0..n): the
+// first j in [li - h, li] with Q[li] - Q[j] <= R and the last j in [li, li + h] with
+// Q[j] - Q[li] <= R, packed as (li - first) | (last - li) << 8.  Q is strictly increasing
+// (every code >= 1), so both predicates are monotone.  The searches take a fixed number
+// of steps, ceil(log2(h + 1)), the same on every lane, so the 2K searches of a step issue
+// their LDS reads together instead of as K dependent chains.  A lower search keeps jl
+// below the first j that passes (every j <= jl fails), an upper one keeps jh on the last
+// j found to pass.
+template <int K, typename Get>
+__device__ __forceinline__ void box_offsets_k(Get Q, const int (&li)[K], int first, int last, unsigned R, int h,
+                                              unsigned (&out)[K]) {
+    int steps = 0;
+    while ((1 << steps) <= h) ++steps;  // 2^steps >= h + 1, the widest search range
+    unsigned qi[K];
+    int jl[K], jh[K], top[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        qi[k] = Q(li[k]);
+        jl[k] = max(li[k] - h, first) - 1;
+        jh[k] = li[k];
+        top[k] = min(li[k] + h, last);
     }
-    const int lo = a;
-    a = li;
-    b = min(li + h, last);
-    while (a < b) {
-        const int m = (a + b + 1) >> 1;
-        if (Q(m) - qi <= R) a = m; else b = m - 1;
+    for (int sb = steps - 1; sb >= 0; --sb) {
+        const int st = 1 << sb;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            // candidates clamped into the search ranges, so the reads are unconditional: a
+            // lower candidate clamped to li fails (qi - qi = 0 <= R), and an upper one
+            // clamped to top passes only if top is the answer, which later steps keep
+            const int cl = min(jl[k] + st, li[k]), ch = min(jh[k] + st, top[k]);
+            const unsigned ql = Q(cl), qh = Q(ch);
+            if (qi[k] - ql > R) jl[k] = cl;
+            if (qh - qi[k] <= R) jh[k] = ch;
+        }
     }
-    return static_cast<unsigned>(li - lo) | (static_cast<unsigned>(a - li) << 8);
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        out[k] = static_cast<unsigned>(li[k] - jl[k] - 1) | (static_cast<unsigned>(jh[k] - li[k]) << 8);
 }
 
 struct BoxBoundsArgs {
@@ -207,8 +226,8 @@ __global__ void __launch_bounds__(kBoxRowThreads) box_bounds_row_kernel(BoxBound
     }
     __syncthreads();
     auto get = [&](int m) { return Q[m]; };
-    // each thread takes consecutive pixels: a binary search places the first box, and the
-    // ends of the following boxes only move forward
+    // each thread takes consecutive pixels: a search places the first box, and the ends of
+    // the following boxes only move forward
     constexpr int kPer = kBoxSeg / kBoxRowThreads;
     int plo[kBoxMaxIters], phi[kBoxMaxIters];
 #pragma unroll
@@ -226,9 +245,11 @@ __global__ void __launch_bounds__(kBoxRowThreads) box_bounds_row_kernel(BoxBound
                     const int h = static_cast<int>(R >> 8);
                     int lo, hi;
                     if (j == 0) {
-                        const unsigned bd = box_offsets(get, li, 0, n - 1, R, h);
-                        lo = li - static_cast<int>(bd & 255u);
-                        hi = li + static_cast<int>(bd >> 8);
+                        const int l1[1] = {li};
+                        unsigned bd[1];
+                        box_offsets_k<1>(get, l1, 0, n - 1, R, h, bd);
+                        lo = li - static_cast<int>(bd[0] & 255u);
+                        hi = li + static_cast<int>(bd[0] >> 8);
                     } else {
                         const int top = min(li + h, n - 1);
                         lo = max(plo[it], li - h);
@@ -855,6 +876,81 @@ __global__ void __launch_bounds__(kWinWaves* kWave) box_colwin_kernel(BoxWinArgs
 }
 
 // ---------------------------------------------------------------------------------------
+// Column bounds for h_1 <= kWinMaxH without transposes: a workgroup owns 64 columns (one
+// per lane) and kWinRows output rows, builds the integer coordinate prefix of its window
+// (the output rows and h_1 rows on either side) in LDS from the column codes, and places
+// every box by the search of box_bounds_row_kernel along its lane's column: a binary
+// search for a wave's first output row, and for the following rows ends that only move
+// forward.  Integer sums, so the boxes are those of the transposed row kernel exactly.
+// ---------------------------------------------------------------------------------------
+constexpr int kBndRowsPerWave = kWinRows / kWinWaves;  // consecutive output rows of a wave
+
+__global__ void __launch_bounds__(kWinWaves* kWave) box_bounds_colwin_kernel(BoxBoundsArgs a, int batch,
+                                                                             int tiles_x, int tiles_y, int tiles) {
+    __shared__ unsigned P[kWinSpan * kWave];      // [row][lane]: coordinate relative to the window start
+    __shared__ unsigned btot[kWinBlocks * kWave];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int T = xcd_band_index(static_cast<int>(blockIdx.x), tiles);
+    const int ty = T % tiles_y, rest = T / tiles_y;
+    const int tx = rest % tiles_x, b = rest / tiles_x;
+    const int col = tx * kWave + lane;
+    const bool valid = col < a.W;
+    const int cx = valid ? col : 0;
+    const size_t plane = static_cast<size_t>(a.H) * a.W;
+    const int y0 = ty * kWinRows;
+    const int s0 = max(y0 - a.h1, 0);
+    const int n = min(y0 + kWinRows + a.h1, a.H) - s0;
+    const int nb = (n + 31) >> 5;
+    const int oEnd = min(y0 + kWinRows, a.H);
+    const unsigned* qc = a.q + static_cast<size_t>(b) * plane + cx;
+
+    // codes of the wave's block (the window's first row contributes none), capped at
+    // R_1 + 1 as in the row kernel, and their prefix within the block
+    unsigned loc[32];
+    const int k = wave;
+    static_assert(kWinBlocksPerWave == 1, "one block per wave");
+    if (k < nb) {
+        unsigned run = 0;
+#pragma unroll
+        for (int u = 0; u < 32; ++u) {
+            const int r = 32 * k + u;
+            const unsigned c = (valid && r > 0 && r < n) ? min(qc[static_cast<size_t>(s0 + r) * a.W], a.cap) : 0u;
+            run += c;
+            loc[u] = run;
+        }
+        btot[k * kWave + lane] = run;
+    }
+    __syncthreads();
+    if (k < nb) {
+        unsigned base = 0;
+        for (int jb = 0; jb < k; ++jb) base += btot[jb * kWave + lane];
+#pragma unroll
+        for (int u = 0; u < 32; ++u) P[(32 * k + u) * kWave + lane] = base + loc[u];
+    }
+    __syncthreads();
+
+    auto get = [&](int m) { return P[m * kWave + lane]; };
+    // the wave's output rows, kBndGroup at a time with their searches side by side
+    constexpr int kBndGroup = 8;
+    static_assert(kBndRowsPerWave % kBndGroup == 0, "whole groups");
+    for (int g0 = 0; g0 < kBndRowsPerWave; g0 += kBndGroup) {
+        const int o0 = y0 + wave * kBndRowsPerWave + g0;
+        if (o0 >= oEnd) break;
+        int li[kBndGroup];
+#pragma unroll
+        for (int j = 0; j < kBndGroup; ++j) li[j] = min(o0 + j, oEnd - 1) - s0;
+        for (int it = 0; it < a.iters; ++it) {
+            unsigned bd[kBndGroup];
+            box_offsets_k<kBndGroup>(get, li, 0, n - 1, a.R[it], static_cast<int>(a.R[it] >> 8), bd);
+            unsigned short* out = a.bounds + (static_cast<size_t>(it) * batch + b) * plane + col;
+#pragma unroll
+            for (int j = 0; j < kBndGroup; ++j)
+                if (valid && o0 + j < oEnd) out[static_cast<size_t>(o0 + j) * a.W] = static_cast<unsigned short>(bd[j]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------------------
 static int max_lds_per_block() {
@@ -926,8 +1022,9 @@ static int launch_bounds_rows(const unsigned* q, unsigned short* bounds, int bat
     return hip_fail(hipGetLastError());
 }
 
-// Row bounds from qx; column bounds as the row bounds of the transposed qy (written over
-// qx, no longer needed), transposed back through `bt` (iters planes of the batch).
+// Row bounds from qx.  Column bounds straight from qy when h_1 fits the window kernel,
+// else as the row bounds of the transposed qy (written over qx, no longer needed),
+// transposed back through `bt` (iters planes of the batch).
 int launch_box_bounds(unsigned* qx, const unsigned* qy, unsigned short* bx, unsigned short* by, unsigned short* bt,
                       int batch, int H, int W, const unsigned* R, int iters, hipStream_t s) {
     BoxBoundsArgs a{};
@@ -938,6 +1035,20 @@ int launch_box_bounds(unsigned* qx, const unsigned* qy, unsigned short* bx, unsi
     if (int rc = box_check_radius(a.h1)) return rc;
     int rc = launch_bounds_rows(qx, bx, batch, H, W, a, "box_bounds_row", s);
     if (rc) return rc;
+    if (box_window_fits(a.h1)) {
+        BoxBoundsArgs c = a;
+        c.q = qy;
+        c.bounds = by;
+        c.H = H;
+        c.W = W;
+        const int tiles_x = (W + kWave - 1) / kWave, tiles_y = (H + kWinRows - 1) / kWinRows;
+        const long long tiles = static_cast<long long>(tiles_x) * tiles_y * batch;
+        if (tiles > 0x7fffffffLL) return DTS_ENOTSUP;
+        ProfScope prof("box_bounds_col_window", static_cast<double>(batch) * H * W * (4.0 + 2.0 * iters), s);
+        hipLaunchKernelGGL(box_bounds_colwin_kernel, dim3(static_cast<unsigned>(tiles)), dim3(kWinWaves * kWave), 0,
+                           s, c, batch, tiles_x, tiles_y, static_cast<int>(tiles));
+        return hip_fail(hipGetLastError());
+    }
     if ((rc = launch_transpose<unsigned>(qy, qx, batch, H, W, "box_transpose_codes", s))) return rc;
     if ((rc = launch_bounds_rows(qx, bt, batch, W, H, a, "box_bounds_col", s))) return rc;
     return launch_transpose<unsigned short>(bt, by, iters * batch, W, H, "box_transpose_bounds", s);
