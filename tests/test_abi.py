@@ -216,6 +216,12 @@ def test_support_rejects_bad_arguments_without_launching(lib):
     assert lib.dts_support(fake, 3, 1, 0, 8, 8.0, 0.2, 3, fake, None, 0, None, fake, ok, None) == dts.DTS_EINVAL
 
 
+def test_box_window_switch(lib):
+    # process-wide launch choice, no device work: on, off, and back to the default
+    assert lib.dts_tune_box_window(0) == 0
+    assert lib.dts_tune_box_window(1) == 0
+
+
 def test_box_rejects_bad_arguments_without_launching(lib):
     ok = lib.dts_box_workspace_bytes(1, 8, 8, 1, 3)
     assert ok > 0

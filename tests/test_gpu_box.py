@@ -130,6 +130,23 @@ def test_solve_box_column_kernels_match_oracle(window):
     assert np.abs(got - ref).max() <= SOLVE_TOL, float(np.abs(got - ref).max())
 
 
+# More window tiles than resident workgroups (800 and 720 against 512 on an MI355X): the
+# plain column pass's workgroups then take several tiles each, the next one's window
+# loaded while the current one is summed.
+PERSISTENT_CASES = [(2560, 2560, 8.0, 3), (2304, 2560, 37.0, 1)]
+
+
+@pytest.mark.parametrize("case", PERSISTENT_CASES, ids=["2560x2560_N3", "2304x2560_h64"])
+def test_filter_box_several_tiles_per_workgroup_matches_oracle(case):
+    H, W, ss, N = case
+    print("CASE box persistent", case, flush=True)
+    c = dts_inputs.random_case(11 + H, H, W, 3, 1, sigma_s=ss, sigma_r=0.2, T=1)
+    got = dts.filter_box(dev(c["guide"][None]), dev(c["target"][None]), ss, 0.2, N).cpu().numpy()[0]
+    qx, qy = oracle.box_codes(c["guide"], ss, 0.2)
+    ref = oracle.box_filter(c["target"], qx, qy, ss, N)
+    assert np.abs(got - ref).max() <= FILTER_TOL, (case, float(np.abs(got - ref).max()))
+
+
 SOLVE_CASES = [
     # H, W, Cg, Ct, Cc, N, T, batch, sigma_s, sigma_r
     (1, 1, 1, 1, 1, 3, 3, 1, 8.0, 0.2),
