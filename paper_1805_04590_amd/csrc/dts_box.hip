@@ -226,43 +226,21 @@ __global__ void __launch_bounds__(kBoxRowThreads) box_bounds_row_kernel(BoxBound
     }
     __syncthreads();
     auto get = [&](int m) { return Q[m]; };
-    // each thread takes consecutive pixels: a search places the first box, and the ends of
-    // the following boxes only move forward
+    // thread t takes pixels x0 + t + 256 j, so that neighbouring lanes search neighbouring
+    // LDS words (four consecutive pixels per thread put lanes four words apart: an 8-way
+    // bank conflict on every read), and its kPer searches run side by side
     constexpr int kPer = kBoxSeg / kBoxRowThreads;
-    int plo[kBoxMaxIters], phi[kBoxMaxIters];
+    int li[kPer];
 #pragma unroll
-    for (int it = 0; it < kBoxMaxIters; ++it) plo[it] = phi[it] = 0;
+    for (int j = 0; j < kPer; ++j) li[j] = min(x0 + static_cast<int>(threadIdx.x) + kBoxRowThreads * j, a.W - 1) - s0;
+    for (int it = 0; it < a.iters; ++it) {
+        unsigned bd[kPer];
+        box_offsets_k<kPer>(get, li, 0, n - 1, a.R[it], static_cast<int>(a.R[it] >> 8), bd);
+        unsigned short* out = a.bounds + (static_cast<size_t>(it) * gridDim.z + b) * plane + static_cast<size_t>(y) * a.W;
 #pragma unroll
-    for (int j = 0; j < kPer; ++j) {
-        const int x = x0 + threadIdx.x * kPer + j;
-        if (x < a.W) {
-            const int li = x - s0;
-            const unsigned qi = Q[li];
-#pragma unroll
-            for (int it = 0; it < kBoxMaxIters; ++it) {
-                if (it < a.iters) {
-                    const unsigned R = a.R[it];
-                    const int h = static_cast<int>(R >> 8);
-                    int lo, hi;
-                    if (j == 0) {
-                        const int l1[1] = {li};
-                        unsigned bd[1];
-                        box_offsets_k<1>(get, l1, 0, n - 1, R, h, bd);
-                        lo = li - static_cast<int>(bd[0] & 255u);
-                        hi = li + static_cast<int>(bd[0] >> 8);
-                    } else {
-                        const int top = min(li + h, n - 1);
-                        lo = max(plo[it], li - h);
-                        hi = max(phi[it], li);
-                        while (qi - Q[lo] > R) ++lo;
-                        while (hi < top && Q[hi + 1] - qi <= R) ++hi;
-                    }
-                    plo[it] = lo;
-                    phi[it] = hi;
-                    a.bounds[(static_cast<size_t>(it) * gridDim.z + b) * plane + static_cast<size_t>(y) * a.W + x] =
-                        static_cast<unsigned short>(static_cast<unsigned>(li - lo) | (static_cast<unsigned>(hi - li) << 8));
-                }
-            }
+        for (int j = 0; j < kPer; ++j) {
+            const int x = x0 + static_cast<int>(threadIdx.x) + kBoxRowThreads * j;
+            if (x < a.W) out[x] = static_cast<unsigned short>(bd[j]);
         }
     }
 }
