@@ -415,9 +415,9 @@ def solve_leg(args, dev):
 
     ms_v = timed(vstep, args.steps, args.warmup)
     dts.workspace_status(wsv)
-    # first row pass: z in, (z, z^2) out, guide in, dx and dy out; 2N - 1 further passes over
-    # the pairs; the confidence kernel reads the pairs and writes the confidences
-    v_bytes = px * (4 * (3 * Ct + Cg + 2) + (2 * N - 1) * 4 * (4 * Ct + 1) + 12 * Ct)
+    # first row pass: z in, (z, z^2) out, guide in, dx and dy out; 2N - 2 further passes over
+    # the pairs; the last column pass reads the pairs and writes the confidences
+    v_bytes = px * (4 * (3 * Ct + Cg + 2) + (2 * N - 2) * 4 * (4 * Ct + 1) + 4 * (3 * Ct + 1))
     variance = dict(workload=f"variance confidence (Eq. 7) of the {W}x{H} target, {Cg}-band guide, "
                              f"sigma_c={sc}, N={N}",
                     ms=round(ms_v, 3), mpix_s=round(px / ms_v / 1e3, 1),

@@ -789,9 +789,15 @@ int dts_variance_confidence(const float* guide, int Cg, const float* z, float* c
         cp.batch = batch;
         cp.log2a = l2a;
         cp.epilogue = false;
+        if (i == filter_iters) {
+            // the last column pass writes the confidences from the filtered pairs
+            cp.dst = conf;
+            cp.variance = true;
+            cp.var_k = variance_k(sigma_c);
+        }
         if ((rc = launch_col_pass(cp, S.ctx))) return rc;
     }
-    return launch_variance_confidence(m, conf, C, batch, static_cast<size_t>(H) * W, sigma_c, S.ctx.stream);
+    return DTS_OK;
 }
 
 size_t dts_box_workspace_bytes(int batch, int H, int W, int C, int filter_iters) {

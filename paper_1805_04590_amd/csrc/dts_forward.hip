@@ -285,13 +285,22 @@ static int col_capacity_t() {
 
 template <int CT, int R, int NWV>
 static int col_capacity_v(int mode) {
+    if (mode == 3) {
+        if constexpr (CT % 2 == 0) return col_capacity_t<CT, R, NWV, 3>();
+        else return 0;
+    }
     return mode == 2 ? col_capacity_t<CT, R, NWV, 2>()
                      : mode == 1 ? col_capacity_t<CT, R, NWV, 1>() : col_capacity_t<CT, R, NWV, 0>();
 }
 
 template <int CT, int R, int NWV>
 static int col_launch_v(const ColArgs& a, unsigned n, hipStream_t s, int mode) {
-    if (mode == 2) {
+    if (mode == 3) {
+        if constexpr (CT % 2 == 0)  // the variance epilogue takes channel pairs
+            hipLaunchKernelGGL((col_pass_kernel<CT, R, NWV, 3>), dim3(n), dim3(kWave * NWV), 0, s, a);
+        else
+            return DTS_ENOTSUP;
+    } else if (mode == 2) {
         if constexpr (CT == 1)  // the data-gradient update serves single-channel solves
             hipLaunchKernelGGL((col_pass_kernel<CT, R, NWV, 2>), dim3(n), dim3(kWave * NWV), 0, s, a);
         else
@@ -458,10 +467,12 @@ int launch_col_pass(const ColPass& p, Ctx& ctx) {
     a.dst2 = p.dst2;
     a.lambda = p.lambda;
     a.step = p.step;
+    a.var_k = p.var_k;
     // every workgroup of the grid must be resident at once: size the grid to the
     // device's capacity for this kernel, in whole strips of G chunks
-    const int mode = !p.epilogue ? 0 : p.data_grad ? 2 : 1;
+    const int mode = p.variance ? 3 : !p.epilogue ? 0 : p.data_grad ? 2 : 1;
     if (mode == 2 && v.ct != 1) return DTS_ENOTSUP;
+    if (mode == 3 && ((p.C & 1) || (v.ct & 1))) return DTS_EINVAL;
     const int cap = v.capacity(mode);
     if (cap <= 0) return hip_fail(hipErrorNoDevice);
     if (a.G > cap) return DTS_ENOTSUP;
@@ -474,9 +485,13 @@ int launch_col_pass(const ColPass& p, Ctx& ctx) {
     const double px = static_cast<double>(p.batch) * a.H * a.W;
     const double bytes = mode == 1   ? px * 4.0 * (4.0 * a.C + 1.0 + (a.Cc == 1 ? 1.0 : a.C))
                          : mode == 2 ? px * 4.0 * (4.0 * a.C + 1.0)
+                         : mode == 3 ? px * 4.0 * (1.5 * a.C + 1.0)  // pairs and distances in, C / 2 out
                                      : px * 4.0 * (2.0 * a.C + 1.0);
-    ProfScope prof(mode == 1 ? "col_pass_update" : mode == 2 ? "col_pass_update_grad" : "col_pass", bytes,
-                   ctx.stream);
+    ProfScope prof(mode == 1   ? "col_pass_update"
+                   : mode == 2 ? "col_pass_update_grad"
+                   : mode == 3 ? "col_pass_variance_conf"
+                               : "col_pass",
+                   bytes, ctx.stream);
     return v.launch(a, n, ctx.stream, mode);
 }
 
@@ -501,32 +516,11 @@ __global__ void copy_kernel(float* __restrict__ dst, const float* __restrict__ s
         dst[i] = src[i];
 }
 
-// Eq. (7): c = exp(-V / (2 sigma_c^2)) with V = DT(z^2) - DT(z)^2, from the filtered
-// pairs: plane 2c of `m` holds DT(z_c), plane 2c + 1 holds DT(z_c^2).  k = -log2(e) /
-// (2 sigma_c^2).  V is used as computed (not clipped at zero).
-__global__ void __launch_bounds__(256) variance_confidence_kernel(const float* __restrict__ m,
-                                                                   float* __restrict__ conf, size_t plane,
-                                                                   size_t total, float k) {
-    const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
-    for (size_t e = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += stride) {
-        const size_t pc = e / plane;  // b * C + c
-        const size_t i = e - pc * plane;
-        const float* p = m + 2 * pc * plane + i;
-        const float m1 = p[0];
-        const float m2 = p[plane];
-        conf[e] = exp2_fast(fmaf(-m1, m1, m2) * k);
-    }
-}
-
-int launch_variance_confidence(const float* moments, float* conf, int C, int batch, size_t plane,
-                               float sigma_c, hipStream_t s) {
-    const size_t total = static_cast<size_t>(batch) * C * plane;
-    const double k = -1.0 / (2.0 * static_cast<double>(sigma_c) * sigma_c * std::log(2.0));
-    const size_t blocks = std::min<size_t>((total + 255) / 256, 65536);
-    ProfScope prof("variance_confidence", static_cast<double>(total) * 12.0, s);
-    hipLaunchKernelGGL(variance_confidence_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
-                       moments, conf, plane, total, static_cast<float>(k));
-    return hip_fail(hipGetLastError());
+// Eq. (7): c = exp(-V / (2 sigma_c^2)) with V = DT(z^2) - DT(z)^2, taken in the last
+// column pass of the variance filter (col_tile's EPI 3) as exp2(k V) with
+// k = -log2(e) / (2 sigma_c^2), rounded once from double.
+float variance_k(float sigma_c) {
+    return static_cast<float>(-1.0 / (2.0 * static_cast<double>(sigma_c) * sigma_c * std::log(2.0)));
 }
 
 // Data-term gradient of the stereo objective (Eq. (11)) at the disparity z, one pixel per

@@ -51,6 +51,10 @@ struct ColPass {
     int Cc;
     float* dst2;
     float lambda, step;
+    // variance (C even, in place of the epilogue): dst = exp2(var_k (K_{2c+1} - K_{2c}^2)),
+    // the confidence of Eq. (7) from the filtered pairs (DT(z), DT(z^2)), C / 2 planes
+    bool variance;
+    float var_k;
 };
 
 // Adjoint of one row pass (update-adjoint epilogue when gz is set).
@@ -116,8 +120,7 @@ int tune_row_segment(int S);
 int launch_zero(void* ptr, size_t bytes, hipStream_t s);
 int launch_stereo_data_grad(const float* z, const float* t, const float* c, const float* left, const float* right,
                             float* D, int Cg, int batch, int H, int W, float gamma, float eps, hipStream_t s);
-int launch_variance_confidence(const float* moments, float* conf, int C, int batch, size_t plane,
-                               float sigma_c, hipStream_t s);
+float variance_k(float sigma_c);
 int launch_copy(float* dst, const float* src, size_t n, hipStream_t s);
 constexpr int kBoxMaxIters = 8;
 int box_check_radius(int h1);

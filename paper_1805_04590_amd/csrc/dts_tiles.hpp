@@ -283,6 +283,7 @@ struct ColArgs {
     int Cc;
     float* dst2;
     float lambda, step;
+    float var_k;  // EPI 3: -log2(e) / (2 sigma_c^2)
 };
 
 struct NoHook {
@@ -294,7 +295,10 @@ struct NoHook {
 // runs on every thread once the chunk's carries are known, i.e. once the tile no longer
 // waits on any other tile.
 // EPI: 0 plain pass; 1 the solver update of Eq. (3) (reads z^k, t, c); 2 the update with
-// a precomputed data-term gradient D in place of c (z - t) (reads z^k and D from `tgt`).
+// a precomputed data-term gradient D in place of c (z - t) (reads z^k and D from `tgt`);
+// 3 the confidence of Eq. (7) from channel pairs (DT(z), DT(z^2)) of an even group size:
+// writes exp(-(DT(z^2) - DT(z)^2) / (2 sigma_c^2)) to channel c / 2 of `dst` (C / 2
+// planes) instead of the pair.
 template <int CT, int R, int NWV, int EPI, typename Hook = NoHook>
 __device__ __forceinline__ void col_tile(const ColArgs& a, const CarryCtx& cctx, ChunkLds<CT, NWV>& L,
                                          int chunk, int strip, int grp, int b, Hook hook = Hook{}) {
@@ -404,6 +408,27 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, const CarryCtx& cctx,
 #pragma unroll
             for (int c = 0; c < CT; ++c) f[c][r] = fmaf(q, Jin[c], f[c][r]);
         }
+    }
+    if constexpr (EPI == 3) {
+        static_assert(CT % 2 == 0, "the variance epilogue takes channel pairs");
+#pragma unroll
+        for (int c = 0; c < CT; c += 2) {
+            if (c < ncv) {  // ncv is even: C and the group's first channel are
+                float K0 = Kin[c], K1 = Kin[c + 1];
+                const size_t pidx = (static_cast<size_t>(b) * a.C + c0 + c) >> 1;
+                const auto ors = plane_rsrc(a.dst + pidx * plane, pbytes);
+                unsigned vo = voff + static_cast<unsigned>(R - 1) * rowb;
+#pragma unroll
+                for (int r = R - 1; r >= 0; --r) {
+                    const float wn = (r + 1 < R) ? w[(r + 1 < R) ? r + 1 : r] : wnext;
+                    K0 = fmaf(wn, K0 - f[c][r], f[c][r]);
+                    K1 = fmaf(wn, K1 - f[c + 1][r], f[c + 1][r]);
+                    bstore(ors, vo, 0, exp2_fast(fmaf(-K0, K0, K1) * a.var_k));
+                    vo = opaque_vadd(vo, 0u - rowb);
+                }
+            }
+        }
+        return;
     }
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
