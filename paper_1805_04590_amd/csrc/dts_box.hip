@@ -13,11 +13,13 @@
 // Since d >= 1, a box never reaches more than h_i = R_i / 256 pixels from its centre.
 //
 // Kernels:
-//   box_codes_kernel        guide -> qx, qy (one pixel per thread)
+//   box_codes_kernel        guide -> qx, qy (four consecutive pixels per thread)
 //   box_bounds_row_kernel   qx -> per pixel and iteration, the box as two u8 offsets
-//                           (a row segment's prefix of codes in LDS, binary searches)
-//   box_transpose_kernel    the column bounds are the row bounds of the transposed
-//                           codes, transposed back (64 x 64 LDS tiles)
+//                           (a row segment's prefix of codes in LDS, searches)
+//   box_bounds_colwin_kernel  qy -> the column boxes for h_1 <= kWinMaxH (a window's
+//                           prefix of codes down 64 columns in LDS, searches)
+//   box_transpose_kernel    for wider boxes the column bounds are the row bounds of the
+//                           transposed codes, transposed back (64 x 64 LDS tiles)
 //   box_rowwin_kernel       one row pass for h <= kWinMaxH: a wave per 512 outputs, the
 //                           FP64 prefix S of the segment and its halo in LDS,
 //                           mean = (S[hi + 1] - S[lo]) / (hi - lo + 1)
