@@ -808,12 +808,14 @@ __global__ void __launch_bounds__(kWinWaves* kWave) box_colwin_kernel(BoxWinArgs
         const bool more = !EPI && Tn < t_end;
         WinTile tn = t;
         WinRes rn = rs;
-        unsigned bdn[kWinOutPerWave];
-        if (more) {
-            tn = win_tile(w, Tn, lane);
-            rn = win_res(a, tn);
-            win_load_signal(a, tn, rn, wave, v);
-            win_load_bounds(a, tn, rn, wave, bdn);
+        [[maybe_unused]] unsigned bdn[kWinOutPerWave];
+        if constexpr (EPI == 0) {
+            if (more) {
+                tn = win_tile(w, Tn, lane);
+                rn = win_res(a, tn);
+                win_load_signal(a, tn, rn, wave, v);
+                win_load_bounds(a, tn, rn, wave, bdn);
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -850,8 +852,9 @@ __global__ void __launch_bounds__(kWinWaves* kWave) box_colwin_kernel(BoxWinArgs
         T = Tn;
         t = tn;
         rs = rn;
-#pragma unroll
-        for (int q = 0; q < kWinOutPerWave; ++q) bd[q] = bdn[q];
+        if constexpr (EPI == 0) {
+            for (int q = 0; q < kWinOutPerWave; ++q) bd[q] = bdn[q];  // a register rename
+        }
     }
 }
 
