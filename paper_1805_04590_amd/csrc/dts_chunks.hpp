@@ -168,8 +168,7 @@ __device__ void chunk_carries(const CarryCtx& a, ChunkLds<NCH, NWV>& L, int b, i
     }
     __syncthreads();
     if (valid) {
-#pragma unroll
-        for (int k = wave; k < CW::kWords; k += NWV) {
+        for (int k = wave; k < CW::kWords; k += NWV) {  // a trip count set by the wave
             float v;
             bool live = true;
             if (k == CW::kA) {
